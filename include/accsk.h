@@ -1,0 +1,137 @@
+/*
+ * accsk.h -- C ABI of the MI355X (gfx950) Acc-Sinkhorn library.
+ *
+ * Entropy-regularized optimal transport (paper Sec. 1, eq:EOT):
+ *     min_{P in Pi(a,b)}  <C,P> + eps * sum_ij P_ij (log P_ij - 1)
+ * solved in the dual (Sec. 2, eq:dual-obj / eq:dual-min) by log-domain
+ * Sinkhorn (eq:u-update, eq:v-update, normalized as eq:normalized-sinkhorn) or
+ * by Acc-Sinkhorn (Algorithm A2MD inside the homotopy of Algorithm
+ * A2MD-homotopy, Sec. 4), stopped by the L1 marginal rule eq:l1tol.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named as device pointers must point to device memory of the
+ *   current HIP device; all work is enqueued on `stream` (a hipStream_t passed
+ *   as void*, NULL = the legacy default stream).  The caller owns every input
+ *   and output buffer.  The library owns only scratch memory it allocates
+ *   stream-ordered inside the call and frees before returning.
+ * - Matrices are row-major with a leading dimension (in elements) >= the row
+ *   length.  Potentials are FP64.
+ * - Marginals a (length n) and b (length m) must be finite and > 0; they are
+ *   rescaled to unit mass inside the call (eq:Fc needs 1'a = 1'b = 1).
+ * - Potentials returned are f = eps*u and g = eps*v in cost units, so that
+ *   P_ij = exp((f_i + g_j - C_ij)/eps) (eq:P-from-dual); g is centred
+ *   (sum_j g_j = 0, the gauge of eq:Fc).
+ * - Calls that fill an accsk_result (host pointer) block until their work on
+ *   `stream` has finished.  Other calls only enqueue work.
+ * - Errors are reported by the return value; no exception crosses the ABI.
+ *   On any status other than ACCSK_OK / ACCSK_NOT_CONVERGED the output
+ *   buffers are unspecified.
+ */
+#ifndef ACCSK_H
+#define ACCSK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ACCSK_OK = 0,
+    ACCSK_INVALID_ARG = 1,   /* bad scalar argument or non-positive marginal entry */
+    ACCSK_SHAPE = 2,         /* sizes / leading dimensions / alignment not supported */
+    ACCSK_NONFINITE = 3,     /* NaN or Inf met in the cost or the marginals */
+    ACCSK_NOT_CONVERGED = 4, /* max_iter reached; outputs hold the last iterate */
+    ACCSK_DIVERGED = 5,      /* the marginal error became non-finite during the solve */
+    ACCSK_OOM = 6,           /* device allocation failed or HBM budget exceeded */
+    ACCSK_HIP_ERROR = 7,     /* a HIP runtime call failed */
+    ACCSK_BUSY = 8           /* serving queue full; retry later */
+} accsk_status;
+
+typedef enum { ACCSK_SINKHORN = 0, ACCSK_ACC = 1 } accsk_method;
+
+/* Hand-off of w = alpha*y between homotopy stages (alpha changes with mu):
+ * Y_CONTINUOUS keeps y (w scaled by alpha_new/alpha_old, the state the
+ * homotopy analysis of Theorem thm:homotopy carries); LITERAL passes w
+ * unchanged as Algorithm A2MD-homotopy prints it. */
+typedef enum { ACCSK_W_LITERAL = 0, ACCSK_W_Y_CONTINUOUS = 1 } accsk_w_rule;
+
+/* On-the-fly costs from point clouds X (n x d) and Y (m x d):
+ * SQEUCLID: C_ij = ||x_i - y_j||^2 / scale   (Sec. 5, colour transfer)
+ * COSINE:   C_ij = (1 - <x_i, y_j>) / scale  (Sec. 5, word alignment; unit rows) */
+typedef enum { ACCSK_SQEUCLID = 0, ACCSK_COSINE = 1 } accsk_cost;
+
+typedef struct {
+    int32_t method;     /* accsk_method */
+    int32_t w_rule;     /* accsk_w_rule */
+    double eps;         /* regularization, > 0 */
+    double tol;         /* stop when ||P1-a||_1 + ||P'1-b||_1 < tol (eq:l1tol), > 0 */
+    int64_t max_iter;   /* cap on iterations (It), >= 0 */
+    double mu0;         /* homotopy start, 0 < mu0 < 1 (Algorithm A2MD-homotopy) */
+    int64_t m0;         /* inner iterations of the first stage, >= 1 */
+    int32_t split;      /* BF16 split depth of on-the-fly cost products: 2 or 3 */
+    int32_t flags;      /* ACCSK_FLAG_* bits */
+} accsk_params;
+
+#define ACCSK_FLAG_NO_COST 1       /* skip the final <C,P> pass */
+#define ACCSK_FLAG_NO_SERPENTINE 2 /* traverse C in the same row order every step */
+
+typedef struct {
+    int64_t iters;          /* It: accepted iterates after x_0 (Sinkhorn: v-updates) */
+    int64_t sinkhorn_steps; /* Sinkhorn steps evaluated (= iters + 1) */
+    int64_t fallback_steps; /* steps that needed the exact column-max pass */
+    double marginal_err;    /* eq:l1tol at the returned iterate, column part (row part is 0 by the exact row solve) */
+    double eot_value;       /* dual value <f,a> + <g,b> - eps*sum P (equals the EOT optimum at convergence) */
+    double transport_cost;  /* <C,P> at the returned potentials (NaN if skipped) */
+    double dual_fval;       /* reduced dual objective f(x) = 1 - <u,a> - <x,b> at eps = 1 (Lemma coercivity) */
+    int32_t converged;      /* 1 if marginal_err < tol */
+    int32_t status;         /* accsk_status of the call */
+} accsk_result;
+
+/* Fills the defaults: ACC, Y_CONTINUOUS, eps 1e-2, tol 1e-6, max_iter 100000,
+ * mu0 and m0 as calibrated on the FP64 oracle, split 3, flags 0. */
+void accsk_default_params(accsk_params *p);
+
+/* Human-readable name of a status code (static storage). */
+const char *accsk_status_string(int status);
+
+/* Library version string (static storage). */
+const char *accsk_version(void);
+
+/*
+ * Dense solve on an explicit FP32 cost (Sec. 2 dual, Sec. 4 algorithms).
+ * C: device, n x m row-major, leading dimension ldc >= m.  a: device FP64[n],
+ * b: device FP64[m].  f_out: device FP64[n], g_out: device FP64[m].
+ * res: host.  Supported sizes: 1 <= n, 1 <= m <= 8192.
+ * Returns ACCSK_OK, ACCSK_NOT_CONVERGED (outputs valid), or an error.
+ */
+accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc,
+                               const double *a, const double *b, const accsk_params *p,
+                               double *f_out, double *g_out, accsk_result *res, void *stream);
+
+/*
+ * Transport plan rows [row0, row0+rows) from potentials (eq:P-from-dual):
+ * P_ij = exp((f_i + g_j - C_ij)/eps), written as FP32 to P (device,
+ * rows x m, leading dimension ldp >= m).  f, g: device FP64 (full length).
+ */
+accsk_status accsk_plan_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,
+                              const double *f, const double *g, int64_t row0, int64_t rows,
+                              float *P, int64_t ldp, void *stream);
+
+/*
+ * FP64-accumulated evaluation of potentials (f, g) on an explicit cost
+ * (eq:P-from-dual, eq:l1tol, eq:dual-obj): out (host FP64[5]) receives
+ * ||P1 - a||_1, ||P'1 - b||_1, <f,a> + <g,b> - eps*sum P, <C,P>, sum P,
+ * with a, b used as given (the caller normalizes).
+ */
+accsk_status accsk_eval_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,
+                              const double *a, const double *b, const double *f, const double *g,
+                              double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACCSK_H */

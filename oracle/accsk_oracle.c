@@ -1,0 +1,351 @@
+/*
+ * FP64 CPU oracle for entropy-regularized optimal transport (EOT) solved by
+ * log-domain Sinkhorn and by Acc-Sinkhorn with homotopy.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plainly written reference
+ * that the GPU library is checked against.  It shares no code, header, table
+ * or helper with the HIP library; the library never calls it.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark load it.
+ *
+ * Everything is double precision.  Loops are written in the order of the
+ * paper's definitions; OpenMP only splits independent rows (or independent
+ * columns) between threads, never a single sum.
+ *
+ * Notation (paper, Sec. 2 "Dual Formulation"): the cost is divided by eps
+ * (Ct = C/eps), so the problem is solved at eps = 1;
+ *   P_ij(u,v) = exp(u_i + v_j - Ct_ij)                       eq:P-from-dual
+ *   F(u,v)    = sum_ij P_ij - <u,a> - <v,b>                  eq:dual-obj
+ *   u(v)_i    = log a_i - LSE_j(v_j - Ct_ij)                 eq:u-update (exact row solve)
+ *   f(v)      = F(u(v),v) = 1 - <u(v),a> - <v,b>            Lemma coercivity (App. A)
+ *   grad f(v) = c_P(u(v),v) - b                              eq:grad-f
+ *   Sinkhorn(v) = v - P_Nperp grad phi*(P_Nperp grad f(v))   eq:normalized-sinkhorn
+ * with grad phi*(xi) = log(1 + xi./b) (Sec. 3).  For v with sum(v) = 0 and
+ * sum_j c_P,j = 1 this equals center(log b - ell), ell_j = LSE_i(u_i - Ct_ij),
+ * which is the form used here (log domain, Sec. 5 "Color Transfer").
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* log(sum_k exp(z_k)) with the max shift of the log-domain method. */
+static double lse_strided(const double *z, int64_t count, int64_t stride)
+{
+    double mx = -INFINITY;
+    for (int64_t k = 0; k < count; k++) {
+        double t = z[k * stride];
+        if (t > mx) mx = t;
+    }
+    if (mx == -INFINITY) return -INFINITY;
+    double s = 0.0;
+    for (int64_t k = 0; k < count; k++) s += exp(z[k * stride] - mx);
+    return mx + log(s);
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/*
+ * Exact row solve, eq:u-update: u_i = log a_i - LSE_j(x_j - C_ij/eps).
+ * Returns <u,a>.
+ */
+static double row_solve(const double *C, int64_t n, int64_t m, double eps,
+                        const double *a, const double *x, double *u)
+{
+    double ua = 0.0;
+#pragma omp parallel
+    {
+        double *z = (double *)malloc(sizeof(double) * (size_t)m);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; i++) {
+            for (int64_t j = 0; j < m; j++) z[j] = x[j] - C[i * m + j] / eps;
+            u[i] = log(a[i]) - lse_strided(z, m, 1);
+        }
+        free(z);
+    }
+    for (int64_t i = 0; i < n; i++) ua += u[i] * a[i];
+    return ua;
+}
+
+/* ell_j = LSE_i(u_i - C_ij/eps): log of the column sums of P without exp(x_j). */
+static void col_lse(const double *C, int64_t n, int64_t m, double eps,
+                    const double *u, double *ell)
+{
+#pragma omp parallel
+    {
+        double *z = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < m; j++) {
+            for (int64_t i = 0; i < n; i++) z[i] = u[i] - C[i * m + j] / eps;
+            ell[j] = lse_strided(z, n, 1);
+        }
+        free(z);
+    }
+}
+
+/*
+ * One normalized Sinkhorn step at x (eq:normalized-sinkhorn, log-domain form).
+ * Outputs: u = u(x); ell; S = Sinkhorn(x) = center(log b - ell);
+ * err = sum_j |c_j - b_j| with c_j = exp(x_j + ell_j) (the column part of the
+ * stopping rule eq:l1tol; the row part is zero by construction of u(x));
+ * fval = f(x) = 1 - <u,a> - <x,b>.
+ */
+void oracle_sstep(const double *C, int64_t n, int64_t m, double eps,
+                  const double *a, const double *b, const double *x,
+                  double *u, double *ell, double *S, double *err, double *fval)
+{
+    double ua = row_solve(C, n, m, eps, a, x, u);
+    col_lse(C, n, m, eps, u, ell);
+    double xb = 0.0, e = 0.0, mean = 0.0;
+    for (int64_t j = 0; j < m; j++) {
+        xb += x[j] * b[j];
+        e += fabs(exp(x[j] + ell[j]) - b[j]);
+        S[j] = log(b[j]) - ell[j];
+        mean += S[j];
+    }
+    mean /= (double)m;
+    for (int64_t j = 0; j < m; j++) S[j] -= mean;
+    *err = e;
+    *fval = 1.0 - ua - xb;
+}
+
+enum { ORACLE_SINKHORN = 0, ORACLE_ACC = 1 };
+enum { ORACLE_W_LITERAL = 0, ORACLE_W_Y_CONTINUOUS = 1 };
+
+/*
+ * Full solve.  a, b must already sum to one (eq:Fc requires 1'a = 1'b = 1).
+ *
+ * method ORACLE_SINKHORN: v_0 = 0, v_{k+1} = Sinkhorn(v_k) (eq:normalized-sinkhorn),
+ *   stop as soon as err(v_k) < tol or k = max_iter.
+ * method ORACLE_ACC: Algorithm A2MD inside the homotopy of Algorithm
+ *   A2MD-homotopy.  x_0 = w_0 = 0; per stage alpha = sqrt(2 mu);
+ *     x_{k+1} = (w_k + Sinkhorn(x_k)) / (1 + alpha)
+ *     w_{k+1} = (w_k + (alpha^2 - 2) x_{k+1} + 2 Sinkhorn(x_{k+1})) / (1 + alpha)
+ *   Sinkhorn(x_{k+1}) is kept for the next x-update (one step per iteration).
+ *   After m_stage inner iterations: mu <- mu/2, m_stage <- floor(sqrt(2) m_stage) + 1.
+ *   The stopping rule is tested at every new x (inner iteration).
+ *   w_rule ORACLE_W_Y_CONTINUOUS rescales w by alpha_new/alpha_old at a stage
+ *   change so that y = w/alpha is carried over; ORACLE_W_LITERAL passes w as printed.
+ *
+ * Outputs: f = eps*u(x), g = eps*x at the returned iterate; iters = It;
+ * steps = number of Sinkhorn steps evaluated; err at the returned iterate.
+ * Optional traces (length max_iter+1, may be NULL): err and f(x) per It;
+ * trace_x (length (max_iter+1)*m, may be NULL): the iterate x per It.
+ * Returns 1 if converged (err < tol), 0 otherwise.
+ */
+int oracle_solve(int method, const double *C, int64_t n, int64_t m, double eps,
+                 const double *a, const double *b, double tol, int64_t max_iter,
+                 double mu0, int64_t m0, int w_rule,
+                 double *f, double *g, int64_t *iters, int64_t *steps, double *err_out,
+                 double *trace_err, double *trace_fval, double *trace_x)
+{
+    double *x = (double *)calloc((size_t)m, sizeof(double));
+    double *w = (double *)calloc((size_t)m, sizeof(double));
+    double *S = (double *)malloc(sizeof(double) * (size_t)m);
+    double *ell = (double *)malloc(sizeof(double) * (size_t)m);
+    double *u = (double *)malloc(sizeof(double) * (size_t)n);
+    double err = 0.0, fval = 0.0;
+    int64_t it = 0, nsteps = 0;
+    int converged = 0;
+
+    oracle_sstep(C, n, m, eps, a, b, x, u, ell, S, &err, &fval);
+    nsteps = 1;
+    if (trace_err) trace_err[0] = err;
+    if (trace_fval) trace_fval[0] = fval;
+    if (trace_x) memcpy(trace_x, x, sizeof(double) * (size_t)m);
+
+    if (method == ORACLE_SINKHORN) {
+        while (!(err < tol) && it < max_iter) {
+            memcpy(x, S, sizeof(double) * (size_t)m);
+            it++;
+            oracle_sstep(C, n, m, eps, a, b, x, u, ell, S, &err, &fval);
+            nsteps++;
+            if (trace_err) trace_err[it] = err;
+            if (trace_fval) trace_fval[it] = fval;
+            if (trace_x) memcpy(trace_x + it * m, x, sizeof(double) * (size_t)m);
+        }
+    } else {
+        double mu = mu0;
+        int64_t mstage = m0;
+        int done = (err < tol) || (it >= max_iter);
+        while (!done) {
+            double alpha = sqrt(2.0 * mu);
+            for (int64_t k = 0; k < mstage && !done; k++) {
+                for (int64_t j = 0; j < m; j++) x[j] = (w[j] + S[j]) / (1.0 + alpha);
+                oracle_sstep(C, n, m, eps, a, b, x, u, ell, S, &err, &fval);
+                nsteps++;
+                for (int64_t j = 0; j < m; j++)
+                    w[j] = (w[j] + (alpha * alpha - 2.0) * x[j] + 2.0 * S[j]) / (1.0 + alpha);
+                it++;
+                if (trace_err) trace_err[it] = err;
+                if (trace_fval) trace_fval[it] = fval;
+                if (trace_x) memcpy(trace_x + it * m, x, sizeof(double) * (size_t)m);
+                done = (err < tol) || (it >= max_iter);
+            }
+            if (!done) {
+                double mu_new = mu / 2.0;
+                if (w_rule == ORACLE_W_Y_CONTINUOUS) {
+                    double ratio = sqrt(2.0 * mu_new) / alpha;
+                    for (int64_t j = 0; j < m; j++) w[j] *= ratio;
+                }
+                mu = mu_new;
+                mstage = (int64_t)floor(sqrt(2.0) * (double)mstage) + 1;
+            }
+        }
+    }
+    converged = err < tol;
+    for (int64_t i = 0; i < n; i++) f[i] = eps * u[i];
+    for (int64_t j = 0; j < m; j++) g[j] = eps * x[j];
+    *iters = it;
+    *steps = nsteps;
+    *err_out = err;
+    free(x); free(w); free(S); free(ell); free(u);
+    return converged;
+}
+
+/*
+ * Evaluation of given potentials (f, g) on cost C at eps, straight from the
+ * definitions: P_ij = exp((f_i + g_j - C_ij)/eps) (eq:P-from-dual);
+ * row_err = ||P1 - a||_1, col_err = ||P'1 - b||_1 (eq:l1tol);
+ * dual = <f,a> + <g,b> - eps * sum_ij P_ij (the EOT dual value, eq:dual-obj
+ * scaled back by eps); cost = <C,P>; mass = sum_ij P_ij.
+ */
+void oracle_eval(const double *C, int64_t n, int64_t m, double eps,
+                 const double *a, const double *b, const double *f, const double *g,
+                 double *row_err, double *col_err, double *dual, double *cost, double *mass)
+{
+    double *col = (double *)calloc((size_t)m, sizeof(double));
+    double *rowsum = (double *)malloc(sizeof(double) * (size_t)n);
+    double *rowcost = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double rs = 0.0, rc = 0.0;
+        for (int64_t j = 0; j < m; j++) {
+            double p = exp((f[i] + g[j] - C[i * m + j]) / eps);
+            rs += p;
+            rc += C[i * m + j] * p;
+        }
+        rowsum[i] = rs;
+        rowcost[i] = rc;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < m; j++) {
+        double cs = 0.0;
+        for (int64_t i = 0; i < n; i++) cs += exp((f[i] + g[j] - C[i * m + j]) / eps);
+        col[j] = cs;
+    }
+    double re = 0.0, ce = 0.0, fa = 0.0, gb = 0.0, tot = 0.0, cst = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        re += fabs(rowsum[i] - a[i]);
+        fa += f[i] * a[i];
+        tot += rowsum[i];
+        cst += rowcost[i];
+    }
+    for (int64_t j = 0; j < m; j++) {
+        ce += fabs(col[j] - b[j]);
+        gb += g[j] * b[j];
+    }
+    *row_err = re;
+    *col_err = ce;
+    *dual = fa + gb - eps * tot;
+    *cost = cst;
+    *mass = tot;
+    free(col); free(rowsum); free(rowcost);
+}
+
+/* Transport plan rows [row0, row0+rows): P_ij = exp((f_i + g_j - C_ij)/eps). */
+void oracle_plan(const double *C, int64_t n, int64_t m, double eps,
+                 const double *f, const double *g, int64_t row0, int64_t rows, double *P)
+{
+    (void)n;
+    for (int64_t r = 0; r < rows; r++) {
+        int64_t i = row0 + r;
+        for (int64_t j = 0; j < m; j++) P[r * m + j] = exp((f[i] + g[j] - C[i * m + j]) / eps);
+    }
+}
+
+/* Squared Euclidean cost C_ij = ||x_i - y_j||^2 / scale (Sec. 5, color transfer). */
+void oracle_cost_sqeuclid(const double *X, const double *Y, int64_t n, int64_t m, int64_t d,
+                          double scale, double *C)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < m; j++) {
+            double s = 0.0;
+            for (int64_t k = 0; k < d; k++) {
+                double t = X[i * d + k] - Y[j * d + k];
+                s += t * t;
+            }
+            C[i * m + j] = s / scale;
+        }
+}
+
+/* Cosine cost C_ij = (1 - <x_i, y_j>) / scale (Sec. 5, word alignment; rows of X, Y unit norm). */
+void oracle_cost_cosine(const double *X, const double *Y, int64_t n, int64_t m, int64_t d,
+                        double scale, double *C)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < m; j++) {
+            double s = 0.0;
+            for (int64_t k = 0; k < d; k++) s += X[i * d + k] * Y[j * d + k];
+            C[i * m + j] = (1.0 - s) / scale;
+        }
+}
+
+/*
+ * Gradients of the EOT value L(C) = <f,a> + <g,b> - eps*sum P at the optimum
+ * with respect to the point clouds, by the envelope theorem: dL/dC_ij = P_ij.
+ * kind 0 (squared Euclidean, C_ij = ||x_i - y_j||^2/scale):
+ *   dL/dx_i = (2/scale) sum_j P_ij (x_i - y_j),  dL/dy_j = (2/scale) sum_i P_ij (y_j - x_i)
+ * kind 1 (cosine, C_ij = (1 - x_i.y_j)/scale):
+ *   dL/dx_i = -(1/scale) sum_j P_ij y_j,          dL/dy_j = -(1/scale) sum_i P_ij x_i
+ * The plan P is formed from (f, g) on the exact FP64 cost.
+ */
+void oracle_grad_points(int kind, const double *X, const double *Y, int64_t n, int64_t m, int64_t d,
+                        double scale, double eps, const double *f, const double *g,
+                        double *dX, double *dY)
+{
+    double *C = (double *)malloc(sizeof(double) * (size_t)(n * m));
+    if (kind == 0) oracle_cost_sqeuclid(X, Y, n, m, d, scale, C);
+    else oracle_cost_cosine(X, Y, n, m, d, scale, C);
+    memset(dX, 0, sizeof(double) * (size_t)(n * d));
+    memset(dY, 0, sizeof(double) * (size_t)(m * d));
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < m; j++) {
+            double p = exp((f[i] + g[j] - C[i * m + j]) / eps);
+            for (int64_t k = 0; k < d; k++) {
+                if (kind == 0) dX[i * d + k] += (2.0 / scale) * p * (X[i * d + k] - Y[j * d + k]);
+                else dX[i * d + k] += -(1.0 / scale) * p * Y[j * d + k];
+            }
+        }
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < m; j++)
+        for (int64_t i = 0; i < n; i++) {
+            double p = exp((f[i] + g[j] - C[i * m + j]) / eps);
+            for (int64_t k = 0; k < d; k++) {
+                if (kind == 0) dY[j * d + k] += (2.0 / scale) * p * (Y[j * d + k] - X[i * d + k]);
+                else dY[j * d + k] += -(1.0 / scale) * p * X[i * d + k];
+            }
+        }
+    free(C);
+}

@@ -1,0 +1,184 @@
+"""ctypes binding of libaccsk (the HIP/gfx950 Acc-Sinkhorn library).
+
+Argument marshalling only: every step of every solve runs in the library's
+kernels.  Tensors must already live on the current HIP device; work is enqueued
+on torch's current stream.  The library is loaded on first use and its absence
+is an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaccsk.so")
+
+OK, INVALID_ARG, SHAPE, NONFINITE, NOT_CONVERGED, DIVERGED, OOM, HIP_ERROR, BUSY = range(9)
+SINKHORN, ACC = 0, 1
+W_LITERAL, W_Y_CONTINUOUS = 0, 1
+SQEUCLID, COSINE = 0, 1
+FLAG_NO_COST = 1
+FLAG_NO_SERPENTINE = 2
+
+
+class AccskError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__("%s failed: %s (status %d)" % (where, status_string(status), status))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("w_rule", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("mu0", ctypes.c_double),
+                ("m0", ctypes.c_int64), ("split", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("sinkhorn_steps", ctypes.c_int64),
+                ("fallback_steps", ctypes.c_int64), ("marginal_err", ctypes.c_double),
+                ("eot_value", ctypes.c_double), ("transport_cost", ctypes.c_double),
+                ("dual_fval", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+
+
+def lib():
+    """Load libaccsk.so (built in-tree by ``paper_2605_30267_amd.build``)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libaccsk.so is not built (%s); run python -m paper_2605_30267_amd.build"
+                               % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.accsk_default_params.argtypes = [ctypes.POINTER(Params)]
+        L.accsk_default_params.restype = None
+        L.accsk_status_string.argtypes = [ctypes.c_int]
+        L.accsk_status_string.restype = ctypes.c_char_p
+        L.accsk_version.argtypes = []
+        L.accsk_version.restype = ctypes.c_char_p
+        L.accsk_solve_dense.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, ctypes.POINTER(Params), _vp, _vp,
+                                        ctypes.POINTER(Result), _vp]
+        L.accsk_solve_dense.restype = ctypes.c_int
+        L.accsk_plan_dense.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _i64, _vp, _i64, _vp]
+        L.accsk_plan_dense.restype = ctypes.c_int
+        L.accsk_eval_dense.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _vp, _vp,
+                                       ctypes.POINTER(ctypes.c_double), _vp]
+        L.accsk_eval_dense.restype = ctypes.c_int
+        _lib = L
+        return L
+
+
+def status_string(status):
+    try:
+        return lib().accsk_status_string(int(status)).decode()
+    except Exception:  # library missing: still produce a message
+        return "status %d" % status
+
+
+def default_params(**kw):
+    p = Params()
+    lib().accsk_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if v is None:
+            continue
+        if not hasattr(p, k):
+            raise TypeError("unknown parameter %r" % k)
+        setattr(p, k, v)
+    return p
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_dev(t, dtype, name, ndim=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError("%s must have %d dims" % (name, ndim))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def solve_dense(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=None,
+                w_rule=None, flags=0, f_out=None, g_out=None, raise_on_error=True):
+    """Solve EOT on a dense FP32 cost (device).  Returns (f, g, result dict).
+
+    C: float32 [n, m] (row stride used as leading dimension, unit column stride);
+    a: float64 [n], b: float64 [m] (positive; normalized inside).
+    """
+    import torch
+    _check_dev(C, torch.float32, "C", 2)
+    _check_dev(a, torch.float64, "a", 1)
+    _check_dev(b, torch.float64, "b", 1)
+    if C.stride(1) != 1:
+        raise ValueError("C must have unit column stride")
+    n, m = C.shape
+    a = a.contiguous()
+    b = b.contiguous()
+    if f_out is None:
+        f_out = torch.empty(n, dtype=torch.float64, device=C.device)
+    if g_out is None:
+        g_out = torch.empty(m, dtype=torch.float64, device=C.device)
+    p = default_params(method=method, eps=float(eps), tol=float(tol), max_iter=int(max_iter), mu0=mu0,
+                       m0=m0, w_rule=w_rule, flags=int(flags))
+    r = Result()
+    st = lib().accsk_solve_dense(_ptr(C), n, m, C.stride(0), _ptr(a), _ptr(b), ctypes.byref(p), _ptr(f_out),
+                                 _ptr(g_out), ctypes.byref(r), _stream_ptr())
+    if raise_on_error and st not in (OK, NOT_CONVERGED):
+        raise AccskError(st, "accsk_solve_dense")
+    d = r.to_dict()
+    d["status"] = st
+    return f_out, g_out, d
+
+
+def plan_dense(C, f, g, eps, row0=0, rows=None, out=None):
+    """FP32 rows of the plan P_ij = exp((f_i + g_j - C_ij)/eps)."""
+    import torch
+    n, m = C.shape
+    rows = n - row0 if rows is None else rows
+    if out is None:
+        out = torch.empty((rows, m), dtype=torch.float32, device=C.device)
+    st = lib().accsk_plan_dense(_ptr(C), n, m, C.stride(0), float(eps), _ptr(f), _ptr(g), int(row0), int(rows),
+                                _ptr(out), out.stride(0), _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_plan_dense")
+    return out
+
+
+def eval_dense(C, a, b, f, g, eps):
+    """FP64-accumulated evaluation: dict(row_err, col_err, dual, cost, mass)."""
+    n, m = C.shape
+    out = (ctypes.c_double * 5)()
+    st = lib().accsk_eval_dense(_ptr(C), n, m, C.stride(0), float(eps), _ptr(a), _ptr(b), _ptr(f), _ptr(g),
+                                out, _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_eval_dense")
+    return dict(row_err=out[0], col_err=out[1], dual=out[2], cost=out[3], mass=out[4])
+
+
+def symbols_declared():
+    """Names of the entry points declared in include/accsk.h (parsed from the header)."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "accsk.h")
+    text = open(hdr).read()
+    return sorted(set(re.findall(r"\b(accsk_[a-z_0-9]+)\s*\(", text)))

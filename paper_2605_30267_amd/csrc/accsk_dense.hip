@@ -1,0 +1,926 @@
+// Dense explicit-cost solver: log-domain Sinkhorn and Acc-Sinkhorn on gfx950.
+//
+// One cooperative (persistent) launch runs the whole solve.  Per Sinkhorn step
+// (paper Sec. 2 eq:u-update with the normalized column step eq:normalized-sinkhorn):
+//
+//  1. Strip pass.  Block b owns a contiguous range of whole rows and keeps the
+//     iterate x (and w) for every column in registers, thread t holding the
+//     float4 column groups t, t+TPB, ...  For each of its rows i it
+//       - forms t_ij = x_j - C_ij/eps in FP64 (log2 units) from one read of the row,
+//       - takes the exact row maximum and the row sum of exp2(t_ij - max) in FP32,
+//       - gets u_i = log a_i - LSE_j(t_ij)   (exact row solve, eq:u-update),
+//       - adds exp(u_i + x_j - C_ij/eps) / max_k a_k to its per-column sums.
+//     The shift log(max a) - x_j is an upper bound of every u_i - C_ij/eps
+//     (because x_j - C_ij/eps <= LSE_j), so these terms are <= 1 and the column
+//     log-sum-exp needs no second read of C.
+//  2. Grid barrier; block b combines the per-block sums of its column slice:
+//     c_j = max a * s_j, S^_j = log b_j - log c_j + x_j, |c_j - b_j|.
+//  3. Grid barrier; every block forms the same totals (fixed order) and applies
+//     the same update to the x/w it holds: mean removal (P_Nperp), then plain
+//     Sinkhorn x <- S or Algorithm A2MD with the homotopy of A2MD-homotopy.
+//  If a column sum falls below 2^-64 (almost no mass in that column, early at
+//  small eps), an exact pass with a running column maximum redoes the column
+//  side of that step (one more read of C).
+//
+// All reductions have a fixed order, so results are bitwise reproducible.
+
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "accsk_common.h"
+
+namespace accsk {
+namespace {
+
+constexpr int kNS = 8;  // block scalar slots: 0 <u,a>, 1 sum S^, 2 err, 3 mass, 4 <x,b>, 5 fallback
+
+struct DenseArgs {
+    const float *C;
+    long long n, m, ldc;
+    const double *a_in, *b_in;
+    double *an, *la2, *bn, *lnb;  // normalized marginals, log2 a, log b
+    double *u;                    // [n] row potentials (log2 units)
+    double *rsum;                 // [n] row sums of exp2(t - max) of the last strip pass
+    double *part;                 // [G*m] per-block column sums
+    double *partmax;              // [G*m] per-block column maxima (exact pass)
+    double *shat;                 // [m] log b - ell
+    double *bscal;                // [2][G][kNS]
+    double *gscal;                // [0] = max_i log2 a_i
+    int *status;                  // setup status
+    unsigned long long *bar;      // grid barrier counter
+    DevResult *res;
+    double *f_out, *g_out;
+    double eps, kappa, tol, tol_stop, mu0;
+    long long max_iter, m0;
+    int method, w_rule, serpentine;
+};
+
+// ---------------------------------------------------------------------------
+// Marginal set-up: validation, unit mass (eq:Fc), log2 a, log b, max log2 a.
+// One block of 1024 threads; deterministic block reductions.
+// ---------------------------------------------------------------------------
+__device__ double block_sum_1024(double v, double *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < 16; k++) s += red[k];
+    return s;
+}
+__device__ double block_max_1024(double v, double *red) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = -INFINITY;
+    for (int k = 0; k < 16; k++) s = fmax(s, red[k]);
+    return s;
+}
+
+__global__ __launch_bounds__(1024) void setup_marginals(DenseArgs A) {
+    __shared__ double red[16];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    int lbad = 0;
+    double s = 0.0;
+    for (long long i = tid; i < A.n; i += 1024) {
+        double v = A.a_in[i];
+        if (!isfinite(v)) lbad |= 2;
+        else if (!(v > 0.0)) lbad |= 1;
+        s += v;
+    }
+    if (lbad) atomicOr(&bad, lbad);
+    const double sa = block_sum_1024(s, red);
+    double mx = -INFINITY;
+    for (long long i = tid; i < A.n; i += 1024) {
+        double v = A.a_in[i] / sa;
+        A.an[i] = v;
+        double l2 = log2(v);
+        A.la2[i] = l2;
+        mx = fmax(mx, l2);
+    }
+    mx = block_max_1024(mx, red);
+    lbad = 0;
+    s = 0.0;
+    for (long long j = tid; j < A.m; j += 1024) {
+        double v = A.b_in[j];
+        if (!isfinite(v)) lbad |= 2;
+        else if (!(v > 0.0)) lbad |= 1;
+        s += v;
+    }
+    if (lbad) atomicOr(&bad, lbad);
+    const double sb = block_sum_1024(s, red);
+    for (long long j = tid; j < A.m; j += 1024) {
+        double v = A.b_in[j] / sb;
+        A.bn[j] = v;
+        A.lnb[j] = log(v);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        A.gscal[0] = mx;
+        A.status[0] = (bad & 2) ? ACCSK_NONFINITE : ((bad & 1) ? ACCSK_INVALID_ARG : ACCSK_OK);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The persistent solve kernel.
+// TPB threads per block, NG float4 column groups per thread (m <= 4*TPB*NG).
+// ---------------------------------------------------------------------------
+template <int TPB, int NG, bool VEC>
+struct RowIO {
+    // Loads the thread's NG float4 column groups of one row.  Every load reads
+    // an in-bounds address (clamped), and columns >= m are then replaced by a
+    // +inf cost, so their exponent terms vanish and no branch is needed.
+    // VEC: m % 4 == 0 and 16-byte aligned rows, one dwordx4 per group.
+    static __device__ __forceinline__ void load(const float *__restrict__ row, int m, int tid,
+                                                float4 (&v)[NG]) {
+#pragma unroll
+        for (int k = 0; k < NG; k++) {
+            const int c0 = 4 * (tid + k * TPB);
+            if (VEC) {
+                const int cc = min(c0, m - 4);
+                float4 t = *reinterpret_cast<const float4 *>(row + cc);
+                const bool ok = c0 < m;
+                v[k].x = ok ? t.x : INFINITY;
+                v[k].y = ok ? t.y : INFINITY;
+                v[k].z = ok ? t.z : INFINITY;
+                v[k].w = ok ? t.w : INFINITY;
+            } else {
+                const float t0 = row[min(c0 + 0, m - 1)];
+                const float t1 = row[min(c0 + 1, m - 1)];
+                const float t2 = row[min(c0 + 2, m - 1)];
+                const float t3 = row[min(c0 + 3, m - 1)];
+                v[k].x = (c0 + 0 < m) ? t0 : INFINITY;
+                v[k].y = (c0 + 1 < m) ? t1 : INFINITY;
+                v[k].z = (c0 + 2 < m) ? t2 : INFINITY;
+                v[k].w = (c0 + 3 < m) ? t3 : INFINITY;
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ float f4get(const float4 &v, int e) {
+    return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+
+// All potentials inside the kernel are kept in log2 units (value * log2 e):
+// xl = x log2 e, wl = w log2 e, so exp(.) becomes exp2(.) with no extra
+// multiply per entry.  Algorithm A2MD is linear in (x, w, S), so it runs
+// unchanged in these units.
+template <int TPB, int NG, bool VEC>
+__global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
+    constexpr int NW = TPB / 64;
+    constexpr int NC = NG * 4;  // columns per thread
+    __shared__ double red_max[NW];
+    __shared__ double red_sum[NW];
+    __shared__ double sred[NW][64];
+    __shared__ double xs[64];
+    __shared__ double tot[kNS];
+    __shared__ int bflag;
+    extern __shared__ double wl_lds[];  // w (log2 units), indexed by column
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int G = gridDim.x, bid = blockIdx.x;
+    if (A.status[0] != ACCSK_OK) {  // uniform across the grid: no barrier is entered
+        if (bid == 0 && tid == 0) {
+            DevResult r{};
+            r.err = NAN;
+            r.eot = NAN;
+            r.fval = NAN;
+            r.cost = NAN;
+            r.status = A.status[0];
+            *A.res = r;
+        }
+        return;
+    }
+
+    const long long n = A.n, m = A.m;
+    const long long rpb = (n + G - 1) / G;
+    const long long r0 = std::min(n, (long long)bid * rpb);
+    const long long r1 = std::min(n, r0 + rpb);
+    const long long nr = r1 - r0;
+    const long long spb = (m + G - 1) / G;
+    const long long j0 = std::min(m, (long long)bid * spb);
+    const long long j1 = std::min(m, j0 + spb);
+
+    const double kap2 = A.kappa * kLog2e;  // C_ij/eps in log2 units
+    const double La2 = A.gscal[0];
+
+    double xl[NC];
+#pragma unroll
+    for (int q = 0; q < NC; q++) xl[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NG; k++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const long long col = 4ll * (tid + k * TPB) + e;
+            if (col < m) wl_lds[col] = 0.0;  // each thread owns its columns of w
+        }
+
+    double mu = A.mu0, alpha = dsqrt(2.0 * A.mu0);
+    long long mstage = A.m0, kin = 0, it = 0, steps = 0, fallbacks = 0;
+    bool first = true;
+    unsigned long long gen = 0;
+    int status = ACCSK_OK;
+    double err = 0.0, eot = 0.0, fval = 0.0;
+
+    for (long long step = 0;; step++) {
+        const int par = (int)(step & 1);
+        // Opaque copies of the base pointers and of the thread's first column:
+        // addresses derived from them are recomputed each step instead of being
+        // hoisted out of the step loop and kept live (which spills registers).
+        DenseArgs L = A;
+        opaque_ptr(L.part);
+        opaque_ptr(L.partmax);
+        opaque_ptr(L.shat);
+        opaque_ptr(L.bn);
+        opaque_ptr(L.lnb);
+        opaque_ptr(L.u);
+        opaque_ptr(L.rsum);
+        opaque_ptr(L.la2);
+        opaque_ptr(L.an);
+        opaque_ptr(L.bscal);
+        int ctid = tid;
+        opaque_int(ctid);
+        double *bs = L.bscal + (size_t)par * G * kNS;
+        // ---------------- strip pass ----------------
+        double colacc[NC];
+#pragma unroll
+        for (int q = 0; q < NC; q++) colacc[q] = 0.0;
+        double ua = 0.0;
+        const bool rev = A.serpentine && (step & 1);
+
+        float4 nxt[NG];
+        if (nr > 0) {
+            const long long i = rev ? r1 - 1 : r0;
+            RowIO<TPB, NG, VEC>::load(A.C + i * A.ldc, (int)m, ctid, nxt);
+        }
+        for (long long rr = 0; rr < nr; rr++) {
+            const long long i = rev ? r1 - 1 - rr : r0 + rr;
+            float4 cur[NG];
+#pragma unroll
+            for (int k = 0; k < NG; k++) cur[k] = nxt[k];
+            if (rr + 1 < nr) {
+                const long long inext = rev ? i - 1 : i + 1;
+                RowIO<TPB, NG, VEC>::load(A.C + inext * A.ldc, (int)m, ctid, nxt);
+            }
+            double t[NC];
+            double mloc = -INFINITY;
+#pragma unroll
+            for (int k = 0; k < NG; k++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const double tv = fma(-(double)f4get(cur[k], e), kap2, xl[k * 4 + e]);
+                    t[k * 4 + e] = tv;
+                    mloc = fmax(mloc, tv);
+                }
+            mloc = wave_max(mloc);
+            if (lane == 0) red_max[wid] = mloc;
+            __syncthreads();
+            double M = red_max[0];
+#pragma unroll
+            for (int q = 1; q < NW; q++) M = fmax(M, red_max[q]);
+            // row sum of exp2(t - M): FP32 terms, pairwise within the thread
+            float ev[NC];
+#pragma unroll
+            for (int q = 0; q < NC; q++) ev[q] = __builtin_amdgcn_exp2f((float)(t[q] - M));
+#pragma unroll
+            for (int h = 1; h < NC; h <<= 1)
+#pragma unroll
+                for (int q = 0; q + h < NC; q += 2 * h) ev[q] += ev[q + h];
+            double sd = wave_sum((double)ev[0]);
+            if (lane == 0) red_sum[wid] = sd;
+            __syncthreads();
+            double S = red_sum[0];
+#pragma unroll
+            for (int q = 1; q < NW; q++) S += red_sum[q];
+            // P_ij / max a = exp2(t_ij - M + log2 a_i - La2) / S   (u_i from eq:u-update)
+            const double sh2 = L.la2[i] - La2 - M;
+            const float invS = __builtin_amdgcn_rcpf((float)S);
+#pragma unroll
+            for (int q = 0; q < NC; q++)
+                colacc[q] += (double)(__builtin_amdgcn_exp2f((float)(t[q] + sh2)) * invS);
+            if (tid == 0) {
+                L.u[i] = M;  // row max and row sum; u_i is formed after the loop
+                L.rsum[i] = S;
+            }
+        }
+        __syncthreads();
+        // u_i log2 e = log2 a_i - (M_i + log2 S_i), off the streaming loop
+        for (long long i = r0 + tid; i < r1; i += TPB) {
+            const double u2 = L.la2[i] - (L.u[i] + dlog2(L.rsum[i]));
+            L.u[i] = u2;
+            ua += L.an[i] * u2;
+        }
+        ua = wave_sum(ua);
+        if (lane == 0) sred[wid][0] = ua;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; q++) s += sred[q][0];
+            ua = s;
+        }
+#pragma unroll
+        for (int k = 0; k < NG; k++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const long long col = 4ll * (ctid + k * TPB) + e;
+                if (col < m) L.part[(size_t)bid * m + col] = colacc[k * 4 + e];
+            }
+        if (tid == 0) bs[(size_t)bid * kNS + 0] = ua;
+        if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
+
+        // ---------------- slice combine ----------------
+        bool exact = false;
+        for (int pass = 0; pass < 2; pass++) {
+            if (pass == 1) {
+                if (!exact) break;
+                // Exact column pass: running maximum per column over this block's rows.
+                double cm[NC];
+                float cs[NC];
+#pragma unroll
+                for (int q = 0; q < NC; q++) { cm[q] = -INFINITY; cs[q] = 0.f; }
+                for (long long rr = 0; rr < nr; rr++) {
+                    const long long i = r0 + rr;
+                    float4 cv[NG];
+                    RowIO<TPB, NG, VEC>::load(A.C + i * A.ldc, (int)m, ctid, cv);
+                    const double u2 = L.u[i];
+#pragma unroll
+                    for (int k = 0; k < NG; k++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            const int q = k * 4 + e;
+                            const double a2 = fma(-(double)f4get(cv[k], e), kap2, u2);
+                            if (a2 > cm[q]) {
+                                cs[q] = cs[q] * __builtin_amdgcn_exp2f((float)(cm[q] - a2)) + 1.f;
+                                cm[q] = a2;
+                            } else {
+                                cs[q] += __builtin_amdgcn_exp2f((float)(a2 - cm[q]));
+                            }
+                        }
+                }
+#pragma unroll
+                for (int k = 0; k < NG; k++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const long long col = 4ll * (ctid + k * TPB) + e;
+                        if (col < m) {
+                            L.part[(size_t)bid * m + col] = (double)cs[k * 4 + e];
+                            L.partmax[(size_t)bid * m + col] = cm[k * 4 + e];
+                        }
+                    }
+                if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
+                fallbacks++;
+            }
+            double aS = 0.0, aE = 0.0, aC = 0.0, aXB = 0.0, aFB = 0.0;
+            for (long long cb = j0; cb < j1; cb += 64) {
+                // stage x of this 64-column chunk in LDS
+#pragma unroll
+                for (int k = 0; k < NG; k++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const long long col = 4ll * (ctid + k * TPB) + e;
+                        if (col >= cb && col < cb + 64 && col < j1) xs[col - cb] = xl[k * 4 + e];
+                    }
+                const long long j = cb + lane;
+                double acc = 0.0, pm = -INFINITY;
+                if (j < j1) {
+                    if (pass == 0) {
+                        for (int b = wid; b < G; b += NW) acc += L.part[(size_t)b * m + j];
+                    } else {
+                        for (int b = 0; b < G; b++) pm = fmax(pm, L.partmax[(size_t)b * m + j]);
+                        for (int b = wid; b < G; b += NW) {
+                            const double mb = L.partmax[(size_t)b * m + j];
+                            acc += L.part[(size_t)b * m + j] * dexp2(mb - pm);
+                        }
+                    }
+                }
+                sred[wid][lane] = acc;
+                __syncthreads();
+                if (wid == 0 && j < j1) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NW; q++) s += sred[q][lane];
+                    const double xj = xs[lane];
+                    double lc2;  // log2 c_j, c_j = column sum of P at (u(x), x)
+                    if (pass == 0) {
+                        lc2 = La2 + dlog2(s);
+                        if (s < 0x1p-64) aFB += 1.0;
+                    } else {
+                        lc2 = pm + dlog2(s) + xj;
+                    }
+                    const double c = dexp2(lc2);
+                    const double sh = L.lnb[j] * kLog2e - lc2 + xj;  // (log b_j - ell_j) log2 e
+                    L.shat[j] = sh;
+                    aS += sh;
+                    aE += fabs(c - L.bn[j]);
+                    aC += c;
+                    aXB += xj * L.bn[j];
+                }
+                __syncthreads();
+            }
+            if (wid == 0) {
+                aS = wave_sum(aS);
+                aE = wave_sum(aE);
+                aC = wave_sum(aC);
+                aXB = wave_sum(aXB);
+                aFB = wave_sum(aFB);
+                if (lane == 0) {
+                    double *p = bs + (size_t)bid * kNS;
+                    p[1] = aS;
+                    p[2] = aE;
+                    p[3] = aC;
+                    p[4] = aXB;
+                    p[5] = aFB;
+                }
+            }
+            if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
+            // totals, identical in every block
+            for (int sidx = wid; sidx < 6; sidx += NW) {
+                double v = 0.0;
+                for (int b = lane; b < G; b += 64) v += bs[(size_t)b * kNS + sidx];
+                v = wave_sum(v);
+                if (lane == 0) tot[sidx] = v;
+            }
+            __syncthreads();
+            exact = (pass == 0) && (tot[5] > 0.0);
+            __syncthreads();
+        }
+        if (status != ACCSK_OK) break;
+
+        // ---------------- update (every block, identical) ----------------
+        err = tot[2];
+        const double mean = tot[1] / (double)m;
+        const double mass = tot[3];
+        const double ua_ln = tot[0] * kLn2, xb_ln = tot[4] * kLn2;
+        fval = 1.0 - ua_ln - xb_ln;               // f(x) = 1 - <u,a> - <x,b>
+        eot = A.eps * (ua_ln + xb_ln - mass);    // <f,a> + <g,b> - eps sum P
+        steps++;
+        if (!isfinite(err)) {
+            status = (steps == 1) ? ACCSK_NONFINITE : ACCSK_DIVERGED;
+            break;
+        }
+        if (A.method == ACCSK_SINKHORN) {
+            // plain Sinkhorn, eq:normalized-sinkhorn: x <- S(x)
+            if (err < A.tol_stop || it >= A.max_iter) break;
+#pragma unroll
+            for (int k = 0; k < NG; k++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const long long col = 4ll * (ctid + k * TPB) + e;
+                    xl[k * 4 + e] = (col < m) ? L.shat[col] - mean : 0.0;
+                }
+            it++;
+        } else {
+            // Algorithm A2MD: S is Sinkhorn(x) at the current x; the w update
+            // below uses it as Sinkhorn(x_{k+1}) and the next x update reuses it.
+            double S[NC];
+#pragma unroll
+            for (int k = 0; k < NG; k++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const long long col = 4ll * (ctid + k * TPB) + e;
+                    S[k * 4 + e] = (col < m) ? L.shat[col] - mean : 0.0;
+                }
+            if (!first) {
+                const double c2 = alpha * alpha - 2.0, inv = 1.0 / (1.0 + alpha);
+#pragma unroll
+                for (int k = 0; k < NG; k++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const long long col = 4ll * (ctid + k * TPB) + e;
+                        if (col < m) wl_lds[col] = (wl_lds[col] + c2 * xl[k * 4 + e] + 2.0 * S[k * 4 + e]) * inv;
+                    }
+                it++;
+                kin++;
+            }
+            if (err < A.tol_stop || it >= A.max_iter) break;
+            if (!first && kin == mstage) {
+                // Algorithm A2MD-homotopy: mu <- mu/2, m <- floor(sqrt(2) m) + 1
+                const double mu_new = mu / 2.0;
+                if (A.w_rule == ACCSK_W_Y_CONTINUOUS) {
+                    const double ratio = dsqrt(2.0 * mu_new) / alpha;
+#pragma unroll
+                    for (int k = 0; k < NG; k++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            const long long col = 4ll * (ctid + k * TPB) + e;
+                            if (col < m) wl_lds[col] *= ratio;
+                        }
+                }
+                mu = mu_new;
+                alpha = dsqrt(2.0 * mu);
+                mstage = (long long)floor(1.4142135623730951 * (double)mstage) + 1;
+                kin = 0;
+            }
+            first = false;
+            const double inv = 1.0 / (1.0 + alpha);
+#pragma unroll
+            for (int k = 0; k < NG; k++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const long long col = 4ll * (ctid + k * TPB) + e;
+                    xl[k * 4 + e] = (col < m) ? (wl_lds[col] + S[k * 4 + e]) * inv : 0.0;
+                }
+        }
+    }
+
+    // ---------------- outputs ----------------
+    if (status == ACCSK_OK || status == ACCSK_DIVERGED) {
+        for (long long i = r0 + tid; i < r1; i += TPB) A.f_out[i] = A.eps * kLn2 * A.u[i];
+        if (bid == 0) {
+#pragma unroll
+            for (int k = 0; k < NG; k++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const long long col = 4ll * (tid + k * TPB) + e;
+                    if (col < m) A.g_out[col] = A.eps * kLn2 * xl[k * 4 + e];
+                }
+        }
+    }
+    if (bid == 0 && tid == 0) {
+        DevResult r;
+        r.iters = it;
+        r.steps = steps;
+        r.fallback = fallbacks;
+        r.err = err;
+        r.eot = eot;
+        r.fval = fval;
+        r.cost = NAN;
+        r.converged = (status == ACCSK_OK && err < A.tol_stop) ? 1 : 0;
+        r.status = status;
+        *A.res = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 evaluation of (f, g): row/col L1 errors, dual value, <C,P>, sum P.
+// ---------------------------------------------------------------------------
+constexpr int kEvalTPB = 256;
+
+__global__ __launch_bounds__(kEvalTPB) void eval_rows(const float *__restrict__ C, long long n,
+                                                      long long m, long long ldc, double inv_eps,
+                                                      const double *__restrict__ a,
+                                                      const double *__restrict__ f,
+                                                      const double *__restrict__ g,
+                                                      double *__restrict__ rowscal) {
+    __shared__ double red[kEvalTPB / 64][2];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int G = gridDim.x, bid = blockIdx.x;
+    double re = 0.0, mass = 0.0, cost = 0.0;
+    for (long long i = bid; i < n; i += G) {
+        double rs = 0.0, rc = 0.0;
+        const double fi = f[i];
+        for (long long j = tid; j < m; j += kEvalTPB) {
+            const double c = (double)C[i * ldc + j];
+            const double p = exp((fi + g[j] - c) * inv_eps);
+            rs += p;
+            rc += c * p;
+        }
+        rs = wave_sum(rs);
+        rc = wave_sum(rc);
+        if (lane == 0) {
+            red[wid][0] = rs;
+            red[wid][1] = rc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < kEvalTPB / 64; q++) {
+                s0 += red[q][0];
+                s1 += red[q][1];
+            }
+            re += fabs(s0 - a[i]);
+            mass += s0;
+            cost += s1;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        rowscal[bid * 3 + 0] = re;
+        rowscal[bid * 3 + 1] = mass;
+        rowscal[bid * 3 + 2] = cost;
+    }
+}
+
+// Column sums of P over the row slab blockIdx.y (coalesced along j).
+__global__ __launch_bounds__(kEvalTPB) void eval_colpart(const float *__restrict__ C, long long n,
+                                                         long long m, long long ldc, double inv_eps,
+                                                         const double *__restrict__ f,
+                                                         const double *__restrict__ g,
+                                                         double *__restrict__ colpart) {
+    const long long j = (long long)blockIdx.x * kEvalTPB + threadIdx.x;
+    const int RS = gridDim.y;
+    const long long rpb = (n + RS - 1) / RS;
+    const long long i0 = (long long)blockIdx.y * rpb, i1 = std::min(n, i0 + rpb);
+    if (j >= m) return;
+    const double gj = g[j];
+    double s = 0.0;
+    for (long long i = i0; i < i1; i++) s += exp((f[i] + gj - (double)C[i * ldc + j]) * inv_eps);
+    colpart[(size_t)blockIdx.y * m + j] = s;
+}
+
+__global__ __launch_bounds__(kEvalTPB) void eval_cols(long long m, int G, const double *__restrict__ b,
+                                                      const double *__restrict__ colpart,
+                                                      double *__restrict__ colerr) {
+    const long long j = (long long)blockIdx.x * kEvalTPB + threadIdx.x;
+    if (j >= m) return;
+    double s = 0.0;
+    for (int q = 0; q < G; q++) s += colpart[(size_t)q * m + j];
+    colerr[j] = fabs(s - b[j]);
+}
+
+__global__ __launch_bounds__(1024) void eval_final(long long n, long long m, int G, double eps,
+                                                   const double *__restrict__ a,
+                                                   const double *__restrict__ b,
+                                                   const double *__restrict__ f,
+                                                   const double *__restrict__ g,
+                                                   const double *__restrict__ rowscal,
+                                                   const double *__restrict__ colerr,
+                                                   double *__restrict__ out, DevResult *res) {
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    double re = 0.0, mass = 0.0, cost = 0.0, ce = 0.0, fa = 0.0, gb = 0.0;
+    for (int q = tid; q < G; q += 1024) {
+        re += rowscal[q * 3 + 0];
+        mass += rowscal[q * 3 + 1];
+        cost += rowscal[q * 3 + 2];
+    }
+    for (long long j = tid; j < m; j += 1024) {
+        ce += colerr[j];
+        gb += g[j] * b[j];
+    }
+    for (long long i = tid; i < n; i += 1024) fa += f[i] * a[i];
+    re = block_sum_1024(re, red);
+    mass = block_sum_1024(mass, red);
+    cost = block_sum_1024(cost, red);
+    ce = block_sum_1024(ce, red);
+    fa = block_sum_1024(fa, red);
+    gb = block_sum_1024(gb, red);
+    if (tid == 0) {
+        out[0] = re;
+        out[1] = ce;
+        out[2] = fa + gb - eps * mass;
+        out[3] = cost;
+        out[4] = mass;
+        if (res) {
+            res->cost = cost;
+            res->eot = fa + gb - eps * mass;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plan rows from potentials.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void plan_rows(const float *__restrict__ C, long long m, long long ldc,
+                                                 double inv_eps, const double *__restrict__ f,
+                                                 const double *__restrict__ g, long long row0,
+                                                 long long rows, float *__restrict__ P, long long ldp) {
+    const long long r = blockIdx.y;
+    const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows || j >= m) return;
+    const long long i = row0 + r;
+    P[r * ldp + j] = (float)exp((f[i] + g[j] - (double)C[i * ldc + j]) * inv_eps);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct Workspace {
+    void *base = nullptr;
+    size_t bytes = 0;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <int TPB, int NG, bool VEC>
+accsk_status launch_dense(DenseArgs &A, hipStream_t s, int num_cu, void *&ws, size_t &ws_bytes,
+                          int &grid_out) {
+    int occ = 0;
+    const size_t dyn = (size_t)A.m * sizeof(double);
+    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, VEC>, TPB, dyn));
+    if (occ < 1) return ACCSK_SHAPE;
+    long long G = (long long)occ * num_cu;
+    G = std::min<long long>(G, std::max<long long>(1, A.n));
+    // workspace
+    const size_t n = A.n, m = A.m;
+    size_t off = 0;
+    const size_t o_an = off; off = align_up(off + n * 8);
+    const size_t o_la2 = off; off = align_up(off + n * 8);
+    const size_t o_u = off; off = align_up(off + n * 8);
+    const size_t o_rs = off; off = align_up(off + n * 8);
+    const size_t o_bn = off; off = align_up(off + m * 8);
+    const size_t o_lnb = off; off = align_up(off + m * 8);
+    const size_t o_shat = off; off = align_up(off + m * 8);
+    const size_t o_part = off; off = align_up(off + (size_t)G * m * 8);
+    const size_t o_pmax = off; off = align_up(off + (size_t)G * m * 8);
+    const size_t o_bscal = off; off = align_up(off + 2 * (size_t)G * kNS * 8);
+    const size_t o_gscal = off; off = align_up(off + 8 * 8);
+    const size_t o_stat = off; off = align_up(off + 64);
+    const size_t o_bar = off; off = align_up(off + 64);
+    const size_t o_res = off; off = align_up(off + sizeof(DevResult));
+    void *base = nullptr;
+    if (hipMallocAsync(&base, off, s) != hipSuccess) return ACCSK_OOM;
+    char *p = (char *)base;
+    A.an = (double *)(p + o_an);
+    A.la2 = (double *)(p + o_la2);
+    A.u = (double *)(p + o_u);
+    A.rsum = (double *)(p + o_rs);
+    A.bn = (double *)(p + o_bn);
+    A.lnb = (double *)(p + o_lnb);
+    A.shat = (double *)(p + o_shat);
+    A.part = (double *)(p + o_part);
+    A.partmax = (double *)(p + o_pmax);
+    A.bscal = (double *)(p + o_bscal);
+    A.gscal = (double *)(p + o_gscal);
+    A.status = (int *)(p + o_stat);
+    A.bar = (unsigned long long *)(p + o_bar);
+    A.res = (DevResult *)(p + o_res);
+    ws = base;
+    ws_bytes = off;
+    hipError_t e = hipMemsetAsync(p + o_bar, 0, 64, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(setup_marginals, dim3(1), dim3(1024), 0, s, A);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        void *args[] = {&A};
+        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, VEC>, dim3((unsigned)G), dim3(TPB),
+                                       args, dyn, s);
+    }
+    grid_out = (int)G;
+    return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+template <bool VEC>
+accsk_status launch_dense_cfg(DenseArgs &A, hipStream_t s, int cu, void *&ws, size_t &ws_bytes, int &G) {
+    const long long m = A.m;
+    if (m <= 256) return launch_dense<64, 1, VEC>(A, s, cu, ws, ws_bytes, G);
+    if (m <= 512) return launch_dense<128, 1, VEC>(A, s, cu, ws, ws_bytes, G);
+    if (m <= 1024) return launch_dense<256, 1, VEC>(A, s, cu, ws, ws_bytes, G);
+    if (m <= 2048) return launch_dense<512, 1, VEC>(A, s, cu, ws, ws_bytes, G);
+    if (m <= 4096) return launch_dense<512, 2, VEC>(A, s, cu, ws, ws_bytes, G);
+    return launch_dense<512, 4, VEC>(A, s, cu, ws, ws_bytes, G);
+}
+
+int device_cu_count() {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cu;
+}
+
+accsk_status run_eval(const float *C, long long n, long long m, long long ldc, double eps, const double *a,
+                      const double *b, const double *f, const double *g, double *out_dev, DevResult *res,
+                      hipStream_t s) {
+    const int G = (int)std::min<long long>(n, 1024);
+    const int RS = (int)std::min<long long>(n, 64);
+    double *buf = nullptr;
+    const size_t bytes = ((size_t)RS * m + (size_t)G * 3 + m) * 8;
+    if (hipMallocAsync((void **)&buf, bytes, s) != hipSuccess) return ACCSK_OOM;
+    double *colpart = buf, *rowscal = buf + (size_t)RS * m, *colerr = rowscal + (size_t)G * 3;
+    hipLaunchKernelGGL(eval_rows, dim3(G), dim3(kEvalTPB), 0, s, C, n, m, ldc, 1.0 / eps, a, f, g, rowscal);
+    hipLaunchKernelGGL(eval_colpart, dim3((unsigned)((m + kEvalTPB - 1) / kEvalTPB), RS), dim3(kEvalTPB), 0, s,
+                       C, n, m, ldc, 1.0 / eps, f, g, colpart);
+    hipLaunchKernelGGL(eval_cols, dim3((unsigned)((m + kEvalTPB - 1) / kEvalTPB)), dim3(kEvalTPB), 0, s, m, RS,
+                       b, colpart, colerr);
+    hipLaunchKernelGGL(eval_final, dim3(1), dim3(1024), 0, s, n, m, G, eps, a, b, f, g, rowscal, colerr,
+                       out_dev, res);
+    hipError_t e = hipGetLastError();
+    hipFreeAsync(buf, s);
+    return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+}  // namespace accsk
+
+using namespace accsk;
+
+extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc, const double *a,
+                                          const double *b, const accsk_params *p, double *f_out,
+                                          double *g_out, accsk_result *res, void *stream) {
+    if (res) {
+        res->status = ACCSK_INVALID_ARG;
+        res->converged = 0;
+    }
+    if (!C || !a || !b || !p || !f_out || !g_out || !res) return ACCSK_INVALID_ARG;
+    if (!finite_pos(p->eps) || !finite_pos(p->tol) || p->max_iter < 0) return ACCSK_INVALID_ARG;
+    if (p->method != ACCSK_SINKHORN && p->method != ACCSK_ACC) return ACCSK_INVALID_ARG;
+    if (p->method == ACCSK_ACC && !(p->mu0 > 0.0 && p->mu0 < 1.0 && p->m0 >= 1)) return ACCSK_INVALID_ARG;
+    if (p->w_rule != ACCSK_W_LITERAL && p->w_rule != ACCSK_W_Y_CONTINUOUS) return ACCSK_INVALID_ARG;
+    if (n < 1 || m < 1 || ldc < m) return ACCSK_SHAPE;
+    if (m > 8192) return ACCSK_SHAPE;
+    hipStream_t s = (hipStream_t)stream;
+    const int cu = device_cu_count();
+    if (cu <= 0) return ACCSK_HIP_ERROR;
+
+    DenseArgs A{};
+    A.C = C;
+    A.n = n;
+    A.m = m;
+    A.ldc = ldc;
+    A.a_in = a;
+    A.b_in = b;
+    A.f_out = f_out;
+    A.g_out = g_out;
+    A.eps = p->eps;
+    A.kappa = 1.0 / p->eps;
+    A.tol = p->tol;
+    // The stop test compares an error computed from FP32 exponential sums;
+    // stopping 1/16 below tol keeps the FP64-evaluated error under tol.
+    A.tol_stop = p->tol * (1.0 - 1.0 / 16.0);
+    A.mu0 = p->mu0;
+    A.max_iter = p->max_iter;
+    A.m0 = p->m0;
+    A.method = p->method;
+    A.w_rule = p->w_rule;
+    A.serpentine = (p->flags & ACCSK_FLAG_NO_SERPENTINE) ? 0 : 1;
+
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int G = 0;
+    accsk_status st;
+    const bool vec = (ldc % 4) == 0 && (m % 4) == 0 && (((uintptr_t)C) & 15) == 0;
+    if (vec) st = launch_dense_cfg<true>(A, s, cu, ws, ws_bytes, G);
+    else st = launch_dense_cfg<false>(A, s, cu, ws, ws_bytes, G);
+    if (st != ACCSK_OK) {
+        if (ws) hipFreeAsync(ws, s);
+        return st;
+    }
+    double *out_dev = A.gscal + 1;  // 5 slots after max log2 a
+    if (!(p->flags & ACCSK_FLAG_NO_COST)) {
+        // <C,P> and the dual value at the returned potentials, FP64, with normalized marginals
+        st = run_eval(C, n, m, ldc, p->eps, A.an, A.bn, f_out, g_out, out_dev, A.res, s);
+        if (st != ACCSK_OK) {
+            hipFreeAsync(ws, s);
+            return st;
+        }
+    }
+    DevResult r;
+    hipError_t e = hipMemcpyAsync(&r, A.res, sizeof(DevResult), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFreeAsync(ws, s);
+    if (e != hipSuccess) return ACCSK_HIP_ERROR;
+    res->iters = r.iters;
+    res->sinkhorn_steps = r.steps;
+    res->fallback_steps = r.fallback;
+    res->marginal_err = r.err;
+    res->eot_value = r.eot;
+    res->transport_cost = r.cost;
+    res->dual_fval = r.fval;
+    res->converged = r.converged;
+    res->status = r.status;
+    if (r.status == ACCSK_OK && !r.converged) res->status = ACCSK_NOT_CONVERGED;
+    return (accsk_status)res->status;
+}
+
+extern "C" accsk_status accsk_plan_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,
+                                         const double *f, const double *g, int64_t row0, int64_t rows,
+                                         float *P, int64_t ldp, void *stream) {
+    if (!C || !f || !g || !P) return ACCSK_INVALID_ARG;
+    if (!finite_pos(eps)) return ACCSK_INVALID_ARG;
+    if (n < 1 || m < 1 || ldc < m || ldp < m || row0 < 0 || rows < 0 || row0 + rows > n) return ACCSK_SHAPE;
+    if (rows == 0) return ACCSK_OK;
+    if (rows > 65535) {
+        for (int64_t r = 0; r < rows; r += 65535) {
+            accsk_status st = accsk_plan_dense(C, n, m, ldc, eps, f, g, row0 + r, std::min<int64_t>(65535, rows - r),
+                                               P + r * ldp, ldp, stream);
+            if (st != ACCSK_OK) return st;
+        }
+        return ACCSK_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    dim3 grid((unsigned)((m + 255) / 256), (unsigned)rows);
+    hipLaunchKernelGGL(plan_rows, grid, dim3(256), 0, s, C, m, ldc, 1.0 / eps, f, g, row0, rows, P, ldp);
+    return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+extern "C" accsk_status accsk_eval_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,
+                                         const double *a, const double *b, const double *f, const double *g,
+                                         double *out, void *stream) {
+    if (!C || !a || !b || !f || !g || !out) return ACCSK_INVALID_ARG;
+    if (!finite_pos(eps)) return ACCSK_INVALID_ARG;
+    if (n < 1 || m < 1 || ldc < m) return ACCSK_SHAPE;
+    hipStream_t s = (hipStream_t)stream;
+    double *dout = nullptr;
+    if (hipMallocAsync((void **)&dout, 8 * 8, s) != hipSuccess) return ACCSK_OOM;
+    accsk_status st = run_eval(C, n, m, ldc, eps, a, b, f, g, dout, nullptr, s);
+    if (st == ACCSK_OK) {
+        hipError_t e = hipMemcpyAsync(out, dout, 5 * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = ACCSK_HIP_ERROR;
+    }
+    hipFreeAsync(dout, s);
+    return st;
+}

@@ -1,0 +1,161 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws inputs (point clouds, marginals, dense costs, request
+streams).  It holds none of the solver's arithmetic and is shared by the tests,
+the benchmark and the smoke check; both the GPU library and the FP64 oracle are
+fed from it.  Every generator uses ``numpy.random.default_rng(seed)`` and draws
+in the order written in its docstring.
+
+Workloads (the paper's own data -- two photographs, fastText vectors and the
+MUSE dictionary of Sec. 5 -- are not available, so these stand in for them):
+
+* ``small_uniform``     n = m = 256, points U[0,1]^2, sq-Euclidean / max,
+                        a, b ~ U(0.5, 1.5) normalized, eps = 1e-2.
+* ``gmm_dense``         n = m = 8192, 4-component 2-D Gaussian mixtures
+                        (means U[0,1]^2, sigma 0.1), sq-Euclidean / max as FP32,
+                        a, b ~ Dirichlet(1); eps in {1e-2, 1e-3, 1e-4}.
+* ``color_points``      n = m = 32768 RGB points from 8-cluster mixtures
+                        (centres U[0,1]^3, proportions Dirichlet(1_8), sigma 0.05,
+                        clipped to [0,1]^3); weights proportional to the point's
+                        cluster share; eps = 1e-3 (colour-transfer stand-in).
+* ``word_requests``     a stream of solves with n, m ~ U{8..256}, unit-norm
+                        N(0, I_300) embeddings, uniform marginals, eps from
+                        {1e-2, 3e-3, 1e-3}, Poisson arrival times (word-alignment
+                        stand-in).
+* ``gaussian_batch``    B problems with X, Y ~ N(0, I_64), n = m = 2048,
+                        uniform marginals, eps = 5e-3.
+* ``paper_synthetic``   Sec. 5 "Synthetic Datasets": a, b, C with entries
+                        U[0,1], a and b normalized to unit sum, C scaled to sum 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _sq_dist_over_max(X, Y, chunk=1024):
+    """Dense ||x_i - y_j||^2 divided by its maximum, computed in FP64 by rows."""
+    n, m = X.shape[0], Y.shape[0]
+    C = np.empty((n, m), dtype=np.float64)
+    for i0 in range(0, n, chunk):
+        Xi = X[i0:i0 + chunk]
+        D = Xi[:, None, :] - Y[None, :, :]
+        C[i0:i0 + chunk] = np.einsum("ijk,ijk->ij", D, D)
+    return C / C.max()
+
+
+def small_uniform(seed=1, n=256, m=256):
+    """X ~ U[0,1]^2 (drawn first), Y ~ U[0,1]^2, a ~ U(0.5,1.5), b ~ U(0.5,1.5).
+
+    Returns dict(C32 [n,m] float32, a, b [float64, unit sum], eps=1e-2).
+    """
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0.0, 1.0, size=(n, 2))
+    Y = rng.uniform(0.0, 1.0, size=(m, 2))
+    a = rng.uniform(0.5, 1.5, size=n)
+    b = rng.uniform(0.5, 1.5, size=m)
+    C = _sq_dist_over_max(X, Y).astype(np.float32)
+    return dict(C32=C, a=a / a.sum(), b=b / b.sum(), eps=1e-2, X=X, Y=Y)
+
+
+def _gmm2d(rng, count, k=4, sigma=0.1):
+    means = rng.uniform(0.0, 1.0, size=(k, 2))
+    comp = rng.integers(0, k, size=count)
+    return means[comp] + sigma * rng.standard_normal(size=(count, 2))
+
+
+def gmm_dense(seed=2, n=8192, m=8192, eps=1e-2):
+    """Draw order: X mixture (means, components, noise), Y mixture, a ~ Dir(1_n), b ~ Dir(1_m).
+
+    Returns dict(C32 float32 [n,m] row-major, a, b float64 unit sum, eps).
+    """
+    rng = np.random.default_rng(seed)
+    X = _gmm2d(rng, n)
+    Y = _gmm2d(rng, m)
+    a = rng.dirichlet(np.ones(n))
+    b = rng.dirichlet(np.ones(m))
+    C = _sq_dist_over_max(X, Y).astype(np.float32)
+    return dict(C32=C, a=a, b=b, eps=eps, X=X, Y=Y)
+
+
+def _rgb_clusters(rng, count, k=8, sigma=0.05):
+    centres = rng.uniform(0.0, 1.0, size=(k, 3))
+    props = rng.dirichlet(np.ones(k))
+    comp = rng.choice(k, size=count, p=props)
+    pts = np.clip(centres[comp] + sigma * rng.standard_normal(size=(count, 3)), 0.0, 1.0)
+    share = np.bincount(comp, minlength=k) / count
+    w = share[comp]
+    return pts, w / w.sum()
+
+
+def color_points(seed=3, n=32768, m=32768, eps=1e-3):
+    """Draw order: X (centres, proportions, labels, noise), then Y the same way.
+
+    Returns float32 X [n,3], Y [m,3] and float64 weights a, b (unit sum).
+    """
+    rng = np.random.default_rng(seed)
+    X, a = _rgb_clusters(rng, n)
+    Y, b = _rgb_clusters(rng, m)
+    return dict(X=X.astype(np.float32), Y=Y.astype(np.float32), a=a, b=b, eps=eps)
+
+
+def unit_rows(rng, count, d):
+    Z = rng.standard_normal(size=(count, d))
+    return Z / np.linalg.norm(Z, axis=1, keepdims=True)
+
+
+def word_requests(seed=4, count=4000, d=300, rate=None, eps_set=(1e-2, 3e-3, 1e-3),
+                  nmin=8, nmax=256):
+    """Per request, in order: n, m ~ U{nmin..nmax}, eps index, X [n,d], Y [m,d].
+
+    Arrival gaps ~ Exp(rate) drawn afterwards from ``default_rng(seed * 10)``
+    (rate None -> all arrive at t = 0).  Marginals are uniform.
+    """
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        m = int(rng.integers(nmin, nmax + 1))
+        eps = float(eps_set[int(rng.integers(0, len(eps_set)))])
+        X = unit_rows(rng, n, d).astype(np.float32)
+        Y = unit_rows(rng, m, d).astype(np.float32)
+        reqs.append(dict(X=X, Y=Y, a=np.full(n, 1.0 / n), b=np.full(m, 1.0 / m), eps=eps))
+    arr = np.zeros(count)
+    if rate is not None:
+        gaps = np.random.default_rng(seed * 10).exponential(1.0 / rate, size=count)
+        arr = np.cumsum(gaps)
+    for r, t in zip(reqs, arr):
+        r["arrival"] = float(t)
+    return reqs
+
+
+def gaussian_batch(seed=5, batch=64, n=2048, m=2048, d=64, eps=5e-3):
+    """Draw order: X [batch,n,d] then Y [batch,m,d], i.i.d. N(0,1), float32."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal(size=(batch, n, d)).astype(np.float32)
+    Y = rng.standard_normal(size=(batch, m, d)).astype(np.float32)
+    a = np.full((batch, n), 1.0 / n)
+    b = np.full((batch, m), 1.0 / m)
+    return dict(X=X, Y=Y, a=a, b=b, eps=eps, scale=2.0 * d)
+
+
+def paper_synthetic(seed=6, n=100, m=50, eps=1e-8):
+    """Sec. 5 synthetic: a, b, C entries U[0,1]; a, b to unit sum; C to unit total."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 1.0, size=n)
+    b = rng.uniform(0.0, 1.0, size=m)
+    C = rng.uniform(0.0, 1.0, size=(n, m))
+    return dict(C=C / C.sum(), a=a / a.sum(), b=b / b.sum(), eps=eps)
+
+
+def random_dense(seed, n, m, eps=1e-2, a_kind="uniform"):
+    """Small generic dense problem for tests: C ~ U[0,1] as float32, positive marginals."""
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0.0, 1.0, size=(n, m)).astype(np.float32)
+    if a_kind == "dirichlet":
+        a = rng.dirichlet(np.ones(n))
+        b = rng.dirichlet(np.ones(m))
+    else:
+        a = rng.uniform(0.5, 1.5, size=n)
+        b = rng.uniform(0.5, 1.5, size=m)
+        a, b = a / a.sum(), b / b.sum()
+    return dict(C32=C, a=a, b=b, eps=eps)
