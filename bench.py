@@ -1,0 +1,212 @@
+"""Benchmark: dense explicit-cost Acc-Sinkhorn solves on one MI355X.
+
+Workload: n = m = 8192 dense FP32 squared-Euclidean cost (max-normalized) of two
+4-component 2-D Gaussian mixtures, Dirichlet(1) marginals, tol 1e-6 on the L1
+marginal error; eps = 1e-3 for the headline value (1e-2 and 1e-4 reported as
+context).  One "step" of this benchmark is one complete solve (set-up, all
+iterations, final FP64 cost pass) with the inputs already resident in HBM.
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--context", type=int, default=1, help="also time Sinkhorn and other eps (1/0)")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_name(m):
+    """Instantiation of the persistent solve kernel the library picks for m columns."""
+    if m <= 256:
+        return "dense_solve<64,1,2>"
+    if m <= 512:
+        return "dense_solve<128,1,2>"
+    if m <= 1024:
+        return "dense_solve<256,1,2>"
+    if m <= 2048:
+        return "dense_solve<512,1,2>"
+    if m <= 4096:
+        return "dense_solve<1024,1,2>"
+    return "dense_solve<1024,2,1>"
+
+
+def copy_calibration(gib=1.0):
+    """Plain device copy of a known size, for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 3}))
+
+
+def traffic_from_profile():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    src = os.path.join(ROOT, "paper_2605_30267_amd", "csrc", "accsk_dense.hip")
+    path = os.path.join(ROOT, "profiles", "dense_solve_gmm8192_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as fh:
+        d = json.load(fh)
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if d.get("source_sha256") != h:
+        return None, None
+    return d.get("hbm_bytes_per_launch"), d
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU row sharding is a design, "
+              "not code); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2605_30267_amd import accsk
+    from paper_2605_30267_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    accsk.lib()
+    dev = torch.device("cuda:0")
+    n = m = args.n
+    log("generating gmm_dense n=m=%d" % n)
+    p = W.gmm_dense(seed=2, n=n, m=m, eps=args.eps)
+    C = torch.as_tensor(p["C32"], device=dev)
+    a = torch.as_tensor(p["a"], dtype=torch.float64, device=dev)
+    b = torch.as_tensor(p["b"], dtype=torch.float64, device=dev)
+    f = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty(m, dtype=torch.float64, device=dev)
+
+    def solve(eps, method):
+        return accsk.solve_dense(C, a, b, eps, tol=1e-6, method=method, max_iter=1000000, f_out=f, g_out=g,
+                                 flags=args.flags)[2]
+
+    for _ in range(args.warmup):
+        r = solve(args.eps, accsk.ACC)
+        log("warmup: It %d err %.3e kernel %.2f ms" % (r["iters"], r["marginal_err"], r["kernel_ms"]))
+    torch.cuda.synchronize()
+    rs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rs.append(solve(args.eps, accsk.ACC))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    ok = all(r["converged"] == 1 for r in rs)
+    solves_per_s = args.steps / dt
+    steps_tot = sum(r["sinkhorn_steps"] for r in rs)
+    kms_tot = sum(r["kernel_ms"] for r in rs)
+    bytes_per_step = n * m * 4  # one read of C per Sinkhorn step (row and column LSE fused)
+    alg_bytes = steps_tot * bytes_per_step
+    achieved = alg_bytes / (kms_tot * 1e-3) / 1e9
+    traffic, tinfo = traffic_from_profile()
+    log("timed: %d solves in %.3f s, It %d, kernel avg %.3f ms, %.1f GB/s algorithmic"
+        % (args.steps, dt, rs[0]["iters"], kms_tot / args.steps, achieved))
+
+    context = {}
+    if args.context:
+        for eps in (1e-2, 1e-3, 1e-4):
+            row = {}
+            for name, meth in (("acc", accsk.ACC), ("sinkhorn", accsk.SINKHORN)):
+                torch.cuda.synchronize()
+                s0 = time.perf_counter()
+                r = solve(eps, meth)
+                torch.cuda.synchronize()
+                s1 = time.perf_counter()
+                row[name] = dict(iters=r["iters"], sinkhorn_steps=r["sinkhorn_steps"],
+                                 fallback_steps=r["fallback_steps"], seconds=round(s1 - s0, 5),
+                                 kernel_ms=round(r["kernel_ms"], 3), converged=r["converged"],
+                                 us_per_step=round(1e3 * r["kernel_ms"] / r["sinkhorn_steps"], 2))
+                log("context eps %g %s: It %d, %.4f s" % (eps, name, r["iters"], s1 - s0))
+            row["speedup_acc_over_sinkhorn"] = round(row["sinkhorn"]["seconds"] / row["acc"]["seconds"], 2)
+            context["eps=%g" % eps] = row
+
+    cpu = None
+    if args.cpu_baseline:
+        from oracle import oracle as O
+        Cd = p["C32"].astype(np.float64)
+        x = np.zeros(m)
+        threads = O.num_threads()
+        log("cpu baseline: oracle Sinkhorn steps on %d threads" % threads)
+        nst = 0
+        c0 = time.perf_counter()
+        while True:
+            st = O.sstep(Cd, args.eps, p["a"], p["b"], x)
+            x = st["S"]
+            nst += 1
+            if time.perf_counter() - c0 > args.cpu_seconds:
+                break
+        c1 = time.perf_counter()
+        per_step = (c1 - c0) / nst
+        gpu_steps = steps_tot / args.steps
+        cpu = {"value": 1.0 / (per_step * gpu_steps), "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": "%d FP64 oracle Sinkhorn steps on the same 8192x8192 input (%.2f s/step), scaled "
+                         "by the %d steps per Acc solve of the GPU run" % (nst, per_step, round(gpu_steps))}
+
+    out = {
+        "metric": "solves/s to L1 marginal err<=1e-6 & % HBM roofline; p50/p99 batched latency",
+        "value": solves_per_s,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "gmm_dense explicit FP32 cost n=m=%d, Acc-Sinkhorn, eps=%g, tol=1e-6"
+                               % (n, args.eps), "n": n, "m": m, "eps": args.eps, "tol": 1e-6,
+                   "method": "acc", "all_converged": ok, "iters": rs[0]["iters"],
+                   "sinkhorn_steps": rs[0]["sinkhorn_steps"], "fallback_steps": rs[0]["fallback_steps"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": kernel_name(n),
+                     "algorithmic_bytes_per_launch": alg_bytes / args.steps,
+                     "avg_launch_ms": kms_tot / args.steps},
+        "cpu_baseline": cpu,
+        "context": context,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -83,9 +83,11 @@ typedef struct {
     int64_t sinkhorn_steps; /* Sinkhorn steps evaluated (= iters + 1) */
     int64_t fallback_steps; /* steps that needed the exact column-max pass */
     double marginal_err;    /* eq:l1tol at the returned iterate, column part (row part is 0 by the exact row solve) */
-    double eot_value;       /* dual value <f,a> + <g,b> - eps*sum P (equals the EOT optimum at convergence) */
+    double eot_value;       /* dual value <f,a> + <g,b> - eps*sum P (equals the EOT optimum at
+                               convergence), FP64-evaluated unless ACCSK_FLAG_NO_COST */
     double transport_cost;  /* <C,P> at the returned potentials (NaN if skipped) */
     double dual_fval;       /* reduced dual objective f(x) = 1 - <u,a> - <x,b> at eps = 1 (Lemma coercivity) */
+    double kernel_ms;       /* duration of the persistent solve kernel (HIP events on `stream`) */
     int32_t converged;      /* 1 if marginal_err < tol */
     int32_t status;         /* accsk_status of the call */
 } accsk_result;

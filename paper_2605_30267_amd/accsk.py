@@ -39,7 +39,8 @@ class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("sinkhorn_steps", ctypes.c_int64),
                 ("fallback_steps", ctypes.c_int64), ("marginal_err", ctypes.c_double),
                 ("eot_value", ctypes.c_double), ("transport_cost", ctypes.c_double),
-                ("dual_fval", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("dual_fval", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("converged", ctypes.c_int32),
                 ("status", ctypes.c_int32)]
 
     def to_dict(self):

@@ -11,9 +11,10 @@ namespace accsk {
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2 = 0.69314718055994530942;
 
-// Every grid barrier spins at most this many sleep rounds (about two seconds)
+// Every grid barrier polls at most this many times, with a sleep between polls
+// (a few seconds in total)
 // before it gives up and reports ACCSK_HIP_ERROR, so a kernel always drains.
-constexpr long kBarrierSpinLimit = 1L << 25;
+constexpr long kBarrierSpinLimit = 1L << 22;
 
 // FP64 transcendentals used off the streaming loops.  Kept out of line so
 // the polynomial constants are not hoisted into registers for the whole
@@ -46,31 +47,124 @@ __device__ __forceinline__ float wave_sumf(float v) {
     return v;
 }
 
-// Grid-wide barrier for a cooperative launch.  `bar` is a zeroed 64-bit
-// counter; `gen` counts the barriers this block has passed (uniform).
-// Returns false if the wait exceeded kBarrierSpinLimit.
+// DPP wave reductions (gfx9 row_shr / row_bcast), result valid in lane 63.
+// Lanes whose DPP source is out of range keep `old`, the identity of the op.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+    const long long vo = __double_as_longlong(old), vv = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)vo, (int)vv, CTRL, ROW_MASK, BANK_MASK, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(vo >> 32), (int)(vv >> 32), CTRL, ROW_MASK, BANK_MASK, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_f32(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROW_MASK,
+                                                      BANK_MASK, false));
+}
+// row_shr:k = 0x110 + k, row_bcast:15 = 0x142, row_bcast:31 = 0x143
+__device__ __forceinline__ double wave_sum_l63(double v) {
+    v += dpp_f64<0x111, 0xf, 0xf>(0.0, v);
+    v += dpp_f64<0x112, 0xf, 0xf>(0.0, v);
+    v += dpp_f64<0x114, 0xf, 0xf>(0.0, v);
+    v += dpp_f64<0x118, 0xf, 0xf>(0.0, v);
+    v += dpp_f64<0x142, 0xa, 0xf>(0.0, v);
+    v += dpp_f64<0x143, 0xc, 0xf>(0.0, v);
+    return v;
+}
+__device__ __forceinline__ float wave_max_l63(float v) {
+    v = fmaxf(v, dpp_f32<0x111, 0xf, 0xf>(v, v));
+    v = fmaxf(v, dpp_f32<0x112, 0xf, 0xf>(v, v));
+    v = fmaxf(v, dpp_f32<0x114, 0xf, 0xf>(v, v));
+    v = fmaxf(v, dpp_f32<0x118, 0xf, 0xf>(v, v));
+    v = fmaxf(v, dpp_f32<0x142, 0xa, 0xf>(v, v));
+    v = fmaxf(v, dpp_f32<0x143, 0xc, 0xf>(v, v));
+    return v;
+}
+
+// Combine NW <= 16 per-wave partials stored in LDS: lane l loads v[l % 16]
+// (identity for l % 16 >= NW), a 16-lane DPP reduction leaves the total in
+// lane 15 of every row, and readlane makes it uniform.  Same order everywhere.
+template <int NW>
+__device__ __forceinline__ double lds_combine_sum(const double *v, int lane) {
+    const int r = lane & 15;
+    double x = r < NW ? v[r] : 0.0;
+    x += dpp_f64<0x111, 0xf, 0xf>(0.0, x);
+    x += dpp_f64<0x112, 0xf, 0xf>(0.0, x);
+    x += dpp_f64<0x114, 0xf, 0xf>(0.0, x);
+    x += dpp_f64<0x118, 0xf, 0xf>(0.0, x);
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, 15);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 15);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int NW>
+__device__ __forceinline__ float lds_combine_max(const float *v, int lane) {
+    const int r = lane & 15;
+    float x = r < NW ? v[r] : -INFINITY;
+    x = fmaxf(x, dpp_f32<0x111, 0xf, 0xf>(x, x));
+    x = fmaxf(x, dpp_f32<0x112, 0xf, 0xf>(x, x));
+    x = fmaxf(x, dpp_f32<0x114, 0xf, 0xf>(x, x));
+    x = fmaxf(x, dpp_f32<0x118, 0xf, 0xf>(x, x));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 15));
+}
+
+// Grid-wide barrier for a cooperative launch.  `bar` points at two zeroed
+// 64-bit words 128 bytes apart: bar[0] counts arrivals, bar[16] holds the
+// number of the last completed barrier.  `gen` counts the barriers this block
+// has passed (uniform).
+// Every wave first drains its own memory operations (s_waitcnt 0), so after
+// the workgroup barrier all of the block's stores have reached L2; one thread
+// then makes them visible device-wide (agent release: L2 write-back) and
+// arrives.  The block whose arrival completes the count publishes `gen` in the
+// flag word; the others poll the flag with relaxed loads (they bypass the
+// per-XCD L2 without invalidating it), away from the counter's cache line.
+// One agent acquire (L2/L1 invalidate) follows.  Returns false if the wait
+// exceeded kBarrierSpinLimit.
 __device__ __forceinline__ bool grid_sync(unsigned long long *bar, unsigned long long &gen,
                                           int *lds_flag) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     gen += 1;
     if (threadIdx.x == 0) {
         const unsigned long long target = gen * (unsigned long long)gridDim.x;
-        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        long spins = 0;
+        unsigned long long *flag = bar + 16;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned long long prev =
+            __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > kBarrierSpinLimit) {
-                ok = 0;
-                break;
+        if (prev + 1 == target) {
+            __hip_atomic_store(flag, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+                __builtin_amdgcn_s_sleep(4);
+                if (++spins > kBarrierSpinLimit) {
+                    ok = 0;
+                    break;
+                }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *lds_flag = ok;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return *lds_flag != 0;
+}
+
+// Stores/loads of data exchanged between blocks between two grid barriers:
+// agent-scope relaxed accesses are coherent across XCDs (written through /
+// read past the per-XCD L2), so the barrier's L2 write-back finds little.
+__device__ __forceinline__ void xstore(float *p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float xload(const float *p) {
+    return __hip_atomic_load(const_cast<float *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xload(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Device-side result record copied back to the host accsk_result.

@@ -43,11 +43,13 @@ struct DenseArgs {
     double *an, *la2, *bn, *lnb;  // normalized marginals, log2 a, log b
     double *u;                    // [n] row potentials (log2 units)
     double *rsum;                 // [n] row sums of exp2(t - max) of the last strip pass
-    double *part;                 // [G*m] per-block column sums
+    float *partf;                 // [G*m] per-block column sums (fast path)
+    double *part;                 // [G*m] per-block column sums (exact pass)
     double *partmax;              // [G*m] per-block column maxima (exact pass)
     double *shat;                 // [m] log b - ell
     double *bscal;                // [2][G][kNS]
-    double *gscal;                // [0] = max_i log2 a_i
+    double *uapart;               // [G] per-block <u,a> at exit
+    double *gscal;                // [0] = max_i log2 a_i, [1] = max_i a_i
     int *status;                  // setup status
     unsigned long long *bar;      // grid barrier counter
     DevResult *res;
@@ -125,6 +127,7 @@ __global__ __launch_bounds__(1024) void setup_marginals(DenseArgs A) {
     __syncthreads();
     if (tid == 0) {
         A.gscal[0] = mx;
+        A.gscal[1] = exp2(mx);
         A.status[0] = (bad & 2) ? ACCSK_NONFINITE : ((bad & 1) ? ACCSK_INVALID_ARG : ACCSK_OK);
     }
 }
@@ -135,9 +138,10 @@ __global__ __launch_bounds__(1024) void setup_marginals(DenseArgs A) {
 // ---------------------------------------------------------------------------
 template <int TPB, int NG, bool VEC>
 struct RowIO {
-    // Loads the thread's NG float4 column groups of one row.  Every load reads
-    // an in-bounds address (clamped), and columns >= m are then replaced by a
-    // +inf cost, so their exponent terms vanish and no branch is needed.
+    // Loads the thread's NG float4 column groups of one row as they are: every
+    // address is clamped into the row, so loads never leave the buffer, and no
+    // value is selected at load time (a select would force an immediate wait
+    // on the prefetch).  Columns >= m are masked by the caller through x = -inf.
     // VEC: m % 4 == 0 and 16-byte aligned rows, one dwordx4 per group.
     static __device__ __forceinline__ void load(const float *__restrict__ row, int m, int tid,
                                                 float4 (&v)[NG]) {
@@ -145,22 +149,12 @@ struct RowIO {
         for (int k = 0; k < NG; k++) {
             const int c0 = 4 * (tid + k * TPB);
             if (VEC) {
-                const int cc = min(c0, m - 4);
-                float4 t = *reinterpret_cast<const float4 *>(row + cc);
-                const bool ok = c0 < m;
-                v[k].x = ok ? t.x : INFINITY;
-                v[k].y = ok ? t.y : INFINITY;
-                v[k].z = ok ? t.z : INFINITY;
-                v[k].w = ok ? t.w : INFINITY;
+                v[k] = *reinterpret_cast<const float4 *>(row + min(c0, m - 4));
             } else {
-                const float t0 = row[min(c0 + 0, m - 1)];
-                const float t1 = row[min(c0 + 1, m - 1)];
-                const float t2 = row[min(c0 + 2, m - 1)];
-                const float t3 = row[min(c0 + 3, m - 1)];
-                v[k].x = (c0 + 0 < m) ? t0 : INFINITY;
-                v[k].y = (c0 + 1 < m) ? t1 : INFINITY;
-                v[k].z = (c0 + 2 < m) ? t2 : INFINITY;
-                v[k].w = (c0 + 3 < m) ? t3 : INFINITY;
+                v[k].x = row[min(c0 + 0, m - 1)];
+                v[k].y = row[min(c0 + 1, m - 1)];
+                v[k].z = row[min(c0 + 2, m - 1)];
+                v[k].w = row[min(c0 + 3, m - 1)];
             }
         }
     }
@@ -174,17 +168,20 @@ __device__ __forceinline__ float f4get(const float4 &v, int e) {
 // xl = x log2 e, wl = w log2 e, so exp(.) becomes exp2(.) with no extra
 // multiply per entry.  Algorithm A2MD is linear in (x, w, S), so it runs
 // unchanged in these units.
-template <int TPB, int NG, bool VEC>
+//
+// Dynamic LDS layout: wl[m] | xl[m] | la2s[rpb] | rowM[rpb] | rowS[rpb] | rowL[rpb]  (doubles).
+// x and w live in LDS between steps (each thread owns the same columns in
+// every phase), so no per-column state is carried in registers across steps.
+template <int TPB, int NG, int RB, bool VEC>
 __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
     constexpr int NW = TPB / 64;
     constexpr int NC = NG * 4;  // columns per thread
-    __shared__ double red_max[NW];
-    __shared__ double red_sum[NW];
+    __shared__ float red_max[RB][NW];
+    __shared__ double red_sum[RB][NW];
     __shared__ double sred[NW][64];
-    __shared__ double xs[64];
     __shared__ double tot[kNS];
     __shared__ int bflag;
-    extern __shared__ double wl_lds[];  // w (log2 units), indexed by column
+    extern __shared__ double dyn_lds[];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int G = gridDim.x, bid = blockIdx.x;
@@ -205,31 +202,64 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
     const long long rpb = (n + G - 1) / G;
     const long long r0 = std::min(n, (long long)bid * rpb);
     const long long r1 = std::min(n, r0 + rpb);
-    const long long nr = r1 - r0;
+    const int nr = (int)(r1 - r0);
     const long long spb = (m + G - 1) / G;
     const long long j0 = std::min(m, (long long)bid * spb);
     const long long j1 = std::min(m, j0 + spb);
 
+    double *wl_lds = dyn_lds;
+    double *xl_lds = dyn_lds + m;
+    double *la2s = dyn_lds + 2 * m;
+    double *rowM = la2s + rpb;
+    double *rowS = rowM + rpb;
+    double *rowL = rowS + rpb;  // shift for the next step (row log-sum-exp, log2 units)
+
     const double kap2 = A.kappa * kLog2e;  // C_ij/eps in log2 units
     const double La2 = A.gscal[0];
 
-    double xl[NC];
-#pragma unroll
-    for (int q = 0; q < NC; q++) xl[q] = 0.0;
 #pragma unroll
     for (int k = 0; k < NG; k++)
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const long long col = 4ll * (tid + k * TPB) + e;
-            if (col < m) wl_lds[col] = 0.0;  // each thread owns its columns of w
+            if (col < m) {  // each thread owns its columns of x and w
+                wl_lds[col] = 0.0;
+                xl_lds[col] = 0.0;
+            }
         }
+    for (int r = tid; r < nr; r += TPB) {
+        la2s[r] = A.la2[r0 + r];
+        rowL[r] = INFINITY;  // unknown: the first step takes the exact row maximum
+    }
+    __syncthreads();
 
     double mu = A.mu0, alpha = dsqrt(2.0 * A.mu0);
     long long mstage = A.m0, kin = 0, it = 0, steps = 0, fallbacks = 0;
     bool first = true;
     unsigned long long gen = 0;
     int status = ACCSK_OK;
-    double err = 0.0, eot = 0.0, fval = 0.0;
+    double err = 0.0, eot = 0.0, fval = 0.0, last_mass = 0.0, last_xb2 = 0.0;
+
+    // u_i log2 e = log2 a_i - (M_i + log2 S_i) for this block's rows, from the
+    // shift and sum of the last strip pass (needed by the exact column pass and
+    // at exit only).  Returns this block's sum_i a_i u_i (log2 units) in tid 0.
+    auto materialize_u = [&]() -> double {
+        double ua = 0.0;
+        for (int r = tid; r < nr; r += TPB) {
+            const double u2 = la2s[r] - (rowM[r] + dlog2(rowS[r]));
+            A.u[r0 + r] = u2;
+            ua += A.an[r0 + r] * u2;
+        }
+        ua = wave_sum(ua);
+        __syncthreads();
+        if (lane == 0) sred[wid][0] = ua;
+        __syncthreads();
+        double tot_ua = 0.0;
+        if (tid == 0)
+            for (int q = 0; q < NW; q++) tot_ua += sred[q][0];
+        __syncthreads();
+        return tot_ua;
+    };
 
     for (long long step = 0;; step++) {
         const int par = (int)(step & 1);
@@ -237,13 +267,13 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
         // addresses derived from them are recomputed each step instead of being
         // hoisted out of the step loop and kept live (which spills registers).
         DenseArgs L = A;
+        opaque_ptr(L.partf);
         opaque_ptr(L.part);
         opaque_ptr(L.partmax);
         opaque_ptr(L.shat);
         opaque_ptr(L.bn);
         opaque_ptr(L.lnb);
         opaque_ptr(L.u);
-        opaque_ptr(L.rsum);
         opaque_ptr(L.la2);
         opaque_ptr(L.an);
         opaque_ptr(L.bscal);
@@ -251,91 +281,134 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
         opaque_int(ctid);
         double *bs = L.bscal + (size_t)par * G * kNS;
         // ---------------- strip pass ----------------
+        double xl[NC];  // this thread's x (log2 units); -inf masks columns >= m
+#pragma unroll
+        for (int k = 0; k < NG; k++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int col = 4 * (ctid + k * TPB) + e;
+                xl[k * 4 + e] = (col < m) ? xl_lds[col] : -INFINITY;
+            }
         double colacc[NC];
 #pragma unroll
         for (int q = 0; q < NC; q++) colacc[q] = 0.0;
-        double ua = 0.0;
         const bool rev = A.serpentine && (step & 1);
+        const int nbat = (nr + RB - 1) / RB;
 
-        float4 nxt[NG];
-        if (nr > 0) {
-            const long long i = rev ? r1 - 1 : r0;
-            RowIO<TPB, NG, VEC>::load(A.C + i * A.ldc, (int)m, ctid, nxt);
-        }
-        for (long long rr = 0; rr < nr; rr++) {
-            const long long i = rev ? r1 - 1 - rr : r0 + rr;
-            float4 cur[NG];
+        // local row index of row q of batch bb (serpentine order), clamped for loading
+        auto rloc = [&](int bb, int q) {
+            const int r = bb * RB + q;
+            const int rc = r < nr ? r : nr - 1;
+            return rev ? nr - 1 - rc : rc;
+        };
+        // One batch of RB rows.  Row side: shift M_i, e_ij = exp2(t_ij - M_i),
+        // S_i = sum_j e_ij (block reduction).  The shift is the row's log-sum-exp
+        // from the previous step (kept in LDS); if the sum leaves [2^-40, 2^40]
+        // (first step, or x moved a lot) the batch is redone with the exact row
+        // maximum.  Column side: P_ij / max a = e_ij * 2^(log2 a_i - La2) / S_i,
+        // one FMA per entry.
+        auto batch = [&](int bb, const float4 (&cur)[RB][NG]) {
+            double t[RB][NC];
+            double M[RB];
+            bool exact_rows = false;
 #pragma unroll
-            for (int k = 0; k < NG; k++) cur[k] = nxt[k];
-            if (rr + 1 < nr) {
-                const long long inext = rev ? i - 1 : i + 1;
-                RowIO<TPB, NG, VEC>::load(A.C + inext * A.ldc, (int)m, ctid, nxt);
+            for (int q = 0; q < RB; q++) {
+                M[q] = rowL[rloc(bb, q)];
+                exact_rows |= !(M[q] < INFINITY);
+#pragma unroll
+                for (int k = 0; k < NG; k++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        t[q][k * 4 + e] = fma(-(double)f4get(cur[q][k], e), kap2, xl[k * 4 + e]);
             }
-            double t[NC];
-            double mloc = -INFINITY;
+            float ev[RB][NC];
+            double S[RB];
+            auto row_sums = [&]() {
 #pragma unroll
-            for (int k = 0; k < NG; k++)
+                for (int q = 0; q < RB; q++) {
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const double tv = fma(-(double)f4get(cur[k], e), kap2, xl[k * 4 + e]);
-                    t[k * 4 + e] = tv;
-                    mloc = fmax(mloc, tv);
+                    for (int c = 0; c < NC; c++) ev[q][c] = __builtin_amdgcn_exp2f((float)(t[q][c] - M[q]));
+                    // FP32 pairwise within the thread, FP64 across lanes and waves
+                    float pv[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; c++) pv[c] = ev[q][c];
+#pragma unroll
+                    for (int h = 1; h < NC; h <<= 1)
+#pragma unroll
+                        for (int c = 0; c + h < NC; c += 2 * h) pv[c] += pv[c + h];
+                    const double sw = wave_sum_l63((double)pv[0]);
+                    if (lane == 63) red_sum[q][wid] = sw;
                 }
-            mloc = wave_max(mloc);
-            if (lane == 0) red_max[wid] = mloc;
-            __syncthreads();
-            double M = red_max[0];
+                __syncthreads();
 #pragma unroll
-            for (int q = 1; q < NW; q++) M = fmax(M, red_max[q]);
-            // row sum of exp2(t - M): FP32 terms, pairwise within the thread
-            float ev[NC];
+                for (int q = 0; q < RB; q++) S[q] = lds_combine_sum<NW>(red_sum[q], lane);
+            };
+            if (!exact_rows) {
+                row_sums();
 #pragma unroll
-            for (int q = 0; q < NC; q++) ev[q] = __builtin_amdgcn_exp2f((float)(t[q] - M));
+                for (int q = 0; q < RB; q++) exact_rows |= !(S[q] >= 0x1p-40 && S[q] <= 0x1p40);
+                __syncthreads();  // red_sum is reused below
+            }
+            if (exact_rows) {  // block-uniform
 #pragma unroll
-            for (int h = 1; h < NC; h <<= 1)
+                for (int q = 0; q < RB; q++) {
+                    double mloc = -INFINITY;
 #pragma unroll
-                for (int q = 0; q + h < NC; q += 2 * h) ev[q] += ev[q + h];
-            double sd = wave_sum((double)ev[0]);
-            if (lane == 0) red_sum[wid] = sd;
-            __syncthreads();
-            double S = red_sum[0];
+                    for (int c = 0; c < NC; c++) mloc = fmax(mloc, t[q][c]);
+                    // the shift only needs to be near the row maximum: reduce it in FP32
+                    const float mw = wave_max_l63((float)mloc);
+                    if (lane == 63) red_max[q][wid] = mw;
+                }
+                __syncthreads();
 #pragma unroll
-            for (int q = 1; q < NW; q++) S += red_sum[q];
-            // P_ij / max a = exp2(t_ij - M + log2 a_i - La2) / S   (u_i from eq:u-update)
-            const double sh2 = L.la2[i] - La2 - M;
-            const float invS = __builtin_amdgcn_rcpf((float)S);
+                for (int q = 0; q < RB; q++) M[q] = (double)lds_combine_max<NW>(red_max[q], lane);
+                row_sums();
+            }
+            float cterm[NC];
 #pragma unroll
-            for (int q = 0; q < NC; q++)
-                colacc[q] += (double)(__builtin_amdgcn_exp2f((float)(t[q] + sh2)) * invS);
-            if (tid == 0) {
-                L.u[i] = M;  // row max and row sum; u_i is formed after the loop
-                L.rsum[i] = S;
+            for (int c = 0; c < NC; c++) cterm[c] = 0.f;
+#pragma unroll
+            for (int q = 0; q < RB; q++) {
+                const int rl = rloc(bb, q);
+                const bool rv = bb * RB + q < nr;
+                const float rfac = rv ? __builtin_amdgcn_exp2f((float)(la2s[rl] - La2)) *
+                                            __builtin_amdgcn_rcpf((float)S[q])
+                                      : 0.f;
+#pragma unroll
+                for (int c = 0; c < NC; c++) cterm[c] = fmaf(ev[q][c], rfac, cterm[c]);
+                if (tid == 0 && rv) {
+                    rowM[rl] = M[q];
+                    rowS[rl] = S[q];
+                    rowL[rl] = M[q] + (double)__builtin_amdgcn_logf((float)S[q]);  // next step's shift
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; c++) colacc[c] += (double)cterm[c];
+        };
+        // ping-pong prefetch buffers: batch bb computes on one while bb+1 loads into the other
+        float4 bufA[RB][NG], bufB[RB][NG];
+        auto load_batch = [&](int bb, float4 (&dst)[RB][NG]) {
+#pragma unroll
+            for (int q = 0; q < RB; q++)
+                RowIO<TPB, NG, VEC>::load(A.C + (r0 + rloc(bb, q)) * A.ldc, (int)m, ctid, dst[q]);
+        };
+        if (nbat > 0) load_batch(0, bufA);
+        for (int bb = 0; bb < nbat; bb += 2) {
+            if (bb + 1 < nbat) load_batch(bb + 1, bufB);
+            batch(bb, bufA);
+            if (bb + 1 < nbat) {
+                if (bb + 2 < nbat) load_batch(bb + 2, bufA);
+                batch(bb + 1, bufB);
             }
         }
         __syncthreads();
-        // u_i log2 e = log2 a_i - (M_i + log2 S_i), off the streaming loop
-        for (long long i = r0 + tid; i < r1; i += TPB) {
-            const double u2 = L.la2[i] - (L.u[i] + dlog2(L.rsum[i]));
-            L.u[i] = u2;
-            ua += L.an[i] * u2;
-        }
-        ua = wave_sum(ua);
-        if (lane == 0) sred[wid][0] = ua;
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-#pragma unroll
-            for (int q = 0; q < NW; q++) s += sred[q][0];
-            ua = s;
-        }
 #pragma unroll
         for (int k = 0; k < NG; k++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const long long col = 4ll * (ctid + k * TPB) + e;
-                if (col < m) L.part[(size_t)bid * m + col] = colacc[k * 4 + e];
+                if (col < m) xstore(&L.partf[(size_t)bid * m + col], (float)colacc[k * 4 + e]);
             }
-        if (tid == 0) bs[(size_t)bid * kNS + 0] = ua;
         if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
 
         // ---------------- slice combine ----------------
@@ -343,6 +416,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
         for (int pass = 0; pass < 2; pass++) {
             if (pass == 1) {
                 if (!exact) break;
+                (void)materialize_u();
                 // Exact column pass: running maximum per column over this block's rows.
                 double cm[NC];
                 float cs[NC];
@@ -373,53 +447,59 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
                     for (int e = 0; e < 4; e++) {
                         const long long col = 4ll * (ctid + k * TPB) + e;
                         if (col < m) {
-                            L.part[(size_t)bid * m + col] = (double)cs[k * 4 + e];
-                            L.partmax[(size_t)bid * m + col] = cm[k * 4 + e];
+                            xstore(&L.part[(size_t)bid * m + col], (double)cs[k * 4 + e]);
+                            xstore(&L.partmax[(size_t)bid * m + col], cm[k * 4 + e]);
                         }
                     }
                 if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
                 fallbacks++;
             }
             double aS = 0.0, aE = 0.0, aC = 0.0, aXB = 0.0, aFB = 0.0;
-            for (long long cb = j0; cb < j1; cb += 64) {
-                // stage x of this 64-column chunk in LDS
-#pragma unroll
-                for (int k = 0; k < NG; k++)
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const long long col = 4ll * (ctid + k * TPB) + e;
-                        if (col >= cb && col < cb + 64 && col < j1) xs[col - cb] = xl[k * 4 + e];
-                    }
-                const long long j = cb + lane;
+            // columns of the slice in chunks of CW; thread t sums the partials of
+            // blocks b = grp, grp + NGRP, ... for column cb + (t % CW)
+            constexpr int CW = TPB >= 64 ? 32 : TPB;
+            constexpr int NGRP = TPB / CW;
+            double *sflat = &sred[0][0];
+            const int coff = tid % CW, grp = tid / CW;
+            for (long long cb = j0; cb < j1; cb += CW) {
+                const long long j = cb + coff;
                 double acc = 0.0, pm = -INFINITY;
-                if (j < j1) {
-                    if (pass == 0) {
-                        for (int b = wid; b < G; b += NW) acc += L.part[(size_t)b * m + j];
-                    } else {
-                        for (int b = 0; b < G; b++) pm = fmax(pm, L.partmax[(size_t)b * m + j]);
-                        for (int b = wid; b < G; b += NW) {
-                            const double mb = L.partmax[(size_t)b * m + j];
-                            acc += L.part[(size_t)b * m + j] * dexp2(mb - pm);
-                        }
-                    }
-                }
-                sred[wid][lane] = acc;
-                __syncthreads();
-                if (wid == 0 && j < j1) {
-                    double s = 0.0;
+                if (pass == 0) {
+                    if (j < j1)
+                        for (int b = grp; b < G; b += NGRP) acc += (double)L.partf[(size_t)b * m + j];
+                } else {
+                    if (j < j1)
+                        for (int b = grp; b < G; b += NGRP) pm = fmax(pm, L.partmax[(size_t)b * m + j]);
+                    sflat[tid] = pm;
+                    __syncthreads();
+                    pm = -INFINITY;
 #pragma unroll
-                    for (int q = 0; q < NW; q++) s += sred[q][lane];
-                    const double xj = xs[lane];
-                    double lc2;  // log2 c_j, c_j = column sum of P at (u(x), x)
+                    for (int q = 0; q < NGRP; q++) pm = fmax(pm, sflat[q * CW + coff]);
+                    __syncthreads();
+                    if (j < j1)
+                        for (int b = grp; b < G; b += NGRP) {
+                            const double mb = L.partmax[(size_t)b * m + j];
+                            if (mb > -INFINITY) acc += L.part[(size_t)b * m + j] * dexp2(mb - pm);
+                        }
+                }
+                sflat[tid] = acc;
+                __syncthreads();
+                if (tid < CW && j < j1) {
+                    double sc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NGRP; q++) sc += sflat[q * CW + tid];
+                    const double xj = xl_lds[j];
+                    double lc2, c;  // log2 c_j and c_j, c_j = column sum of P at (u(x), x)
                     if (pass == 0) {
-                        lc2 = La2 + dlog2(s);
-                        if (s < 0x1p-64) aFB += 1.0;
+                        lc2 = La2 + dlog2(sc);
+                        c = sc * A.gscal[1];
+                        if (sc < 0x1p-64) aFB += 1.0;
                     } else {
-                        lc2 = pm + dlog2(s) + xj;
+                        lc2 = pm + dlog2(sc) + xj;
+                        c = dexp2(lc2);
                     }
-                    const double c = dexp2(lc2);
                     const double sh = L.lnb[j] * kLog2e - lc2 + xj;  // (log b_j - ell_j) log2 e
-                    L.shat[j] = sh;
+                    xstore(&L.shat[j], sh);
                     aS += sh;
                     aE += fabs(c - L.bn[j]);
                     aC += c;
@@ -435,11 +515,11 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
                 aFB = wave_sum(aFB);
                 if (lane == 0) {
                     double *p = bs + (size_t)bid * kNS;
-                    p[1] = aS;
-                    p[2] = aE;
-                    p[3] = aC;
-                    p[4] = aXB;
-                    p[5] = aFB;
+                    xstore(&p[1], aS);
+                    xstore(&p[2], aE);
+                    xstore(&p[3], aC);
+                    xstore(&p[4], aXB);
+                    xstore(&p[5], aFB);
                 }
             }
             if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
@@ -460,9 +540,8 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
         err = tot[2];
         const double mean = tot[1] / (double)m;
         const double mass = tot[3];
-        const double ua_ln = tot[0] * kLn2, xb_ln = tot[4] * kLn2;
-        fval = 1.0 - ua_ln - xb_ln;               // f(x) = 1 - <u,a> - <x,b>
-        eot = A.eps * (ua_ln + xb_ln - mass);    // <f,a> + <g,b> - eps sum P
+        last_mass = mass;
+        last_xb2 = tot[4];
         steps++;
         if (!isfinite(err)) {
             status = (steps == 1) ? ACCSK_NONFINITE : ACCSK_DIVERGED;
@@ -476,7 +555,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     const long long col = 4ll * (ctid + k * TPB) + e;
-                    xl[k * 4 + e] = (col < m) ? L.shat[col] - mean : 0.0;
+                    if (col < m) xl_lds[col] = L.shat[col] - mean;
                 }
             it++;
         } else {
@@ -497,7 +576,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
                         const long long col = 4ll * (ctid + k * TPB) + e;
-                        if (col < m) wl_lds[col] = (wl_lds[col] + c2 * xl[k * 4 + e] + 2.0 * S[k * 4 + e]) * inv;
+                        if (col < m) wl_lds[col] = (wl_lds[col] + c2 * xl_lds[col] + 2.0 * S[k * 4 + e]) * inv;
                     }
                 it++;
                 kin++;
@@ -528,13 +607,15 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     const long long col = 4ll * (ctid + k * TPB) + e;
-                    xl[k * 4 + e] = (col < m) ? (wl_lds[col] + S[k * 4 + e]) * inv : 0.0;
+                    if (col < m) xl_lds[col] = (wl_lds[col] + S[k * 4 + e]) * inv;
                 }
         }
     }
 
     // ---------------- outputs ----------------
     if (status == ACCSK_OK || status == ACCSK_DIVERGED) {
+        const double ua_blk = materialize_u();  // u at the returned iterate, this block's rows
+        if (tid == 0) xstore(&A.uapart[bid], ua_blk);
         for (long long i = r0 + tid; i < r1; i += TPB) A.f_out[i] = A.eps * kLn2 * A.u[i];
         if (bid == 0) {
 #pragma unroll
@@ -542,8 +623,16 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     const long long col = 4ll * (tid + k * TPB) + e;
-                    if (col < m) A.g_out[col] = A.eps * kLn2 * xl[k * 4 + e];
+                    if (col < m) A.g_out[col] = A.eps * kLn2 * xl_lds[col];
                 }
+        }
+        if (!grid_sync(A.bar, gen, &bflag)) status = ACCSK_HIP_ERROR;
+        if (bid == 0 && tid == 0 && status != ACCSK_HIP_ERROR) {
+            double ua2 = 0.0;
+            for (int b = 0; b < G; b++) ua2 += A.uapart[b];
+            const double ua_ln = ua2 * kLn2, xb_ln = last_xb2 * kLn2;
+            fval = 1.0 - ua_ln - xb_ln;               // f(x) = 1 - <u,a> - <x,b>
+            eot = A.eps * (ua_ln + xb_ln - last_mass);  // <f,a> + <g,b> - eps sum P
         }
     }
     if (bid == 0 && tid == 0) {
@@ -702,15 +791,20 @@ struct Workspace {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-template <int TPB, int NG, bool VEC>
+template <int TPB, int NG, int RB, bool VEC>
 accsk_status launch_dense(DenseArgs &A, hipStream_t s, int num_cu, void *&ws, size_t &ws_bytes,
-                          int &grid_out) {
+                          int &grid_out, hipEvent_t ev0, hipEvent_t ev1) {
     int occ = 0;
-    const size_t dyn = (size_t)A.m * sizeof(double);
-    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, VEC>, TPB, dyn));
+    // dynamic LDS: w[m] and three per-row arrays for this block's rows
+    const long long G_est = std::min<long long>((long long)num_cu, std::max<long long>(1, A.n));
+    const long long rpb_max = (A.n + G_est - 1) / G_est;
+    const size_t dyn = (size_t)(2 * A.m + 4 * rpb_max) * sizeof(double);
+    if (dyn > 150 * 1024) return ACCSK_SHAPE;
+    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC>, TPB, dyn));
     if (occ < 1) return ACCSK_SHAPE;
-    long long G = (long long)occ * num_cu;
-    G = std::min<long long>(G, std::max<long long>(1, A.n));
+    // at most two blocks per CU: the grid barrier's cost grows with the block count
+    long long G = (long long)std::min(occ, 2) * num_cu;
+    G = std::min<long long>(G, std::max<long long>(1, A.n));  // >= G_est, so rows per block <= rpb_max
     // workspace
     const size_t n = A.n, m = A.m;
     size_t off = 0;
@@ -721,12 +815,14 @@ accsk_status launch_dense(DenseArgs &A, hipStream_t s, int num_cu, void *&ws, si
     const size_t o_bn = off; off = align_up(off + m * 8);
     const size_t o_lnb = off; off = align_up(off + m * 8);
     const size_t o_shat = off; off = align_up(off + m * 8);
+    const size_t o_partf = off; off = align_up(off + (size_t)G * m * 4);
     const size_t o_part = off; off = align_up(off + (size_t)G * m * 8);
     const size_t o_pmax = off; off = align_up(off + (size_t)G * m * 8);
     const size_t o_bscal = off; off = align_up(off + 2 * (size_t)G * kNS * 8);
+    const size_t o_uap = off; off = align_up(off + (size_t)G * 8);
     const size_t o_gscal = off; off = align_up(off + 8 * 8);
     const size_t o_stat = off; off = align_up(off + 64);
-    const size_t o_bar = off; off = align_up(off + 64);
+    const size_t o_bar = off; off = align_up(off + 256);
     const size_t o_res = off; off = align_up(off + sizeof(DevResult));
     void *base = nullptr;
     if (hipMallocAsync(&base, off, s) != hipSuccess) return ACCSK_OOM;
@@ -738,38 +834,43 @@ accsk_status launch_dense(DenseArgs &A, hipStream_t s, int num_cu, void *&ws, si
     A.bn = (double *)(p + o_bn);
     A.lnb = (double *)(p + o_lnb);
     A.shat = (double *)(p + o_shat);
+    A.partf = (float *)(p + o_partf);
     A.part = (double *)(p + o_part);
     A.partmax = (double *)(p + o_pmax);
     A.bscal = (double *)(p + o_bscal);
+    A.uapart = (double *)(p + o_uap);
     A.gscal = (double *)(p + o_gscal);
     A.status = (int *)(p + o_stat);
     A.bar = (unsigned long long *)(p + o_bar);
     A.res = (DevResult *)(p + o_res);
     ws = base;
     ws_bytes = off;
-    hipError_t e = hipMemsetAsync(p + o_bar, 0, 64, s);
+    hipError_t e = hipMemsetAsync(p + o_bar, 0, 256, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(setup_marginals, dim3(1), dim3(1024), 0, s, A);
         e = hipGetLastError();
     }
+    if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
     if (e == hipSuccess) {
         void *args[] = {&A};
-        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, VEC>, dim3((unsigned)G), dim3(TPB),
+        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, RB, VEC>, dim3((unsigned)G), dim3(TPB),
                                        args, dyn, s);
     }
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     grid_out = (int)G;
     return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
 }
 
 template <bool VEC>
-accsk_status launch_dense_cfg(DenseArgs &A, hipStream_t s, int cu, void *&ws, size_t &ws_bytes, int &G) {
+accsk_status launch_dense_cfg(DenseArgs &A, hipStream_t s, int cu, void *&ws, size_t &ws_bytes, int &G,
+                              hipEvent_t ev0, hipEvent_t ev1) {
     const long long m = A.m;
-    if (m <= 256) return launch_dense<64, 1, VEC>(A, s, cu, ws, ws_bytes, G);
-    if (m <= 512) return launch_dense<128, 1, VEC>(A, s, cu, ws, ws_bytes, G);
-    if (m <= 1024) return launch_dense<256, 1, VEC>(A, s, cu, ws, ws_bytes, G);
-    if (m <= 2048) return launch_dense<512, 1, VEC>(A, s, cu, ws, ws_bytes, G);
-    if (m <= 4096) return launch_dense<512, 2, VEC>(A, s, cu, ws, ws_bytes, G);
-    return launch_dense<512, 4, VEC>(A, s, cu, ws, ws_bytes, G);
+    if (m <= 256) return launch_dense<64, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
+    if (m <= 512) return launch_dense<128, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
+    if (m <= 1024) return launch_dense<256, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
+    if (m <= 2048) return launch_dense<512, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
+    if (m <= 4096) return launch_dense<1024, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
+    return launch_dense<1024, 2, 1, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
 }
 
 int device_cu_count() {
@@ -796,7 +897,7 @@ accsk_status run_eval(const float *C, long long n, long long m, long long ldc, d
     hipLaunchKernelGGL(eval_final, dim3(1), dim3(1024), 0, s, n, m, G, eps, a, b, f, g, rowscal, colerr,
                        out_dev, res);
     hipError_t e = hipGetLastError();
-    hipFreeAsync(buf, s);
+    (void)hipFreeAsync(buf, s);
     return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
 }
 
@@ -852,10 +953,18 @@ extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, 
     int G = 0;
     accsk_status st;
     const bool vec = (ldc % 4) == 0 && (m % 4) == 0 && (((uintptr_t)C) & 15) == 0;
-    if (vec) st = launch_dense_cfg<true>(A, s, cu, ws, ws_bytes, G);
-    else st = launch_dense_cfg<false>(A, s, cu, ws, ws_bytes, G);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+    if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+    if (vec) st = launch_dense_cfg<true>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
+    else st = launch_dense_cfg<false>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
+    auto drop_events = [&]() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    };
     if (st != ACCSK_OK) {
-        if (ws) hipFreeAsync(ws, s);
+        if (ws) (void)hipFreeAsync(ws, s);
+        drop_events();
         return st;
     }
     double *out_dev = A.gscal + 1;  // 5 slots after max log2 a
@@ -863,15 +972,20 @@ extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, 
         // <C,P> and the dual value at the returned potentials, FP64, with normalized marginals
         st = run_eval(C, n, m, ldc, p->eps, A.an, A.bn, f_out, g_out, out_dev, A.res, s);
         if (st != ACCSK_OK) {
-            hipFreeAsync(ws, s);
+            (void)hipFreeAsync(ws, s);
+            drop_events();
             return st;
         }
     }
     DevResult r;
     hipError_t e = hipMemcpyAsync(&r, A.res, sizeof(DevResult), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFreeAsync(ws, s);
+    (void)hipFreeAsync(ws, s);
+    float kms = -1.f;
+    if (e == hipSuccess && ev0 && ev1 && hipEventElapsedTime(&kms, ev0, ev1) != hipSuccess) kms = -1.f;
+    drop_events();
     if (e != hipSuccess) return ACCSK_HIP_ERROR;
+    res->kernel_ms = kms;
     res->iters = r.iters;
     res->sinkhorn_steps = r.steps;
     res->fallback_steps = r.fallback;
@@ -921,6 +1035,6 @@ extern "C" accsk_status accsk_eval_dense(const float *C, int64_t n, int64_t m, i
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = ACCSK_HIP_ERROR;
     }
-    hipFreeAsync(dout, s);
+    (void)hipFreeAsync(dout, s);
     return st;
 }
