@@ -402,13 +402,23 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
             }
         }
         __syncthreads();
+        // per-block column sums: FP64-accumulated, rounded once to FP32, stored as
+        // full float4 groups (the barrier's L2 write-back flushes whole lines)
 #pragma unroll
-        for (int k = 0; k < NG; k++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const long long col = 4ll * (ctid + k * TPB) + e;
-                if (col < m) xstore(&L.partf[(size_t)bid * m + col], (float)colacc[k * 4 + e]);
+        for (int k = 0; k < NG; k++) {
+            const int c0 = 4 * (ctid + k * TPB);
+            float *dst = L.partf + (size_t)bid * m + c0;
+            const float4 v = make_float4((float)colacc[k * 4 + 0], (float)colacc[k * 4 + 1],
+                                         (float)colacc[k * 4 + 2], (float)colacc[k * 4 + 3]);
+            if (VEC && c0 + 3 < m) {
+                *reinterpret_cast<float4 *>(dst) = v;
+            } else {
+                if (c0 + 0 < m) dst[0] = v.x;
+                if (c0 + 1 < m) dst[1] = v.y;
+                if (c0 + 2 < m) dst[2] = v.z;
+                if (c0 + 3 < m) dst[3] = v.w;
             }
+        }
         if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
 
         // ---------------- slice combine ----------------
@@ -447,8 +457,8 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
                     for (int e = 0; e < 4; e++) {
                         const long long col = 4ll * (ctid + k * TPB) + e;
                         if (col < m) {
-                            xstore(&L.part[(size_t)bid * m + col], (double)cs[k * 4 + e]);
-                            xstore(&L.partmax[(size_t)bid * m + col], cm[k * 4 + e]);
+                            L.part[(size_t)bid * m + col] = (double)cs[k * 4 + e];
+                            L.partmax[(size_t)bid * m + col] = cm[k * 4 + e];
                         }
                     }
                 if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
@@ -499,7 +509,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
                         c = dexp2(lc2);
                     }
                     const double sh = L.lnb[j] * kLog2e - lc2 + xj;  // (log b_j - ell_j) log2 e
-                    xstore(&L.shat[j], sh);
+                    L.shat[j] = sh;
                     aS += sh;
                     aE += fabs(c - L.bn[j]);
                     aC += c;
