@@ -132,6 +132,31 @@ accsk_status accsk_eval_dense(const float *C, int64_t n, int64_t m, int64_t ldc,
                               const double *a, const double *b, const double *f, const double *g,
                               double *out, void *stream);
 
+/* One problem of a batch (explicit FP32 cost).  All pointers are device
+ * pointers; C is n x m row-major with leading dimension ldc >= m. */
+typedef struct {
+    const float *C;
+    int64_t n, m, ldc;
+    const double *a, *b; /* marginals, > 0, normalized inside */
+    double *f, *g;       /* outputs: potentials in cost units */
+    double eps;          /* regularization of this problem, > 0 */
+} accsk_problem;
+
+/*
+ * Batched solve of independent dense problems (Sec. 2 dual, Sec. 4
+ * algorithms, stopping rule eq:l1tol per problem).  One workgroup owns each
+ * problem: its iterate, extrapolation state and homotopy counters stay in
+ * on-chip memory, no grid-wide barrier is used, and every problem stops on its
+ * own test.  probs: host array of `count` descriptors (the library copies it);
+ * res: host array of `count` results.  p supplies method, tol, max_iter,
+ * mu0, m0, w_rule and flags (p->eps is ignored; each problem has its own).
+ * Limits per problem: 1 <= m <= 1024, 1 <= n <= 4096.
+ * Returns ACCSK_OK if every problem converged, ACCSK_NOT_CONVERGED if some hit
+ * max_iter, otherwise the first error (per-problem status in res[k].status).
+ */
+accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                               accsk_result *res, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,12 @@ class Result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_void_p), ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("ldc", ctypes.c_int64),
+                ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("f", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("eps", ctypes.c_double)]
+
+
 _lib = None
 _lock = threading.Lock()
 _vp = ctypes.c_void_p
@@ -78,6 +84,9 @@ def lib():
         L.accsk_eval_dense.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _vp, _vp,
                                        ctypes.POINTER(ctypes.c_double), _vp]
         L.accsk_eval_dense.restype = ctypes.c_int
+        L.accsk_solve_batch.argtypes = [ctypes.POINTER(Problem), _i64, ctypes.POINTER(Params),
+                                        ctypes.POINTER(Result), _vp]
+        L.accsk_solve_batch.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -150,6 +159,42 @@ def solve_dense(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m
     d = r.to_dict()
     d["status"] = st
     return f_out, g_out, d
+
+
+def solve_batch(problems, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=None, w_rule=None, flags=0,
+                raise_on_error=True):
+    """Solve independent dense problems, one workgroup each.
+
+    problems: list of (C float32 [n,m] device, a float64 [n], b float64 [m], eps).
+    Returns (list of (f, g), list of result dicts, batch status).
+    """
+    import torch
+    k = len(problems)
+    arr = (Problem * k)()
+    outs = []
+    keep = []
+    for idx, (C, a, b, eps) in enumerate(problems):
+        _check_dev(C, torch.float32, "C", 2)
+        _check_dev(a, torch.float64, "a", 1)
+        _check_dev(b, torch.float64, "b", 1)
+        if C.stride(1) != 1:
+            raise ValueError("C must have unit column stride")
+        n, m = C.shape
+        a = a.contiguous()
+        b = b.contiguous()
+        f = torch.empty(n, dtype=torch.float64, device=C.device)
+        g = torch.empty(m, dtype=torch.float64, device=C.device)
+        keep += [a, b]
+        outs.append((f, g))
+        arr[idx] = Problem(C.data_ptr(), n, m, C.stride(0), a.data_ptr(), b.data_ptr(), f.data_ptr(),
+                           g.data_ptr(), float(eps))
+    p = default_params(method=method, tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0, w_rule=w_rule,
+                       flags=int(flags))
+    res = (Result * k)()
+    st = lib().accsk_solve_batch(arr, k, ctypes.byref(p), res, _stream_ptr())
+    if raise_on_error and st not in (OK, NOT_CONVERGED):
+        raise AccskError(st, "accsk_solve_batch")
+    return outs, [r.to_dict() for r in res], st
 
 
 def plan_dense(C, f, g, eps, row0=0, rows=None, out=None):

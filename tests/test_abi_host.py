@@ -1,0 +1,90 @@
+"""Host-side checks of the C-ABI (no GPU needed).
+
+* libaccsk.so loads and exports every entry point declared in include/accsk.h.
+* Argument validation happens on the host before any device work: invalid
+  scalars and shapes return the documented status with null device pointers.
+* The ctypes structures match the header's field lists.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2605_30267_amd import accsk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(accsk.LIB_PATH):
+        pytest.skip("libaccsk.so not built")
+    return accsk.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = accsk.symbols_declared()
+    assert "accsk_solve_dense" in names and "accsk_solve_batch" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_fields_match_header():
+    text = open(os.path.join(ROOT, "include", "accsk.h")).read()
+
+    def fields(struct_name):
+        body = re.search(r"typedef struct \{(.*?)\} %s;" % struct_name, text, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        out = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            for part in decl.split(","):
+                out.append(part.strip().split()[-1].lstrip("*"))
+        return out
+
+    assert fields("accsk_params") == [f for f, _ in accsk.Params._fields_]
+    assert fields("accsk_result") == [f for f, _ in accsk.Result._fields_]
+    assert fields("accsk_problem") == [f for f, _ in accsk.Problem._fields_]
+
+
+def test_defaults(lib):
+    p = accsk.default_params()
+    assert p.method == accsk.ACC and p.w_rule == accsk.W_Y_CONTINUOUS
+    assert 0 < p.mu0 < 1 and p.m0 >= 1 and p.tol == 1e-6
+    assert lib.accsk_status_string(accsk.SHAPE).decode().startswith("unsupported")
+
+
+def _solve_dense_raw(lib, n, m, ldc, eps=1e-2, tol=1e-6, method=1, mu0=0.25, m0=5, ptr=1):
+    p = accsk.default_params(eps=eps, tol=tol, method=method, mu0=mu0, m0=m0)
+    r = accsk.Result()
+    fake = ctypes.c_void_p(ptr)
+    return lib.accsk_solve_dense(fake, n, m, ldc, fake, fake, ctypes.byref(p), fake, fake, ctypes.byref(r), None)
+
+
+def test_host_validation_dense(lib):
+    assert _solve_dense_raw(lib, 4, 4, 4, eps=-1.0) == accsk.INVALID_ARG
+    assert _solve_dense_raw(lib, 4, 4, 4, eps=float("nan")) == accsk.INVALID_ARG
+    assert _solve_dense_raw(lib, 4, 4, 4, tol=0.0) == accsk.INVALID_ARG
+    assert _solve_dense_raw(lib, 4, 4, 4, mu0=1.0) == accsk.INVALID_ARG
+    assert _solve_dense_raw(lib, 4, 4, 4, m0=0) == accsk.INVALID_ARG
+    assert _solve_dense_raw(lib, 4, 4, 4, method=7) == accsk.INVALID_ARG
+    assert _solve_dense_raw(lib, 0, 4, 4) == accsk.SHAPE
+    assert _solve_dense_raw(lib, 4, 4, 3) == accsk.SHAPE
+    assert _solve_dense_raw(lib, 4, 9000, 9000) == accsk.SHAPE
+    assert _solve_dense_raw(lib, 4, 4, 4, ptr=0) == accsk.INVALID_ARG
+
+
+def test_host_validation_batch(lib):
+    p = accsk.default_params()
+    res = (accsk.Result * 1)()
+    arr = (accsk.Problem * 1)()
+    arr[0] = accsk.Problem(1, 4, 4, 4, 1, 1, 1, 1, 1e-2)
+    bad = accsk.Problem(1, 4, 2000, 2000, 1, 1, 1, 1, 1e-2)
+    arr2 = (accsk.Problem * 1)(bad)
+    assert lib.accsk_solve_batch(arr2, 1, ctypes.byref(p), res, None) == accsk.SHAPE
+    arr3 = (accsk.Problem * 1)(accsk.Problem(1, 4, 4, 4, 1, 1, 1, 1, 0.0))
+    assert lib.accsk_solve_batch(arr3, 1, ctypes.byref(p), res, None) == accsk.INVALID_ARG
+    assert lib.accsk_solve_batch(arr, 0, ctypes.byref(p), res, None) == accsk.OK

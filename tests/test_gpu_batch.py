@@ -1,0 +1,114 @@
+"""GPU parity of the batched small-problem solver (one workgroup per problem).
+
+Each problem is compared with the FP64 oracle run on the same FP32 cost:
+FP64 two-sided marginal error <= tol at the returned potentials, stopping
+iterate consistent with the oracle's FP64 error trace (tests/_stopcheck.py), dual
+value at the returned potentials equal to the reported one within eps*1e-7
+(the kernel's mass sum_ij P_ij comes from FP32 exponentials summed in FP64,
+relative error ~1e-8, and enters the value multiplied by eps), and
+<C,P> to 1e-6 relative (FP32 exponentials, FP64 sums).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+from _stopcheck import check_stop
+from paper_2605_30267_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+from _stopcheck import STOP  # noqa: E402
+
+
+def _dev(torch, x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _check_batch(torch, probs, method, tol=1e-6, **kw):
+    from paper_2605_30267_amd import accsk
+    dev_probs = [(_dev(torch, p["C32"], torch.float32), _dev(torch, p["a"], torch.float64),
+                  _dev(torch, p["b"], torch.float64), p["eps"]) for p in probs]
+    outs, res, st = accsk.solve_batch(dev_probs, tol=tol, method=method, **kw)
+    torch.cuda.synchronize()
+    dp = accsk.default_params()
+    for k, (p, (f, g), r) in enumerate(zip(probs, outs, res)):
+        C = p["C32"].astype(np.float64)
+        fh, gh = f.cpu().numpy(), g.cpu().numpy()
+        an, bn = p["a"] / p["a"].sum(), p["b"] / p["b"].sum()
+        ev = O.evaluate(C, p["eps"], an, bn, fh, gh)
+        o = O.solve(C, p["a"], p["b"], p["eps"], tol=tol * STOP, method=O.ACC if method == 1 else O.SINKHORN,
+                    mu0=kw.get("mu0") or dp.mu0, m0=kw.get("m0") or dp.m0,
+                    w_rule=dp.w_rule if kw.get("w_rule") is None else kw["w_rule"], max_iter=100000)
+        print("problem", k, C.shape, p["eps"], "gpu It", r["iters"], "oracle It", o["iters"], "err",
+              ev["err"], flush=True)
+        assert r["status"] == 0 and r["converged"] == 1, r
+        assert ev["err"] <= tol
+        check_stop(C, an, bn, p["eps"], tol, O.ACC if method == 1 else O.SINKHORN, r["iters"],
+                   kw.get("mu0") or dp.mu0, kw.get("m0") or dp.m0,
+                   dp.w_rule if kw.get("w_rule") is None else kw["w_rule"])
+        assert abs(r["eot_value"] - ev["dual"]) <= 1e-7 * p["eps"] + 1e-12 * abs(ev["dual"])
+        assert abs(r["transport_cost"] - ev["cost"]) <= 1e-6 * abs(ev["cost"]) + 1e-13
+        assert abs(gh.mean()) <= 1e-12 * max(1.0, np.abs(gh).max())
+    return res
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_batch_mixed_sizes(torch_gpu, method):
+    rng = np.random.default_rng(5)
+    probs = []
+    sizes = [(256, 256), (1, 1), (3, 7), (64, 64), (100, 37), (256, 130), (17, 256), (513, 255),
+             (40, 300), (128, 512), (300, 1000), (2000, 64), (1500, 16)]
+    for k, (n, m) in enumerate(sizes):
+        eps = float(rng.choice([1e-1, 1e-2, 3e-3]))
+        probs.append(W.random_dense(100 + k, n, m, eps=eps, a_kind="dirichlet"))
+    print("case batch mixed", method, flush=True)
+    _check_batch(torch_gpu, probs, method)
+
+
+def test_batch_small_uniform(torch_gpu):
+    p = W.small_uniform()
+    print("case batch small_uniform", flush=True)
+    res = _check_batch(torch_gpu, [p] * 8, 1)
+    assert len({r["iters"] for r in res}) == 1
+
+
+def test_batch_alone_equals_mixed(torch_gpu):
+    """A problem's result does not depend on the other problems of the batch."""
+    from paper_2605_30267_amd import accsk
+    torch = torch_gpu
+    probs = [W.random_dense(200 + k, 50 + 20 * k, 60 + 13 * k, eps=1e-2) for k in range(6)]
+    dev = [(_dev(torch, p["C32"], torch.float32), _dev(torch, p["a"], torch.float64),
+            _dev(torch, p["b"], torch.float64), p["eps"]) for p in probs]
+    outs_all, res_all, _ = accsk.solve_batch(dev)
+    outs_one, res_one, _ = accsk.solve_batch([dev[3]])
+    torch.cuda.synchronize()
+    assert torch.equal(outs_all[3][0], outs_one[0][0]) and torch.equal(outs_all[3][1], outs_one[0][1])
+    assert res_all[3] == res_one[0]
+
+
+def test_batch_small_eps_fallback(torch_gpu):
+    p = W.random_dense(23, 256, 256, eps=1e-4)
+    print("case batch eps 1e-4", flush=True)
+    res = _check_batch(torch_gpu, [p], 1)
+    assert res[0]["fallback_steps"] >= 1
+
+
+def test_batch_errors(torch_gpu):
+    from paper_2605_30267_amd import accsk
+    torch = torch_gpu
+    p = W.random_dense(25, 64, 64)
+    C = _dev(torch, p["C32"], torch.float32)
+    a, b = _dev(torch, p["a"], torch.float64), _dev(torch, p["b"], torch.float64)
+    bad = a.clone()
+    bad[0] = -1.0
+    outs, res, st = accsk.solve_batch([(C, a, b, 1e-2), (C, bad, b, 1e-2)], raise_on_error=False)
+    assert res[0]["status"] == 0 and res[1]["status"] == accsk.INVALID_ARG
+    assert st == accsk.INVALID_ARG
+
+
+def test_batch_tall(torch_gpu):
+    """n = 4096 rows (the largest the workgroup keeps in LDS) with few columns."""
+    probs = [W.random_dense(300, 4096, 16, eps=1e-2), W.random_dense(301, 4096, 64, eps=3e-3)]
+    print("case batch tall", flush=True)
+    _check_batch(torch_gpu, probs, 1)
