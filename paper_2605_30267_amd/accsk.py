@@ -227,4 +227,5 @@ def symbols_declared():
     import re
     hdr = os.path.join(os.path.dirname(HERE), "include", "accsk.h")
     text = open(hdr).read()
-    return sorted(set(re.findall(r"\b(accsk_[a-z_0-9]+)\s*\(", text)))
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)  # declarations only, not comments
+    return sorted(set(re.findall(r"^[a-z_][a-z_0-9 \t*]*?\b(accsk_[a-z_0-9]+)\s*\(", text, re.M)))

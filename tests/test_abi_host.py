@@ -34,7 +34,7 @@ def test_struct_fields_match_header():
     text = open(os.path.join(ROOT, "include", "accsk.h")).read()
 
     def fields(struct_name):
-        body = re.search(r"typedef struct \{(.*?)\} %s;" % struct_name, text, re.S).group(1)
+        body = re.search(r"typedef struct \{([^{}]*)\} %s;" % struct_name, text).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         out = []
         for decl in body.split(";"):
