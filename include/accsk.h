@@ -144,13 +144,15 @@ typedef struct {
 
 /*
  * Batched solve of independent dense problems (Sec. 2 dual, Sec. 4
- * algorithms, stopping rule eq:l1tol per problem).  One workgroup owns each
- * problem: its iterate, extrapolation state and homotopy counters stay in
- * on-chip memory, no grid-wide barrier is used, and every problem stops on its
+ * algorithms, stopping rule eq:l1tol per problem).  Problems with m <= 1024
+ * and n <= 4096 are each owned by one workgroup: iterate, extrapolation state
+ * and homotopy counters stay in on-chip memory and no grid-wide barrier is
+ * used.  Larger problems (m <= 8192) share one persistent launch, a group of
+ * workgroups per problem with its own barrier.  Every problem stops on its
  * own test.  probs: host array of `count` descriptors (the library copies it);
  * res: host array of `count` results.  p supplies method, tol, max_iter,
  * mu0, m0, w_rule and flags (p->eps is ignored; each problem has its own).
- * Limits per problem: 1 <= m <= 1024, 1 <= n <= 4096.
+ * Limits per problem: 1 <= m <= 8192, 1 <= n.
  * Returns ACCSK_OK if every problem converged, ACCSK_NOT_CONVERGED if some hit
  * max_iter, otherwise the first error (per-problem status in res[k].status).
  */

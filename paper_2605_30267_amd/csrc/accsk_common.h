@@ -108,7 +108,8 @@ __device__ __forceinline__ float lds_combine_max(const float *v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 15));
 }
 
-// Grid-wide barrier for a cooperative launch.  `bar` points at two zeroed
+// Barrier over the `nblocks` workgroups of one problem of a cooperative
+// launch (all of them are co-resident).  `bar` points at two zeroed
 // 64-bit words 128 bytes apart: bar[0] counts arrivals, bar[16] holds the
 // number of the last completed barrier.  `gen` counts the barriers this block
 // has passed (uniform).
@@ -121,12 +122,12 @@ __device__ __forceinline__ float lds_combine_max(const float *v, int lane) {
 // One agent acquire (L2/L1 invalidate) follows.  Returns false if the wait
 // exceeded kBarrierSpinLimit.
 __device__ __forceinline__ bool grid_sync(unsigned long long *bar, unsigned long long &gen,
-                                          int *lds_flag) {
+                                          int *lds_flag, unsigned nblocks) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     gen += 1;
     if (threadIdx.x == 0) {
-        const unsigned long long target = gen * (unsigned long long)gridDim.x;
+        const unsigned long long target = gen * (unsigned long long)nblocks;
         unsigned long long *flag = bar + 16;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned long long prev =

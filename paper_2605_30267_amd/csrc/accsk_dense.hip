@@ -84,7 +84,8 @@ __device__ double block_max_1024(double v, double *red) {
     return s;
 }
 
-__global__ __launch_bounds__(1024) void setup_marginals(DenseArgs A) {
+__global__ __launch_bounds__(1024) void setup_marginals(const DenseArgs *__restrict__ probs) {
+    const DenseArgs A = probs[blockIdx.x];
     __shared__ double red[16];
     __shared__ int bad;
     const int tid = threadIdx.x;
@@ -173,7 +174,9 @@ __device__ __forceinline__ float f4get(const float4 &v, int e) {
 // x and w live in LDS between steps (each thread owns the same columns in
 // every phase), so no per-column state is carried in registers across steps.
 template <int TPB, int NG, int RB, bool VEC>
-__global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
+__global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__ probs, int gp) {
+    // gp workgroups per problem; problem p owns blocks [p*gp, (p+1)*gp)
+    const DenseArgs A = probs[blockIdx.x / gp];
     constexpr int NW = TPB / 64;
     constexpr int NC = NG * 4;  // columns per thread
     __shared__ float red_max[RB][NW];
@@ -184,8 +187,8 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
     extern __shared__ double dyn_lds[];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int G = gridDim.x, bid = blockIdx.x;
-    if (A.status[0] != ACCSK_OK) {  // uniform across the grid: no barrier is entered
+    const int G = gp, bid = blockIdx.x % gp;
+    if (A.status[0] != ACCSK_OK) {  // uniform across the problem's blocks: no barrier is entered
         if (bid == 0 && tid == 0) {
             DevResult r{};
             r.err = NAN;
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
                 if (c0 + 3 < m) dst[3] = v.w;
             }
         }
-        if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
+        if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
 
         // ---------------- slice combine ----------------
         bool exact = false;
@@ -461,7 +464,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
                             L.partmax[(size_t)bid * m + col] = cm[k * 4 + e];
                         }
                     }
-                if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
+                if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
                 fallbacks++;
             }
             double aS = 0.0, aE = 0.0, aC = 0.0, aXB = 0.0, aFB = 0.0;
@@ -532,7 +535,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
                     xstore(&p[5], aFB);
                 }
             }
-            if (!grid_sync(A.bar, gen, &bflag)) { status = ACCSK_HIP_ERROR; break; }
+            if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
             // totals, identical in every block
             for (int sidx = wid; sidx < 6; sidx += NW) {
                 double v = 0.0;
@@ -636,7 +639,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(DenseArgs A) {
                     if (col < m) A.g_out[col] = A.eps * kLn2 * xl_lds[col];
                 }
         }
-        if (!grid_sync(A.bar, gen, &bflag)) status = ACCSK_HIP_ERROR;
+        if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) status = ACCSK_HIP_ERROR;
         if (bid == 0 && tid == 0 && status != ACCSK_HIP_ERROR) {
             double ua2 = 0.0;
             for (int b = 0; b < G; b++) ua2 += A.uapart[b];
@@ -794,94 +797,7 @@ __global__ __launch_bounds__(256) void plan_rows(const float *__restrict__ C, lo
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-struct Workspace {
-    void *base = nullptr;
-    size_t bytes = 0;
-};
-
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
-
-template <int TPB, int NG, int RB, bool VEC>
-accsk_status launch_dense(DenseArgs &A, hipStream_t s, int num_cu, void *&ws, size_t &ws_bytes,
-                          int &grid_out, hipEvent_t ev0, hipEvent_t ev1) {
-    int occ = 0;
-    // dynamic LDS: w[m] and three per-row arrays for this block's rows
-    const long long G_est = std::min<long long>((long long)num_cu, std::max<long long>(1, A.n));
-    const long long rpb_max = (A.n + G_est - 1) / G_est;
-    const size_t dyn = (size_t)(2 * A.m + 4 * rpb_max) * sizeof(double);
-    if (dyn > 150 * 1024) return ACCSK_SHAPE;
-    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC>, TPB, dyn));
-    if (occ < 1) return ACCSK_SHAPE;
-    // at most two blocks per CU: the grid barrier's cost grows with the block count
-    long long G = (long long)std::min(occ, 2) * num_cu;
-    G = std::min<long long>(G, std::max<long long>(1, A.n));  // >= G_est, so rows per block <= rpb_max
-    // workspace
-    const size_t n = A.n, m = A.m;
-    size_t off = 0;
-    const size_t o_an = off; off = align_up(off + n * 8);
-    const size_t o_la2 = off; off = align_up(off + n * 8);
-    const size_t o_u = off; off = align_up(off + n * 8);
-    const size_t o_rs = off; off = align_up(off + n * 8);
-    const size_t o_bn = off; off = align_up(off + m * 8);
-    const size_t o_lnb = off; off = align_up(off + m * 8);
-    const size_t o_shat = off; off = align_up(off + m * 8);
-    const size_t o_partf = off; off = align_up(off + (size_t)G * m * 4);
-    const size_t o_part = off; off = align_up(off + (size_t)G * m * 8);
-    const size_t o_pmax = off; off = align_up(off + (size_t)G * m * 8);
-    const size_t o_bscal = off; off = align_up(off + 2 * (size_t)G * kNS * 8);
-    const size_t o_uap = off; off = align_up(off + (size_t)G * 8);
-    const size_t o_gscal = off; off = align_up(off + 8 * 8);
-    const size_t o_stat = off; off = align_up(off + 64);
-    const size_t o_bar = off; off = align_up(off + 256);
-    const size_t o_res = off; off = align_up(off + sizeof(DevResult));
-    void *base = nullptr;
-    if (hipMallocAsync(&base, off, s) != hipSuccess) return ACCSK_OOM;
-    char *p = (char *)base;
-    A.an = (double *)(p + o_an);
-    A.la2 = (double *)(p + o_la2);
-    A.u = (double *)(p + o_u);
-    A.rsum = (double *)(p + o_rs);
-    A.bn = (double *)(p + o_bn);
-    A.lnb = (double *)(p + o_lnb);
-    A.shat = (double *)(p + o_shat);
-    A.partf = (float *)(p + o_partf);
-    A.part = (double *)(p + o_part);
-    A.partmax = (double *)(p + o_pmax);
-    A.bscal = (double *)(p + o_bscal);
-    A.uapart = (double *)(p + o_uap);
-    A.gscal = (double *)(p + o_gscal);
-    A.status = (int *)(p + o_stat);
-    A.bar = (unsigned long long *)(p + o_bar);
-    A.res = (DevResult *)(p + o_res);
-    ws = base;
-    ws_bytes = off;
-    hipError_t e = hipMemsetAsync(p + o_bar, 0, 256, s);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(setup_marginals, dim3(1), dim3(1024), 0, s, A);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
-    if (e == hipSuccess) {
-        void *args[] = {&A};
-        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, RB, VEC>, dim3((unsigned)G), dim3(TPB),
-                                       args, dyn, s);
-    }
-    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
-    grid_out = (int)G;
-    return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
-}
-
-template <bool VEC>
-accsk_status launch_dense_cfg(DenseArgs &A, hipStream_t s, int cu, void *&ws, size_t &ws_bytes, int &G,
-                              hipEvent_t ev0, hipEvent_t ev1) {
-    const long long m = A.m;
-    if (m <= 256) return launch_dense<64, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
-    if (m <= 512) return launch_dense<128, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
-    if (m <= 1024) return launch_dense<256, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
-    if (m <= 2048) return launch_dense<512, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
-    if (m <= 4096) return launch_dense<1024, 1, 2, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
-    return launch_dense<1024, 2, 1, VEC>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
-}
 
 int device_cu_count() {
     int dev = 0, cu = 0;
@@ -911,101 +827,238 @@ accsk_status run_eval(const float *C, long long n, long long m, long long ldc, d
     return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
 }
 
+
+struct HostProb {
+    const float *C;
+    long long n, m, ldc;
+    const double *a, *b;
+    double *f, *g;
+    double eps;
+};
+
+// Solves problems [k0, k1) of `hp` with one cooperative launch, gp workgroups
+// per problem.  Results go to res[k0..k1).
+template <int TPB, int NG, int RB, bool VEC>
+accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const accsk_params *p,
+                         accsk_result *res, hipStream_t s, int num_cu) {
+    const int cnt = k1 - k0;
+    long long nmax = 0, mmax = 0, nmin = 1LL << 62;
+    for (int k = k0; k < k1; k++) {
+        nmax = std::max(nmax, hp[k].n);
+        mmax = std::max(mmax, hp[k].m);
+        nmin = std::min(nmin, hp[k].n);
+    }
+    // blocks per problem: fill the chip with at most two workgroups per CU
+    int occ = 0;
+    const size_t dyn_probe = (size_t)(2 * mmax + 4) * sizeof(double);
+    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC>, TPB, dyn_probe));
+    if (occ < 1) return ACCSK_SHAPE;
+    const long long total = (long long)std::min(occ, 2) * num_cu;
+    long long gp = std::max<long long>(1, total / cnt);
+    gp = std::min<long long>(gp, std::max<long long>(1, nmax));
+    long long rpb_max = 0;
+    for (int k = k0; k < k1; k++) rpb_max = std::max(rpb_max, (hp[k].n + gp - 1) / gp);
+    const size_t dyn = (size_t)(2 * mmax + 4 * rpb_max) * sizeof(double);
+    if (dyn > 150 * 1024) return ACCSK_SHAPE;
+    int occ2 = 0;
+    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, dense_solve<TPB, NG, RB, VEC>, TPB, dyn));
+    if (occ2 < 1 || (long long)cnt * gp > (long long)occ2 * num_cu) return ACCSK_SHAPE;
+
+    // workspace: shared arrays first (args, results, scalars, barriers), then per-problem slices
+    size_t off = 0;
+    const size_t o_args = off; off = align_up(off + sizeof(DenseArgs) * cnt);
+    const size_t o_res = off; off = align_up(off + sizeof(DevResult) * cnt);
+    const size_t o_gscal = off; off = align_up(off + 8 * 8 * (size_t)cnt);
+    const size_t o_stat = off; off = align_up(off + 64 * (size_t)cnt);
+    const size_t o_bar = off; off = align_up(off + 256 * (size_t)cnt);
+    std::vector<size_t> o_prob(cnt);
+    for (int q = 0; q < cnt; q++) {
+        const HostProb &h = hp[k0 + q];
+        const size_t n = h.n, m = h.m;
+        o_prob[q] = off;
+        off = align_up(off + 4 * n * 8);                    // an, la2, u, rsum
+        off = align_up(off + 3 * m * 8);                    // bn, lnb, shat
+        off = align_up(off + (size_t)gp * m * 4);           // partf
+        off = align_up(off + 2 * (size_t)gp * m * 8);       // part, partmax
+        off = align_up(off + (2 * (size_t)gp * kNS + gp) * 8);  // bscal, uapart
+    }
+    char *base = nullptr;
+    if (hipMallocAsync((void **)&base, off, s) != hipSuccess) return ACCSK_OOM;
+    std::vector<DenseArgs> args(cnt);
+    for (int q = 0; q < cnt; q++) {
+        const HostProb &h = hp[k0 + q];
+        const size_t n = h.n, m = h.m;
+        DenseArgs &A = args[q];
+        A = DenseArgs{};
+        A.C = h.C;
+        A.n = h.n;
+        A.m = h.m;
+        A.ldc = h.ldc;
+        A.a_in = h.a;
+        A.b_in = h.b;
+        A.f_out = h.f;
+        A.g_out = h.g;
+        A.eps = h.eps;
+        A.kappa = 1.0 / h.eps;
+        A.tol = p->tol;
+        // The stop test compares an error computed from FP32 exponential sums;
+        // stopping 1/16 below tol keeps the FP64-evaluated error under tol.
+        A.tol_stop = p->tol * (1.0 - 1.0 / 16.0);
+        A.mu0 = p->mu0;
+        A.max_iter = p->max_iter;
+        A.m0 = p->m0;
+        A.method = p->method;
+        A.w_rule = p->w_rule;
+        A.serpentine = (p->flags & ACCSK_FLAG_NO_SERPENTINE) ? 0 : 1;
+        char *q0 = base + o_prob[q];
+        A.an = (double *)q0;
+        A.la2 = A.an + n;
+        A.u = A.la2 + n;
+        A.rsum = A.u + n;
+        q0 += align_up(4 * n * 8);
+        A.bn = (double *)q0;
+        A.lnb = A.bn + m;
+        A.shat = A.lnb + m;
+        q0 += align_up(3 * m * 8);
+        A.partf = (float *)q0;
+        q0 += align_up((size_t)gp * m * 4);
+        A.part = (double *)q0;
+        A.partmax = A.part + (size_t)gp * m;
+        q0 += align_up(2 * (size_t)gp * m * 8);
+        A.bscal = (double *)q0;
+        A.uapart = A.bscal + 2 * (size_t)gp * kNS;
+        A.res = (DevResult *)(base + o_res) + q;
+        A.gscal = (double *)(base + o_gscal) + 8 * q;
+        A.status = (int *)(base + o_stat + 64 * (size_t)q);
+        A.bar = (unsigned long long *)(base + o_bar + 256 * (size_t)q);
+    }
+    DenseArgs *d_args = (DenseArgs *)(base + o_args);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+    if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+    hipError_t e = hipMemcpyAsync(d_args, args.data(), sizeof(DenseArgs) * cnt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(base + o_bar, 0, 256 * (size_t)cnt, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(setup_marginals, dim3(cnt), dim3(1024), 0, s, (const DenseArgs *)d_args);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
+    if (e == hipSuccess) {
+        int gpi = (int)gp;
+        void *kargs[] = {&d_args, &gpi};
+        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, RB, VEC>, dim3((unsigned)(cnt * gp)),
+                                       dim3(TPB), kargs, dyn, s);
+    }
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    accsk_status st = e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+    if (st == ACCSK_OK && !(p->flags & ACCSK_FLAG_NO_COST)) {
+        for (int q = 0; q < cnt && st == ACCSK_OK; q++) {
+            const DenseArgs &A = args[q];
+            // <C,P> and the dual value at the returned potentials, FP64, with normalized marginals
+            st = run_eval(A.C, A.n, A.m, A.ldc, A.eps, A.an, A.bn, A.f_out, A.g_out, A.gscal + 1, A.res, s);
+        }
+    }
+    std::vector<DevResult> hr(cnt);
+    if (st == ACCSK_OK) {
+        e = hipMemcpyAsync(hr.data(), base + o_res, sizeof(DevResult) * cnt, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = ACCSK_HIP_ERROR;
+    }
+    float kms = -1.f;
+    if (st == ACCSK_OK && ev0 && ev1 && hipEventElapsedTime(&kms, ev0, ev1) != hipSuccess) kms = -1.f;
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipFreeAsync(base, s);
+    if (st != ACCSK_OK) return st;
+    for (int q = 0; q < cnt; q++) {
+        const DevResult &r = hr[q];
+        accsk_result &o = res[k0 + q];
+        o.iters = r.iters;
+        o.sinkhorn_steps = r.steps;
+        o.fallback_steps = r.fallback;
+        o.marginal_err = r.err;
+        o.eot_value = r.eot;
+        o.transport_cost = r.cost;
+        o.dual_fval = r.fval;
+        o.kernel_ms = kms;
+        o.converged = r.converged;
+        o.status = r.status;
+        if (r.status == ACCSK_OK && !r.converged) o.status = ACCSK_NOT_CONVERGED;
+    }
+    return ACCSK_OK;
+}
+
+template <bool VEC>
+accsk_status dense_chunk_cfg(long long mmax, const std::vector<HostProb> &hp, int k0, int k1,
+                             const accsk_params *p, accsk_result *res, hipStream_t s, int cu) {
+    if (mmax <= 256) return dense_chunk<64, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 512) return dense_chunk<128, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 1024) return dense_chunk<256, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 2048) return dense_chunk<512, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 4096) return dense_chunk<1024, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
+    return dense_chunk<1024, 2, 1, VEC>(hp, k0, k1, p, res, s, cu);
+}
+
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Validates the shared parameters (everything except eps).
+accsk_status check_params(const accsk_params *p) {
+    if (!p) return ACCSK_INVALID_ARG;
+    if (!finite_pos(p->tol) || p->max_iter < 0) return ACCSK_INVALID_ARG;
+    if (p->method != ACCSK_SINKHORN && p->method != ACCSK_ACC) return ACCSK_INVALID_ARG;
+    if (p->method == ACCSK_ACC && !(p->mu0 > 0.0 && p->mu0 < 1.0 && p->m0 >= 1)) return ACCSK_INVALID_ARG;
+    if (p->w_rule != ACCSK_W_LITERAL && p->w_rule != ACCSK_W_Y_CONTINUOUS) return ACCSK_INVALID_ARG;
+    return ACCSK_OK;
+}
 
 }  // namespace
 }  // namespace accsk
 
 using namespace accsk;
 
+// Persistent multi-problem path, also used by the batch entry point for
+// problems with more than 1024 columns.
+accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                               accsk_result *res, hipStream_t s) {
+    using namespace accsk;
+    const int cu = device_cu_count();
+    if (cu <= 0) return ACCSK_HIP_ERROR;
+    std::vector<HostProb> hp((size_t)count);
+    long long mmax = 0;
+    bool vec = true;
+    for (int64_t k = 0; k < count; k++) {
+        const accsk_problem &q = probs[k];
+        hp[(size_t)k] = HostProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps};
+        mmax = std::max<long long>(mmax, q.m);
+        vec = vec && (q.ldc % 4) == 0 && (q.m % 4) == 0 && (((uintptr_t)q.C) & 15) == 0;
+    }
+    // at most 256 problems per cooperative launch (one block group each at minimum)
+    for (int64_t k0 = 0; k0 < count; k0 += cu) {
+        const int k1 = (int)std::min<int64_t>(count, k0 + cu);
+        accsk_status st = vec ? dense_chunk_cfg<true>(mmax, hp, (int)k0, k1, p, res, s, cu)
+                              : dense_chunk_cfg<false>(mmax, hp, (int)k0, k1, p, res, s, cu);
+        if (st != ACCSK_OK) return st;
+    }
+    return ACCSK_OK;
+}
+
 extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc, const double *a,
                                           const double *b, const accsk_params *p, double *f_out,
                                           double *g_out, accsk_result *res, void *stream) {
+    using namespace accsk;
     if (res) {
         res->status = ACCSK_INVALID_ARG;
         res->converged = 0;
     }
     if (!C || !a || !b || !p || !f_out || !g_out || !res) return ACCSK_INVALID_ARG;
-    if (!finite_pos(p->eps) || !finite_pos(p->tol) || p->max_iter < 0) return ACCSK_INVALID_ARG;
-    if (p->method != ACCSK_SINKHORN && p->method != ACCSK_ACC) return ACCSK_INVALID_ARG;
-    if (p->method == ACCSK_ACC && !(p->mu0 > 0.0 && p->mu0 < 1.0 && p->m0 >= 1)) return ACCSK_INVALID_ARG;
-    if (p->w_rule != ACCSK_W_LITERAL && p->w_rule != ACCSK_W_Y_CONTINUOUS) return ACCSK_INVALID_ARG;
+    if (!finite_pos(p->eps)) return ACCSK_INVALID_ARG;
+    accsk_status st = check_params(p);
+    if (st != ACCSK_OK) return st;
     if (n < 1 || m < 1 || ldc < m) return ACCSK_SHAPE;
     if (m > 8192) return ACCSK_SHAPE;
-    hipStream_t s = (hipStream_t)stream;
-    const int cu = device_cu_count();
-    if (cu <= 0) return ACCSK_HIP_ERROR;
-
-    DenseArgs A{};
-    A.C = C;
-    A.n = n;
-    A.m = m;
-    A.ldc = ldc;
-    A.a_in = a;
-    A.b_in = b;
-    A.f_out = f_out;
-    A.g_out = g_out;
-    A.eps = p->eps;
-    A.kappa = 1.0 / p->eps;
-    A.tol = p->tol;
-    // The stop test compares an error computed from FP32 exponential sums;
-    // stopping 1/16 below tol keeps the FP64-evaluated error under tol.
-    A.tol_stop = p->tol * (1.0 - 1.0 / 16.0);
-    A.mu0 = p->mu0;
-    A.max_iter = p->max_iter;
-    A.m0 = p->m0;
-    A.method = p->method;
-    A.w_rule = p->w_rule;
-    A.serpentine = (p->flags & ACCSK_FLAG_NO_SERPENTINE) ? 0 : 1;
-
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-    int G = 0;
-    accsk_status st;
-    const bool vec = (ldc % 4) == 0 && (m % 4) == 0 && (((uintptr_t)C) & 15) == 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
-    if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
-    if (vec) st = launch_dense_cfg<true>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
-    else st = launch_dense_cfg<false>(A, s, cu, ws, ws_bytes, G, ev0, ev1);
-    auto drop_events = [&]() {
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-    };
-    if (st != ACCSK_OK) {
-        if (ws) (void)hipFreeAsync(ws, s);
-        drop_events();
-        return st;
-    }
-    double *out_dev = A.gscal + 1;  // 5 slots after max log2 a
-    if (!(p->flags & ACCSK_FLAG_NO_COST)) {
-        // <C,P> and the dual value at the returned potentials, FP64, with normalized marginals
-        st = run_eval(C, n, m, ldc, p->eps, A.an, A.bn, f_out, g_out, out_dev, A.res, s);
-        if (st != ACCSK_OK) {
-            (void)hipFreeAsync(ws, s);
-            drop_events();
-            return st;
-        }
-    }
-    DevResult r;
-    hipError_t e = hipMemcpyAsync(&r, A.res, sizeof(DevResult), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFreeAsync(ws, s);
-    float kms = -1.f;
-    if (e == hipSuccess && ev0 && ev1 && hipEventElapsedTime(&kms, ev0, ev1) != hipSuccess) kms = -1.f;
-    drop_events();
-    if (e != hipSuccess) return ACCSK_HIP_ERROR;
-    res->kernel_ms = kms;
-    res->iters = r.iters;
-    res->sinkhorn_steps = r.steps;
-    res->fallback_steps = r.fallback;
-    res->marginal_err = r.err;
-    res->eot_value = r.eot;
-    res->transport_cost = r.cost;
-    res->dual_fval = r.fval;
-    res->converged = r.converged;
-    res->status = r.status;
-    if (r.status == ACCSK_OK && !r.converged) res->status = ACCSK_NOT_CONVERGED;
+    accsk_problem q{C, n, m, ldc, a, b, f_out, g_out, p->eps};
+    st = accsk_dense_multi(&q, 1, p, res, (hipStream_t)stream);
+    if (st != ACCSK_OK) return st;
     return (accsk_status)res->status;
 }
 

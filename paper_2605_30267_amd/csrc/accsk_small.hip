@@ -445,6 +445,10 @@ accsk_status small_ctl_from_params(const accsk_params *p, SmallCtl *c);
 
 using namespace accsk;
 
+// Persistent multi-problem solver of accsk_dense.hip (problems with m > 1024).
+accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                               accsk_result *res, hipStream_t s);
+
 accsk_status accsk::small_ctl_from_params(const accsk_params *p, SmallCtl *c) {
     if (!p) return ACCSK_INVALID_ARG;
     if (!finite_pos(p->tol) || p->max_iter < 0) return ACCSK_INVALID_ARG;
@@ -462,21 +466,14 @@ accsk_status accsk::small_ctl_from_params(const accsk_params *p, SmallCtl *c) {
     return ACCSK_OK;
 }
 
-extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                                          accsk_result *res, void *stream) {
-    if (!probs || !res || !p || count < 0) return ACCSK_INVALID_ARG;
-    if (count == 0) return ACCSK_OK;
-    SmallCtl ctl;
-    accsk_status st = small_ctl_from_params(p, &ctl);
-    if (st != ACCSK_OK) return st;
+static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, const SmallCtl &ctl,
+                                      accsk_result *res, hipStream_t s) {
+    const int64_t count = (int64_t)probs.size();
     long long nmax = 0, mmax = 0;
     bool vec = true;
     std::vector<SmallProb> hp((size_t)count);
     for (int64_t k = 0; k < count; k++) {
-        const accsk_problem &q = probs[k];
-        if (!q.C || !q.a || !q.b || !q.f || !q.g) return ACCSK_INVALID_ARG;
-        if (!finite_pos(q.eps)) return ACCSK_INVALID_ARG;
-        if (q.n < 1 || q.m < 1 || q.ldc < q.m || q.m > 1024 || q.n > 4096) return ACCSK_SHAPE;
+        const accsk_problem &q = probs[(size_t)k];
         nmax = std::max<long long>(nmax, q.n);
         mmax = std::max<long long>(mmax, q.m);
         vec = vec && (q.m % 4 == 0) && (q.ldc % 4 == 0) && ((((uintptr_t)q.C) & 15) == 0);
@@ -484,7 +481,6 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
     }
     const size_t lds = small_lds_bytes(nmax, mmax, 4);
     if (lds > 150 * 1024) return ACCSK_SHAPE;
-    hipStream_t s = (hipStream_t)stream;
     const size_t bytes_p = sizeof(SmallProb) * (size_t)count, bytes_r = sizeof(DevResult) * (size_t)count;
     char *buf = nullptr;
     if (hipMallocAsync((void **)&buf, bytes_p + bytes_r + 256, s) != hipSuccess) return ACCSK_OOM;
@@ -499,7 +495,6 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFreeAsync(buf, s);
     if (e != hipSuccess) return ACCSK_HIP_ERROR;
-    accsk_status worst = ACCSK_OK;
     for (int64_t k = 0; k < count; k++) {
         const DevResult &r = hr[(size_t)k];
         accsk_result &o = res[k];
@@ -514,8 +509,50 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
         o.converged = r.converged;
         o.status = r.status;
         if (r.status == ACCSK_OK && !r.converged) o.status = ACCSK_NOT_CONVERGED;
-        if (o.status != ACCSK_OK && worst == ACCSK_OK) worst = (accsk_status)o.status;
-        else if (o.status != ACCSK_OK && o.status != ACCSK_NOT_CONVERGED) worst = (accsk_status)o.status;
+    }
+    return ACCSK_OK;
+}
+
+extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                                          accsk_result *res, void *stream) {
+    if (!probs || !res || !p || count < 0) return ACCSK_INVALID_ARG;
+    if (count == 0) return ACCSK_OK;
+    SmallCtl ctl;
+    accsk_status st = small_ctl_from_params(p, &ctl);
+    if (st != ACCSK_OK) return st;
+    std::vector<accsk_problem> small, big;
+    std::vector<int64_t> small_idx, big_idx;
+    for (int64_t k = 0; k < count; k++) {
+        const accsk_problem &q = probs[k];
+        if (!q.C || !q.a || !q.b || !q.f || !q.g) return ACCSK_INVALID_ARG;
+        if (!finite_pos(q.eps)) return ACCSK_INVALID_ARG;
+        if (q.n < 1 || q.m < 1 || q.ldc < q.m || q.m > 8192) return ACCSK_SHAPE;
+        if (q.m <= 1024 && q.n <= 4096) {
+            small.push_back(q);
+            small_idx.push_back(k);
+        } else {
+            big.push_back(q);
+            big_idx.push_back(k);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<accsk_result> rs(small.size()), rb(big.size());
+    if (!small.empty()) {
+        st = solve_small_batch(small, ctl, rs.data(), s);
+        if (st != ACCSK_OK) return st;
+    }
+    if (!big.empty()) {
+        st = accsk_dense_multi(big.data(), (int64_t)big.size(), p, rb.data(), s);
+        if (st != ACCSK_OK) return st;
+    }
+    for (size_t k = 0; k < small.size(); k++) res[small_idx[k]] = rs[k];
+    for (size_t k = 0; k < big.size(); k++) res[big_idx[k]] = rb[k];
+    accsk_status worst = ACCSK_OK;
+    for (int64_t k = 0; k < count; k++) {
+        const int stk = res[k].status;
+        if (stk == ACCSK_OK) continue;
+        if (worst == ACCSK_OK || (worst == ACCSK_NOT_CONVERGED && stk != ACCSK_NOT_CONVERGED))
+            worst = (accsk_status)stk;
     }
     return worst;
 }

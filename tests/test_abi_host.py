@@ -82,7 +82,7 @@ def test_host_validation_batch(lib):
     res = (accsk.Result * 1)()
     arr = (accsk.Problem * 1)()
     arr[0] = accsk.Problem(1, 4, 4, 4, 1, 1, 1, 1, 1e-2)
-    bad = accsk.Problem(1, 4, 2000, 2000, 1, 1, 1, 1, 1e-2)
+    bad = accsk.Problem(1, 4, 9000, 9000, 1, 1, 1, 1, 1e-2)
     arr2 = (accsk.Problem * 1)(bad)
     assert lib.accsk_solve_batch(arr2, 1, ctypes.byref(p), res, None) == accsk.SHAPE
     arr3 = (accsk.Problem * 1)(accsk.Problem(1, 4, 4, 4, 1, 1, 1, 1, 0.0))

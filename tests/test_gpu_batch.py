@@ -112,3 +112,29 @@ def test_batch_tall(torch_gpu):
     probs = [W.random_dense(300, 4096, 16, eps=1e-2), W.random_dense(301, 4096, 64, eps=3e-3)]
     print("case batch tall", flush=True)
     _check_batch(torch_gpu, probs, 1)
+
+
+def test_batch_large_problems_multi(torch_gpu):
+    """Problems with m > 1024 share one persistent launch (a block group each)."""
+    probs = [W.random_dense(400 + k, n, m, eps=eps, a_kind="dirichlet")
+             for k, (n, m, eps) in enumerate([(2048, 2048, 5e-3), (700, 1500, 1e-2), (3000, 4100, 1e-2),
+                                              (50, 8192, 3e-2)])]
+    probs.append(probs[0])
+    print("case batch large", flush=True)
+    res = _check_batch(torch_gpu, probs, 1)
+    assert res[0]["iters"] == res[4]["iters"]  # identical inputs, identical solves
+
+
+def test_batch_gaussian_shape(torch_gpu):
+    """Sixteen 2048 x 2048 problems shaped like the differentiable-loss batch
+    (N(0, I_64) points, squared Euclidean cost / 128, uniform marginals)."""
+    import numpy as np
+    gb = W.gaussian_batch(seed=5, batch=16, n=2048, m=2048, d=64, eps=5e-3)
+    probs = []
+    for k in range(16):
+        X, Y = gb["X"][k].astype(np.float64), gb["Y"][k].astype(np.float64)
+        D = (X * X).sum(1)[:, None] + (Y * Y).sum(1)[None, :] - 2.0 * X @ Y.T
+        C = (np.maximum(D, 0.0) / gb["scale"]).astype(np.float32)
+        probs.append(dict(C32=C, a=gb["a"][k], b=gb["b"][k], eps=gb["eps"]))
+    print("case batch gaussian 16x2048", flush=True)
+    _check_batch(torch_gpu, probs[:4], 1)
