@@ -71,7 +71,8 @@ typedef struct {
     int64_t max_iter;   /* cap on iterations (It), >= 0 */
     double mu0;         /* homotopy start, 0 < mu0 < 1 (Algorithm A2MD-homotopy) */
     int64_t m0;         /* inner iterations of the first stage, >= 1 */
-    int32_t split;      /* BF16 split depth of on-the-fly cost products: 2 or 3 */
+    int32_t split;      /* point-cloud cross terms X Y^T: 0 = FP64 dot products (default),
+                           2 or 3 = BF16 matrix cores on a 2- or 3-piece split of X and Y */
     int32_t flags;      /* ACCSK_FLAG_* bits */
 } accsk_params;
 
@@ -93,7 +94,7 @@ typedef struct {
 } accsk_result;
 
 /* Fills the defaults: ACC, Y_CONTINUOUS, eps 1e-2, tol 1e-6, max_iter 100000,
- * mu0 and m0 as calibrated on the FP64 oracle, split 3, flags 0. */
+ * mu0 and m0 as calibrated on the FP64 oracle, split 0, flags 0. */
 void accsk_default_params(accsk_params *p);
 
 /* Human-readable name of a status code (static storage). */
@@ -158,6 +159,56 @@ typedef struct {
  */
 accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t count, const accsk_params *p,
                                accsk_result *res, void *stream);
+
+/*
+ * Cost matrix from point clouds (Sec. 5: squared Euclidean for colour
+ * transfer, cosine for word alignment).  X: device FP32 n x d, Y: device FP32
+ * m x d (row-major, rows contiguous).  C: device FP32 n x m, leading
+ * dimension ldc >= m.  cost_scale s > 0 divides the raw cost.
+ * split: 0 = FP64 dot products (C exact up to its FP32 rounding); 2 or 3 =
+ * BF16 matrix cores on a 2- or 3-piece BF16 split of X and Y (cross-term
+ * pieces down to 2^-16 or 2^-24 relative, FP32 accumulation per 32-wide K
+ * chunk, chunks summed in FP64).  Limits: d <= 512.
+ */
+accsk_status accsk_cost_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                               double cost_scale, int split, float *C, int64_t ldc, void *stream);
+
+/*
+ * Point-cloud solve: builds the cost as accsk_cost_points does (with
+ * p->split) into library scratch memory and solves EOT on it.  a, b, f_out,
+ * g_out as for accsk_solve_dense.  Limits: m <= 8192, d <= 512.
+ */
+accsk_status accsk_solve_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                                double cost_scale, const double *a, const double *b, const accsk_params *p,
+                                double *f_out, double *g_out, accsk_result *res, void *stream);
+
+/*
+ * Batch of `batch` independent point-cloud problems of equal shape: X is
+ * batch x n x d, Y batch x m x d, a batch x n, b batch x m, f_out batch x n,
+ * g_out batch x m (all contiguous device arrays); res: host array of `batch`
+ * results.  Every problem stops on its own test (accsk_solve_batch).
+ */
+accsk_status accsk_solve_points_batched(const float *X, const float *Y, int64_t batch, int64_t n, int64_t m,
+                                        int64_t d, int kind, double cost_scale, const double *a,
+                                        const double *b, const accsk_params *p, double *f_out, double *g_out,
+                                        accsk_result *res, void *stream);
+
+/*
+ * Gradients of the EOT value at the potentials (f, g) by the envelope theorem
+ * (dEOT/dC = P with P_ij = exp((f_i + g_j - C_ij)/eps), eq:P-from-dual), for a
+ * batch of equal-shape point-cloud problems laid out as in
+ * accsk_solve_points_batched.  P is recomputed tile by tile (never stored),
+ * with the cost formed in FP64 from X and Y.  grad_scale: device FP64[batch]
+ * upstream gradient per problem, or NULL for 1.  Outputs (device, scaled by
+ * grad_scale): dX (batch x n x d FP32), dY (batch x m x d FP32) and, if not
+ * NULL, da (batch x n FP64) = (f - <f, a/sum a>)/sum a and db likewise, the
+ * gradients with respect to un-normalized marginals.  a, b may be NULL when
+ * da, db are.  Limits: d <= 448.
+ */
+accsk_status accsk_backward_points(const float *X, const float *Y, int64_t batch, int64_t n, int64_t m,
+                                   int64_t d, int kind, double cost_scale, double eps, const double *a,
+                                   const double *b, const double *f, const double *g, const double *grad_scale,
+                                   float *dX, float *dY, double *da, double *db, void *stream);
 
 #ifdef __cplusplus
 }

@@ -229,3 +229,162 @@ def symbols_declared():
     text = open(hdr).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)  # declarations only, not comments
     return sorted(set(re.findall(r"^[a-z_][a-z_0-9 \t*]*?\b(accsk_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+def _register_points(L):
+    if getattr(L, "_points_ready", False):
+        return
+    L.accsk_cost_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, ctypes.c_int, _vp, _i64, _vp]
+    L.accsk_cost_points.restype = ctypes.c_int
+    L.accsk_solve_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, _vp, _vp,
+                                     ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(Result), _vp]
+    L.accsk_solve_points.restype = ctypes.c_int
+    L.accsk_solve_points_batched.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.c_int, _dbl, _vp, _vp,
+                                             ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(Result), _vp]
+    L.accsk_solve_points_batched.restype = ctypes.c_int
+    L.accsk_backward_points.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp,
+                                        _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.accsk_backward_points.restype = ctypes.c_int
+    L._points_ready = True
+
+
+def _points_lib():
+    L = lib()
+    _register_points(L)
+    return L
+
+
+def cost_points(X, Y, kind=SQEUCLID, cost_scale=1.0, split=0, out=None):
+    """Cost matrix from point clouds X [n, d], Y [m, d] (float32, device)."""
+    import torch
+    _check_dev(X, torch.float32, "X", 2)
+    _check_dev(Y, torch.float32, "Y", 2)
+    X = X.contiguous()
+    Y = Y.contiguous()
+    n, d = X.shape
+    m = Y.shape[0]
+    if Y.shape[1] != d:
+        raise ValueError("X and Y must have the same feature dimension")
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.float32, device=X.device)
+    st = _points_lib().accsk_cost_points(_ptr(X), _ptr(Y), n, m, d, int(kind), float(cost_scale), int(split),
+                                         _ptr(out), out.stride(0), _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_cost_points")
+    return out
+
+
+def _as_batched(X, Y, a, b):
+    import torch
+    single = X.dim() == 2
+    if single:
+        X, Y, a, b = X[None], Y[None], a[None], b[None]
+    _check_dev(X, torch.float32, "X", 3)
+    _check_dev(Y, torch.float32, "Y", 3)
+    _check_dev(a, torch.float64, "a", 2)
+    _check_dev(b, torch.float64, "b", 2)
+    B, n, d = X.shape
+    if Y.shape[0] != B or Y.shape[2] != d or a.shape != (B, n) or b.shape != (B, Y.shape[1]):
+        raise ValueError("inconsistent point-cloud batch shapes")
+    return single, X.contiguous(), Y.contiguous(), a.contiguous(), b.contiguous()
+
+
+def solve_points(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e-6, method=ACC,
+                 max_iter=100000, mu0=None, m0=None, w_rule=None, flags=0, raise_on_error=True):
+    """EOT between point clouds.  X [n,d] / [B,n,d] float32, a [n] / [B,n] float64.
+
+    Returns (f, g, results): f, g shaped like a, b; results a list of dicts.
+    """
+    import torch
+    single, X, Y, a, b = _as_batched(X, Y, a, b)
+    B, n, d = X.shape
+    m = Y.shape[1]
+    f = torch.empty((B, n), dtype=torch.float64, device=X.device)
+    g = torch.empty((B, m), dtype=torch.float64, device=X.device)
+    p = default_params(method=method, eps=float(eps), tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0,
+                       w_rule=w_rule, split=int(split), flags=int(flags))
+    res = (Result * B)()
+    st = _points_lib().accsk_solve_points_batched(_ptr(X), _ptr(Y), B, n, m, d, int(kind), float(cost_scale),
+                                                  _ptr(a), _ptr(b), ctypes.byref(p), _ptr(f), _ptr(g), res,
+                                                  _stream_ptr())
+    if raise_on_error and st not in (OK, NOT_CONVERGED):
+        raise AccskError(st, "accsk_solve_points_batched")
+    out = [r.to_dict() for r in res]
+    if single:
+        return f[0], g[0], out
+    return f, g, out
+
+
+def backward_points(X, Y, a, b, f, g, eps, kind=SQEUCLID, cost_scale=1.0, grad_scale=None, marginals=True):
+    """Envelope-theorem gradients of EOT at potentials (f, g).
+
+    Returns (dX, dY, da, db) shaped like the inputs (da, db None if not asked).
+    grad_scale: None or float64 device tensor [B] (or scalar tensor for one problem).
+    """
+    import torch
+    single, X, Y, a, b = _as_batched(X, Y, a, b)
+    B, n, d = X.shape
+    m = Y.shape[1]
+    f = f.reshape(B, n).contiguous()
+    g = g.reshape(B, m).contiguous()
+    _check_dev(f, torch.float64, "f")
+    _check_dev(g, torch.float64, "g")
+    dX = torch.empty_like(X)
+    dY = torch.empty_like(Y)
+    da = torch.empty_like(a) if marginals else None
+    db = torch.empty_like(b) if marginals else None
+    gs = None
+    if grad_scale is not None:
+        gs = grad_scale.to(device=X.device, dtype=torch.float64).reshape(B).contiguous()
+    st = _points_lib().accsk_backward_points(
+        _ptr(X), _ptr(Y), B, n, m, d, int(kind), float(cost_scale), float(eps), _ptr(a), _ptr(b), _ptr(f),
+        _ptr(g), _ptr(gs) if gs is not None else None, _ptr(dX), _ptr(dY),
+        _ptr(da) if da is not None else None, _ptr(db) if db is not None else None, _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_backward_points")
+    if single:
+        return dX[0], dY[0], (da[0] if marginals else None), (db[0] if marginals else None)
+    return dX, dY, da, db
+
+
+def _eot_function():
+    import torch
+
+    class EOTLoss(torch.autograd.Function):
+        """EOT value of point-cloud problems, differentiable in X, Y, a, b.
+
+        Forward solves with the library and returns the FP64 EOT values [B];
+        backward applies the envelope-theorem gradients (dEOT/dC = P) scaled
+        by the incoming gradient, all in the library's kernels.
+        """
+
+        @staticmethod
+        def forward(ctx, X, Y, a, b, eps, kind, cost_scale, split, tol, method):
+            f, g, res = solve_points(X, Y, a, b, eps, kind=kind, cost_scale=cost_scale, split=split, tol=tol,
+                                     method=method)
+            ctx.save_for_backward(X, Y, a, b, f, g)
+            ctx.cfg = (eps, kind, cost_scale)
+            vals = torch.tensor([r["eot_value"] for r in res], dtype=torch.float64, device=X.device)
+            return vals[0] if X.dim() == 2 else vals
+
+        @staticmethod
+        def backward(ctx, grad):
+            X, Y, a, b, f, g = ctx.saved_tensors
+            eps, kind, cost_scale = ctx.cfg
+            dX, dY, da, db = backward_points(X, Y, a, b, f, g, eps, kind=kind, cost_scale=cost_scale,
+                                             grad_scale=grad.detach().to(torch.float64),
+                                             marginals=ctx.needs_input_grad[2] or ctx.needs_input_grad[3])
+            return dX, dY, da, db, None, None, None, None, None, None
+
+    return EOTLoss
+
+
+_EOT = None
+
+
+def eot_loss(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e-6, method=ACC):
+    """Differentiable EOT value (torch.autograd) between point clouds; see EOTLoss."""
+    global _EOT
+    if _EOT is None:
+        _EOT = _eot_function()
+    return _EOT.apply(X, Y, a, b, eps, kind, cost_scale, split, tol, method)

@@ -16,7 +16,7 @@ extern "C" void accsk_default_params(accsk_params *p) {
     p->max_iter = 100000;
     p->mu0 = kDefaultMu0;
     p->m0 = kDefaultM0;
-    p->split = 3;
+    p->split = 0;
     p->flags = 0;
 }
 

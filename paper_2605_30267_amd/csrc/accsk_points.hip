@@ -1,0 +1,416 @@
+// Costs built from point clouds, point-cloud solves, and the backward pass.
+//
+// Costs (paper Sec. 5): squared Euclidean C_ij = ||x_i - y_j||^2 / s (colour
+// transfer) and cosine C_ij = (1 - <x_i, y_j>) / s (word alignment).
+//
+// The cross term X Y^T is the only dense contraction of the method.  Two ways
+// to form it:
+//  * split = 0: FP64 dot products on the vector ALUs (exact up to the final
+//    rounding of C to FP32);
+//  * split = 2 or 3: BF16 matrix cores (v_mfma_f32_16x16x32_bf16) on a split
+//    of each FP32 operand into 2 or 3 BF16 pieces, x = x_hi + x_mid + x_lo.
+//    split 2 keeps hi*hi + hi*lo + lo*hi (pieces down to 2^-16 relative),
+//    split 3 adds hi*mid, mid*hi, mid*mid (down to 2^-24).  Each product of
+//    each 32-wide K chunk is accumulated separately in FP32 by the matrix core
+//    and the partial sums are added in FP64, small terms first.
+// The cost error is amplified by 1/eps in the exponent, so the split depth is
+// chosen by the caller and its error is measured by the tests.
+//
+// Backward (envelope theorem; the paper's primal map eq:P-from-dual gives
+// dEOT/dC = P): with P_ij = exp((f_i + g_j - C_ij)/eps) recomputed tile by
+// tile (never stored),
+//   sq-Euclidean: dX_i = (2/s) (r_i x_i - sum_j P_ij y_j),
+//                 dY_j = (2/s) (c_j y_j - sum_i P_ij x_i),
+//   cosine:       dX_i = -(1/s) sum_j P_ij y_j,  dY_j = -(1/s) sum_i P_ij x_i,
+//   da_i = (f_i - <f, a_hat>) / sum(a),  db_j = (g_j - <g, b_hat>) / sum(b),
+// where r, c are the plan's row and column sums and a_hat = a / sum(a).
+
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "accsk_common.h"
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                               accsk_result *res, hipStream_t s);
+
+namespace accsk {
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ---------------------------------------------------------------------------
+// Row norms ||x_i||^2 in FP64
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void row_norms(const float *__restrict__ X, long long rows, long long d,
+                                                 double *__restrict__ out) {
+    const long long i = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= rows) return;
+    double s = 0.0;
+    for (long long k = lane; k < d; k += 64) {
+        const double v = X[i * d + k];
+        s = fma(v, v, s);
+    }
+    s = wave_sum(s);
+    if (lane == 0) out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 cost tile: block 16x16 outputs, X and Y rows staged in LDS.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(256) void cost_fp64(const float *__restrict__ X, const float *__restrict__ Y,
+                                                 long long n, long long m, long long d, double inv_s,
+                                                 float *__restrict__ C, long long ldc) {
+    extern __shared__ float sm[];
+    float *xs = sm;           // [16][d]
+    float *ys = sm + 16 * d;  // [16][d]
+    const long long i0 = (long long)blockIdx.y * 16, j0 = (long long)blockIdx.x * 16;
+    for (long long t = threadIdx.x; t < 16 * d; t += 256) {
+        const long long r = t / d, k = t % d;
+        xs[t] = (i0 + r < n) ? X[(i0 + r) * d + k] : 0.f;
+        ys[t] = (j0 + r < m) ? Y[(j0 + r) * d + k] : 0.f;
+    }
+    __syncthreads();
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    const long long i = i0 + r, j = j0 + c;
+    double acc = 0.0;
+    for (long long k = 0; k < d; k++) {
+        const double xv = xs[r * d + k], yv = ys[c * d + k];
+        if (KIND == ACCSK_SQEUCLID) {
+            const double t = xv - yv;
+            acc = fma(t, t, acc);
+        } else {
+            acc = fma(xv, yv, acc);
+        }
+    }
+    if (i < n && j < m) C[i * ldc + j] = (float)((KIND == ACCSK_SQEUCLID ? acc : 1.0 - acc) * inv_s);
+}
+
+// ---------------------------------------------------------------------------
+// BF16-split matrix-core cost tile.  One wave computes a 16x16 tile with
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16)..+7] and
+// B[8(l/16)..+7][l%16], and receives D[4(l/16)+i][l%16], i = 0..3.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &mi, __bf16 &lo) {
+    h = (__bf16)v;
+    const float r1 = v - (float)h;
+    mi = (__bf16)r1;
+    lo = (__bf16)(r1 - (float)mi);
+}
+
+template <int SPLIT, int KIND>
+__global__ __launch_bounds__(256) void cost_mfma(const float *__restrict__ X, const float *__restrict__ Y,
+                                                 const double *__restrict__ nx, const double *__restrict__ ny,
+                                                 long long n, long long m, long long d, double inv_s,
+                                                 float *__restrict__ C, long long ldc) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // block tile 32 x 32: wave (wid>>1, wid&1) owns the 16x16 sub-tile
+    const long long i0 = (long long)blockIdx.y * 32 + (wid >> 1) * 16;
+    const long long j0 = (long long)blockIdx.x * 32 + (wid & 1) * 16;
+    const int rr = lane & 15, kq = (lane >> 4) * 8;
+    const long long ia = std::min(i0 + rr, n - 1), jb = std::min(j0 + rr, m - 1);
+    const float *xrow = X + ia * d, *yrow = Y + jb * d;
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long k0 = 0; k0 < d; k0 += 32) {
+        bf16x8 ah, am, al, bh, bm, bl;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const long long k = k0 + kq + e;
+            const float xv = k < d ? xrow[k] : 0.f;
+            const float yv = k < d ? yrow[k] : 0.f;
+            __bf16 h, mi, lo;
+            split3(xv, h, mi, lo);
+            ah[e] = h;
+            am[e] = mi;
+            al[e] = lo;
+            split3(yv, h, mi, lo);
+            bh[e] = h;
+            bm[e] = mi;
+            bl[e] = lo;
+        }
+        const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+        // SPLIT 2 treats mid as the low piece (x = hi + mid to 2^-16)
+        const floatx4 p_hl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, SPLIT == 2 ? bm : bl, z, 0, 0, 0);
+        const floatx4 p_lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(SPLIT == 2 ? am : al, bh, z, 0, 0, 0);
+        floatx4 p_mm = z, p_hm = z, p_mh = z;
+        if (SPLIT == 3) {
+            p_mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, z, 0, 0, 0);
+            p_hm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, z, 0, 0, 0);
+            p_mh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, z, 0, 0, 0);
+        }
+        const floatx4 p_hh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, z, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            double small = (double)p_hl[q] + (double)p_lh[q];
+            if (SPLIT == 3) small += (double)p_mm[q] + ((double)p_hm[q] + (double)p_mh[q]);
+            g[q] += small + (double)p_hh[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const long long i = i0 + (lane >> 4) * 4 + q, j = j0 + (lane & 15);
+        if (i < n && j < m) {
+            const double v = KIND == ACCSK_SQEUCLID ? fmax(nx[i] + ny[j] - 2.0 * g[q], 0.0) : 1.0 - g[q];
+            C[i * ldc + j] = (float)(v * inv_s);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: one kernel per side.  A block owns 16 rows of one problem (rows
+// side) and walks all columns in chunks of 64: P chunk (16 x 64) in LDS, then
+// sum_j P_ij y_j for its 16 rows and d features, and the row sums r_i.
+// The cost is recomputed in FP64 from the points.  The column side is the same
+// with X and Y (and f and g) exchanged.
+// ---------------------------------------------------------------------------
+constexpr int kBR = 16, kBC = 64;
+
+template <int KIND>
+__global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, const float *__restrict__ Y,
+                                                 long long n, long long m, long long d, double inv_s,
+                                                 double inv_eps, const double *__restrict__ f,
+                                                 const double *__restrict__ g, const double *__restrict__ gsc,
+                                                 float *__restrict__ dX, long long sX, long long sY,
+                                                 long long sf, long long sg) {
+    // batch index blockIdx.y; this block: rows [i0, i0+16) of X against all rows of Y
+    extern __shared__ float sm[];
+    const long long bidx = blockIdx.y;
+    const double gscale = gsc ? gsc[bidx] : 1.0;
+    X += bidx * sX;
+    Y += bidx * sY;
+    f += bidx * sf;
+    g += bidx * sg;
+    dX += bidx * sX;
+    float *xs = sm;                       // [16][d]
+    float *ys = xs + kBR * d;             // [64][d]
+    float *ps = ys + kBC * d;             // [16][64]
+    const long long i0 = (long long)blockIdx.x * kBR;
+    const int tid = threadIdx.x;
+    for (long long t = tid; t < kBR * d; t += 256) {
+        const long long r = t / d;
+        xs[t] = (i0 + r < n) ? X[(i0 + r) * d + (t % d)] : 0.f;
+    }
+    // each thread accumulates (row tr, features tk, tk+16, ...) of sum_j P_ij y_j
+    const int tr = tid >> 4, tk = tid & 15;
+    double acc[32];
+    const int nk = (int)((d - tk + 15) / 16);  // features handled by this thread (<= 32: d <= 512)
+#pragma unroll
+    for (int q = 0; q < 32; q++) acc[q] = 0.0;
+    double rs = 0.0;
+    for (long long j0 = 0; j0 < m; j0 += kBC) {
+        __syncthreads();
+        for (long long t = tid; t < kBC * d; t += 256) {
+            const long long r = t / d;
+            ys[t] = (j0 + r < m) ? Y[(j0 + r) * d + (t % d)] : 0.f;
+        }
+        __syncthreads();
+        // P chunk: 16 x 64 = 1024 entries, 4 per thread
+        for (int e = tid; e < kBR * kBC; e += 256) {
+            const int r = e / kBC, c = e % kBC;
+            const long long i = i0 + r, j = j0 + c;
+            float pv = 0.f;
+            if (i < n && j < m) {
+                double acc_c = 0.0;
+                for (long long k = 0; k < d; k++) {
+                    const double xv = xs[r * d + k], yv = ys[c * d + k];
+                    if (KIND == ACCSK_SQEUCLID) {
+                        const double t = xv - yv;
+                        acc_c = fma(t, t, acc_c);
+                    } else {
+                        acc_c = fma(xv, yv, acc_c);
+                    }
+                }
+                const double cij = (KIND == ACCSK_SQEUCLID ? acc_c : 1.0 - acc_c) * inv_s;
+                pv = (float)exp((f[i] + g[j] - cij) * inv_eps);
+            }
+            ps[e] = pv;
+        }
+        __syncthreads();
+        for (int c = 0; c < kBC; c++) {
+            const double pv = ps[tr * kBC + c];
+            if (tk == 0) rs += pv;
+#pragma unroll
+            for (int q = 0; q < 32; q++)
+                if (q < nk) acc[q] = fma(pv, (double)ys[c * d + tk + 16 * q], acc[q]);
+        }
+    }
+    const long long i = i0 + tr;
+    // row sum r_i to every thread of the row
+    __shared__ double rsh[kBR];
+    if (tk == 0) rsh[tr] = rs;
+    __syncthreads();
+    if (i >= n) return;
+    const double ri = rsh[tr];
+#pragma unroll
+    for (int q = 0; q < 32; q++) {
+        if (q >= nk) break;
+        const long long k = tk + 16 * q;
+        double v;
+        if (KIND == ACCSK_SQEUCLID) v = 2.0 * inv_s * (ri * (double)xs[tr * d + k] - acc[q]);
+        else v = -inv_s * acc[q];
+        dX[i * d + k] = (float)(gscale * v);
+    }
+}
+
+__global__ __launch_bounds__(256) void grad_marginal(const double *__restrict__ pot, const double *__restrict__ w,
+                                                     long long len, long long sp, long long sw,
+                                                     const double *__restrict__ gsc, double *__restrict__ out) {
+    const double gscale = gsc ? gsc[blockIdx.x] : 1.0;
+    // out = gscale * (pot - <pot, w_hat>) / sum(w), one block per problem
+    __shared__ double red[2][4];
+    pot += blockIdx.x * sp;
+    w += blockIdx.x * sw;
+    out += blockIdx.x * sp;
+    double s1 = 0.0, s2 = 0.0;
+    for (long long i = threadIdx.x; i < len; i += 256) {
+        s1 += pot[i] * w[i];
+        s2 += w[i];
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s1;
+        red[1][threadIdx.x >> 6] = s2;
+    }
+    __syncthreads();
+    const double pw = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double sw_ = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const double mean = pw / sw_;
+    for (long long i = threadIdx.x; i < len; i += 256) out[i] = gscale * (pot[i] - mean) / sw_;
+}
+
+accsk_status build_cost(const float *X, const float *Y, long long n, long long m, long long d, int kind,
+                        double scale, int split, float *C, long long ldc, double *norms_ws, hipStream_t s) {
+    const double inv_s = 1.0 / scale;
+    if (split == 0) {
+        const size_t lds = 2 * 16 * (size_t)d * sizeof(float);
+        if (lds > 64 * 1024) return ACCSK_SHAPE;
+        dim3 grid((unsigned)((m + 15) / 16), (unsigned)((n + 15) / 16));
+        if (kind == ACCSK_SQEUCLID)
+            hipLaunchKernelGGL(cost_fp64<ACCSK_SQEUCLID>, grid, dim3(256), lds, s, X, Y, n, m, d, inv_s, C, ldc);
+        else
+            hipLaunchKernelGGL(cost_fp64<ACCSK_COSINE>, grid, dim3(256), lds, s, X, Y, n, m, d, inv_s, C, ldc);
+    } else {
+        double *nx = norms_ws, *ny = norms_ws + n;
+        if (kind == ACCSK_SQEUCLID) {
+            hipLaunchKernelGGL(row_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d, nx);
+            hipLaunchKernelGGL(row_norms, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, Y, m, d, ny);
+        }
+        dim3 grid((unsigned)((m + 31) / 32), (unsigned)((n + 31) / 32));
+        if (kind == ACCSK_SQEUCLID) {
+            if (split == 2)
+                hipLaunchKernelGGL((cost_mfma<2, ACCSK_SQEUCLID>), grid, dim3(256), 0, s, X, Y, nx, ny, n, m, d, inv_s, C, ldc);
+            else
+                hipLaunchKernelGGL((cost_mfma<3, ACCSK_SQEUCLID>), grid, dim3(256), 0, s, X, Y, nx, ny, n, m, d, inv_s, C, ldc);
+        } else {
+            if (split == 2)
+                hipLaunchKernelGGL((cost_mfma<2, ACCSK_COSINE>), grid, dim3(256), 0, s, X, Y, nx, ny, n, m, d, inv_s, C, ldc);
+            else
+                hipLaunchKernelGGL((cost_mfma<3, ACCSK_COSINE>), grid, dim3(256), 0, s, X, Y, nx, ny, n, m, d, inv_s, C, ldc);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+accsk_status check_points(const float *X, const float *Y, long long n, long long m, long long d, int kind,
+                          double scale, int split) {
+    if (!X || !Y) return ACCSK_INVALID_ARG;
+    if (kind != ACCSK_SQEUCLID && kind != ACCSK_COSINE) return ACCSK_INVALID_ARG;
+    if (!finite_pos(scale)) return ACCSK_INVALID_ARG;
+    if (split != 0 && split != 2 && split != 3) return ACCSK_INVALID_ARG;
+    if (n < 1 || m < 1 || d < 1 || d > 512) return ACCSK_SHAPE;
+    return ACCSK_OK;
+}
+
+}  // namespace
+}  // namespace accsk
+
+using namespace accsk;
+
+extern "C" accsk_status accsk_cost_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                                          double cost_scale, int split, float *C, int64_t ldc, void *stream) {
+    accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, split);
+    if (st != ACCSK_OK) return st;
+    if (!C || ldc < m) return C ? ACCSK_SHAPE : ACCSK_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    double *ws = nullptr;
+    if (split != 0 && hipMallocAsync((void **)&ws, (size_t)(n + m) * 8, s) != hipSuccess) return ACCSK_OOM;
+    st = build_cost(X, Y, n, m, d, kind, cost_scale, split, C, ldc, ws, s);
+    if (ws) (void)hipFreeAsync(ws, s);
+    return st;
+}
+
+extern "C" accsk_status accsk_solve_points_batched(const float *X, const float *Y, int64_t batch, int64_t n,
+                                                   int64_t m, int64_t d, int kind, double cost_scale,
+                                                   const double *a, const double *b, const accsk_params *p,
+                                                   double *f_out, double *g_out, accsk_result *res,
+                                                   void *stream) {
+    if (!p || !a || !b || !f_out || !g_out || !res || batch < 1) return ACCSK_INVALID_ARG;
+    accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, p->split);
+    if (st != ACCSK_OK) return st;
+    if (!finite_pos(p->eps)) return ACCSK_INVALID_ARG;
+    if (m > 8192) return ACCSK_SHAPE;
+    hipStream_t s = (hipStream_t)stream;
+    const long long ldc = (m + 3) / 4 * 4;
+    const size_t cbytes = (size_t)batch * n * ldc * sizeof(float);
+    char *ws = nullptr;
+    if (hipMallocAsync((void **)&ws, cbytes + (size_t)(n + m) * 8 + 256, s) != hipSuccess) return ACCSK_OOM;
+    float *C = (float *)ws;
+    double *nws = (double *)(ws + ((cbytes + 255) & ~size_t(255)));
+    for (int64_t k = 0; k < batch && st == ACCSK_OK; k++)
+        st = build_cost(X + k * n * d, Y + k * m * d, n, m, d, kind, cost_scale, p->split, C + k * n * ldc, ldc,
+                        nws, s);
+    if (st == ACCSK_OK) {
+        std::vector<accsk_problem> probs((size_t)batch);
+        for (int64_t k = 0; k < batch; k++)
+            probs[(size_t)k] = accsk_problem{C + k * n * ldc, n, m, ldc, a + k * n, b + k * m,
+                                             f_out + k * n, g_out + k * m, p->eps};
+        st = accsk_solve_batch(probs.data(), batch, p, res, stream);
+    }
+    (void)hipFreeAsync(ws, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return ACCSK_HIP_ERROR;
+    return st;
+}
+
+extern "C" accsk_status accsk_solve_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                                           double cost_scale, const double *a, const double *b,
+                                           const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
+                                           void *stream) {
+    return accsk_solve_points_batched(X, Y, 1, n, m, d, kind, cost_scale, a, b, p, f_out, g_out, res, stream);
+}
+
+extern "C" accsk_status accsk_backward_points(const float *X, const float *Y, int64_t batch, int64_t n, int64_t m,
+                                              int64_t d, int kind, double cost_scale, double eps, const double *a,
+                                              const double *b, const double *f, const double *g,
+                                              const double *grad_scale, float *dX, float *dY, double *da, double *db,
+                                              void *stream) {
+    accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, 0);
+    if (st != ACCSK_OK) return st;
+    if (!f || !g || !dX || !dY || batch < 1 || !finite_pos(eps))
+        return ACCSK_INVALID_ARG;
+    if (d > 448) return ACCSK_SHAPE;  // X, Y and P tiles staged in on-chip memory
+    hipStream_t s = (hipStream_t)stream;
+    const double inv_s = 1.0 / cost_scale, inv_eps = 1.0 / eps;
+    const size_t lds = ((size_t)(kBR + kBC) * d + kBR * kBC) * sizeof(float);
+    dim3 gx((unsigned)((n + kBR - 1) / kBR), (unsigned)batch), gy((unsigned)((m + kBR - 1) / kBR), (unsigned)batch);
+    if (kind == ACCSK_SQEUCLID) {
+        hipLaunchKernelGGL(grad_side<ACCSK_SQEUCLID>, gx, dim3(256), lds, s, X, Y, n, m, d, inv_s, inv_eps, f, g,
+                           grad_scale, dX, n * d, m * d, n, m);
+        hipLaunchKernelGGL(grad_side<ACCSK_SQEUCLID>, gy, dim3(256), lds, s, Y, X, m, n, d, inv_s, inv_eps, g, f,
+                           grad_scale, dY, m * d, n * d, m, n);
+    } else {
+        hipLaunchKernelGGL(grad_side<ACCSK_COSINE>, gx, dim3(256), lds, s, X, Y, n, m, d, inv_s, inv_eps, f, g,
+                           grad_scale, dX, n * d, m * d, n, m);
+        hipLaunchKernelGGL(grad_side<ACCSK_COSINE>, gy, dim3(256), lds, s, Y, X, m, n, d, inv_s, inv_eps, g, f,
+                           grad_scale, dY, m * d, n * d, m, n);
+    }
+    if (da && a) hipLaunchKernelGGL(grad_marginal, dim3((unsigned)batch), dim3(256), 0, s, f, a, n, n, n, grad_scale, da);
+    if (db && b) hipLaunchKernelGGL(grad_marginal, dim3((unsigned)batch), dim3(256), 0, s, g, b, m, m, m, grad_scale, db);
+    return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
