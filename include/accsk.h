@@ -210,6 +210,72 @@ accsk_status accsk_backward_points(const float *X, const float *Y, int64_t batch
                                    const double *b, const double *f, const double *g, const double *grad_scale,
                                    float *dX, float *dY, double *da, double *db, void *stream);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Serving loop (continuous batching of point-cloud requests).
+ *
+ * A server owns one persistent kernel on its own stream: requests of uneven
+ * (n, m, eps) are admitted while others run, each is solved by one workgroup
+ * (cost built on the device, then the Sec. 4 Algorithms A2MD / A2MD-homotopy
+ * with the Sec. 2 row solve, stop on eq:l1tol per request), and each retires
+ * on its own test.  Admission is by HBM footprint: every request needs an
+ * n x ceil4(m) FP32 cost block from the server's arena of hbm_budget bytes; a
+ * request waits until a block fits (later requests that fit may go first).
+ * Results do not depend on which other requests are in flight.
+ * ---------------------------------------------------------------------------
+ */
+typedef struct accsk_request {
+    const float *X;      /* device FP32 n x d, rows contiguous */
+    const float *Y;      /* device FP32 m x d */
+    int64_t n, m, d;     /* 1 <= n, m <= 512, 1 <= d <= 512 */
+    int32_t kind;        /* ACCSK_SQEUCLID or ACCSK_COSINE */
+    int32_t reserved;    /* 0 */
+    double cost_scale;   /* s > 0: C = raw cost / s */
+    const double *a;     /* device FP64 [n], positive (normalized inside) */
+    const double *b;     /* device FP64 [m] */
+    double eps;          /* > 0 */
+    double *f_out;       /* device FP64 [n] */
+    double *g_out;       /* device FP64 [m] */
+} accsk_request;
+
+typedef struct accsk_server accsk_server;
+
+/*
+ * Creates a server on the current device.  hbm_budget: bytes of the cost
+ * arena (allocated here).  max_slots: worker workgroups (requests solved at
+ * once), 0 = as many as stay resident (up to three per compute unit, minus
+ * one for the dispatcher).  p: method, tol, max_iter, mu0, m0, w_rule, flags and the
+ * cost split (0, 2, 3) used for every request (p->eps is ignored).
+ * Returns ACCSK_OOM if the arena cannot be allocated.
+ */
+accsk_status accsk_server_create(size_t hbm_budget, int max_slots, const accsk_params *p, accsk_server **out);
+
+/*
+ * Queues one request and returns its ticket.  The request's buffers must stay
+ * valid (and unchanged) until accsk_server_poll reports it done; they must be
+ * ready when submitted (synchronize their producers first).  Errors:
+ * INVALID_ARG, SHAPE (limits above), OOM (cost block larger than the whole
+ * budget), HIP_ERROR (an earlier launch failed).
+ */
+accsk_status accsk_server_submit(accsk_server *srv, const accsk_request *req, uint64_t *ticket);
+
+/*
+ * Non-blocking: *done = 1 and *res filled once the request has finished
+ * (res->kernel_ms = its time on the device); the ticket is then released.
+ * times (optional, 3 doubles): submit, admission and completion instants on
+ * the accsk_clock_seconds() clock.  INVALID_ARG for an unknown ticket.
+ */
+accsk_status accsk_server_poll(accsk_server *srv, uint64_t ticket, accsk_result *res, int *done, double *times);
+
+/* info[5]: worker workgroups, waiting requests, requests in flight, kernel launches, free arena bytes. */
+accsk_status accsk_server_info(accsk_server *srv, int64_t *info);
+
+/* Stops the persistent kernel once the requests in flight have finished, and frees the server. */
+accsk_status accsk_server_destroy(accsk_server *srv);
+
+/* Monotonic host clock (seconds) used for the serving timestamps. */
+double accsk_clock_seconds(void);
+
 #ifdef __cplusplus
 }
 #endif

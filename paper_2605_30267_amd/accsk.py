@@ -388,3 +388,134 @@ def eot_loss(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e-6, 
     if _EOT is None:
         _EOT = _eot_function()
     return _EOT.apply(X, Y, a, b, eps, kind, cost_scale, split, tol, method)
+
+
+# ---------------------------------------------------------------------------
+# Serving loop
+# ---------------------------------------------------------------------------
+
+class Request(ctypes.Structure):
+    _fields_ = [("X", _vp), ("Y", _vp), ("n", _i64), ("m", _i64), ("d", _i64), ("kind", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("cost_scale", _dbl), ("a", _vp), ("b", _vp), ("eps", _dbl),
+                ("f_out", _vp), ("g_out", _vp)]
+
+
+def _register_server(L):
+    if getattr(L, "_server_ready", False):
+        return
+    L.accsk_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(Params),
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    L.accsk_server_create.restype = ctypes.c_int
+    L.accsk_server_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.accsk_server_submit.restype = ctypes.c_int
+    L.accsk_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.accsk_server_poll.restype = ctypes.c_int
+    L.accsk_server_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+    L.accsk_server_info.restype = ctypes.c_int
+    L.accsk_server_destroy.argtypes = [_vp]
+    L.accsk_server_destroy.restype = ctypes.c_int
+    L.accsk_clock_seconds.argtypes = []
+    L.accsk_clock_seconds.restype = ctypes.c_double
+    L._server_ready = True
+
+
+def clock_seconds():
+    L = lib()
+    _register_server(L)
+    return L.accsk_clock_seconds()
+
+
+class Server:
+    """Persistent serving loop (continuous batching of point-cloud requests).
+
+    submit() queues a request and returns a ticket; poll() returns None until
+    the request is done, then (f, g, result dict, (t_submit, t_admit, t_done)).
+    The request's tensors are kept alive here until it is done.
+    """
+
+    def __init__(self, hbm_budget=1 << 30, max_slots=0, method=ACC, tol=1e-6, max_iter=100000, mu0=None, m0=None,
+                 w_rule=None, split=0, flags=0):
+        L = lib()
+        _register_server(L)
+        self._L = L
+        p = default_params(method=method, tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0, w_rule=w_rule,
+                           split=int(split), flags=int(flags))
+        h = ctypes.c_void_p()
+        st = L.accsk_server_create(int(hbm_budget), int(max_slots), ctypes.byref(p), ctypes.byref(h))
+        if st != OK:
+            raise AccskError(st, "accsk_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0):
+        import torch
+        _check_dev(X, torch.float32, "X", 2)
+        _check_dev(Y, torch.float32, "Y", 2)
+        _check_dev(a, torch.float64, "a", 1)
+        _check_dev(b, torch.float64, "b", 1)
+        X, Y, a, b = X.contiguous(), Y.contiguous(), a.contiguous(), b.contiguous()
+        n, d = X.shape
+        m = Y.shape[0]
+        if Y.shape[1] != d or a.shape[0] != n or b.shape[0] != m:
+            raise ValueError("inconsistent request shapes")
+        f = torch.empty(n, dtype=torch.float64, device=X.device)
+        g = torch.empty(m, dtype=torch.float64, device=X.device)
+        req = Request(X.data_ptr(), Y.data_ptr(), n, m, d, int(kind), 0, float(cost_scale), a.data_ptr(),
+                      b.data_ptr(), float(eps), f.data_ptr(), g.data_ptr())
+        t = ctypes.c_uint64()
+        st = self._L.accsk_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if st != OK:
+            raise AccskError(st, "accsk_server_submit")
+        self._live[t.value] = (X, Y, a, b, f, g)
+        return t.value
+
+    def poll(self, ticket):
+        r = Result()
+        done = ctypes.c_int()
+        times = (ctypes.c_double * 3)()
+        st = self._L.accsk_server_poll(self._h, ticket, ctypes.byref(r), ctypes.byref(done), times)
+        if st != OK:
+            raise AccskError(st, "accsk_server_poll")
+        if not done.value:
+            return None
+        X, Y, a, b, f, g = self._live.pop(ticket)
+        return f, g, r.to_dict(), (times[0], times[1], times[2])
+
+    def wait(self, ticket, timeout=60.0):
+        import time
+        t0 = time.monotonic()
+        while True:
+            out = self.poll(ticket)
+            if out is not None:
+                return out
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError("request %d not done after %.1f s" % (ticket, timeout))
+            time.sleep(20e-6)
+
+    def info(self):
+        v = (ctypes.c_int64 * 5)()
+        st = self._L.accsk_server_info(self._h, v)
+        if st != OK:
+            raise AccskError(st, "accsk_server_info")
+        return dict(workers=v[0], waiting=v[1], in_flight=v[2], launches=v[3], free_bytes=v[4])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            st = self._L.accsk_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+            if st != OK:
+                raise AccskError(st, "accsk_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

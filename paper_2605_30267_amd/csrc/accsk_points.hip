@@ -8,11 +8,11 @@
 //  * split = 0: FP64 dot products on the vector ALUs (exact up to the final
 //    rounding of C to FP32);
 //  * split = 2 or 3: BF16 matrix cores (v_mfma_f32_16x16x32_bf16) on a split
-//    of each FP32 operand into 2 or 3 BF16 pieces, x = x_hi + x_mid + x_lo.
-//    split 2 keeps hi*hi + hi*lo + lo*hi (pieces down to 2^-16 relative),
-//    split 3 adds hi*mid, mid*hi, mid*mid (down to 2^-24).  Each product of
+//    of each FP32 operand into 2 or 3 BF16 pieces, x = x_hi + x_mid (+ x_lo).
+//    split 2 keeps hi*hi + hi*mid + mid*hi (pieces down to 2^-16 relative),
+//    split 3 adds mid*mid, hi*lo, lo*hi (down to 2^-24).  Each product of
 //    each 32-wide K chunk is accumulated separately in FP32 by the matrix core
-//    and the partial sums are added in FP64, small terms first.
+//    and the partial sums are added in FP64, small terms first (cost_tiles.h).
 // The cost error is amplified by 1/eps in the exponent, so the split depth is
 // chosen by the caller and its error is measured by the tests.
 //
@@ -31,9 +31,7 @@
 #include <vector>
 
 #include "accsk_common.h"
-
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+#include "cost_tiles.h"
 
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
                                accsk_result *res, hipStream_t s);
@@ -51,12 +49,7 @@ __global__ __launch_bounds__(256) void row_norms(const float *__restrict__ X, lo
     const long long i = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= rows) return;
-    double s = 0.0;
-    for (long long k = lane; k < d; k += 64) {
-        const double v = X[i * d + k];
-        s = fma(v, v, s);
-    }
-    s = wave_sum(s);
+    const double s = row_norm_wave(X + i * d, d, lane);
     if (lane == 0) out[i] = s;
 }
 
@@ -79,31 +72,13 @@ __global__ __launch_bounds__(256) void cost_fp64(const float *__restrict__ X, co
     __syncthreads();
     const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
     const long long i = i0 + r, j = j0 + c;
-    double acc = 0.0;
-    for (long long k = 0; k < d; k++) {
-        const double xv = xs[r * d + k], yv = ys[c * d + k];
-        if (KIND == ACCSK_SQEUCLID) {
-            const double t = xv - yv;
-            acc = fma(t, t, acc);
-        } else {
-            acc = fma(xv, yv, acc);
-        }
-    }
-    if (i < n && j < m) C[i * ldc + j] = (float)((KIND == ACCSK_SQEUCLID ? acc : 1.0 - acc) * inv_s);
+    const double acc = cross_fp64<KIND>(xs + r * d, ys + c * d, d);
+    if (i < n && j < m) C[i * ldc + j] = finish_fp64<KIND>(acc, inv_s);
 }
 
 // ---------------------------------------------------------------------------
-// BF16-split matrix-core cost tile.  One wave computes a 16x16 tile with
-// v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16)..+7] and
-// B[8(l/16)..+7][l%16], and receives D[4(l/16)+i][l%16], i = 0..3.
+// BF16-split matrix-core cost: block tile 32 x 32, one 16 x 16 tile per wave.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &mi, __bf16 &lo) {
-    h = (__bf16)v;
-    const float r1 = v - (float)h;
-    mi = (__bf16)r1;
-    lo = (__bf16)(r1 - (float)mi);
-}
-
 template <int SPLIT, int KIND>
 __global__ __launch_bounds__(256) void cost_mfma(const float *__restrict__ X, const float *__restrict__ Y,
                                                  const double *__restrict__ nx, const double *__restrict__ ny,
@@ -113,52 +88,15 @@ __global__ __launch_bounds__(256) void cost_mfma(const float *__restrict__ X, co
     // block tile 32 x 32: wave (wid>>1, wid&1) owns the 16x16 sub-tile
     const long long i0 = (long long)blockIdx.y * 32 + (wid >> 1) * 16;
     const long long j0 = (long long)blockIdx.x * 32 + (wid & 1) * 16;
-    const int rr = lane & 15, kq = (lane >> 4) * 8;
+    const int rr = lane & 15;
     const long long ia = std::min(i0 + rr, n - 1), jb = std::min(j0 + rr, m - 1);
-    const float *xrow = X + ia * d, *yrow = Y + jb * d;
-    double g[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long k0 = 0; k0 < d; k0 += 32) {
-        bf16x8 ah, am, al, bh, bm, bl;
-#pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const long long k = k0 + kq + e;
-            const float xv = k < d ? xrow[k] : 0.f;
-            const float yv = k < d ? yrow[k] : 0.f;
-            __bf16 h, mi, lo;
-            split3(xv, h, mi, lo);
-            ah[e] = h;
-            am[e] = mi;
-            al[e] = lo;
-            split3(yv, h, mi, lo);
-            bh[e] = h;
-            bm[e] = mi;
-            bl[e] = lo;
-        }
-        const floatx4 z = {0.f, 0.f, 0.f, 0.f};
-        // SPLIT 2 treats mid as the low piece (x = hi + mid to 2^-16)
-        const floatx4 p_hl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, SPLIT == 2 ? bm : bl, z, 0, 0, 0);
-        const floatx4 p_lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(SPLIT == 2 ? am : al, bh, z, 0, 0, 0);
-        floatx4 p_mm = z, p_hm = z, p_mh = z;
-        if (SPLIT == 3) {
-            p_mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, z, 0, 0, 0);
-            p_hm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, z, 0, 0, 0);
-            p_mh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, z, 0, 0, 0);
-        }
-        const floatx4 p_hh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, z, 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            double small = (double)p_hl[q] + (double)p_lh[q];
-            if (SPLIT == 3) small += (double)p_mm[q] + ((double)p_hm[q] + (double)p_mh[q]);
-            g[q] += small + (double)p_hh[q];
-        }
-    }
+    double g[4];
+    mfma_cross_tile<SPLIT>(X + ia * d, Y + jb * d, d, lane, g);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const long long i = i0 + (lane >> 4) * 4 + q, j = j0 + (lane & 15);
-        if (i < n && j < m) {
-            const double v = KIND == ACCSK_SQEUCLID ? fmax(nx[i] + ny[j] - 2.0 * g[q], 0.0) : 1.0 - g[q];
-            C[i * ldc + j] = (float)(v * inv_s);
-        }
+        if (i < n && j < m) C[i * ldc + j] = finish_mfma<KIND>(g[q], KIND == ACCSK_SQEUCLID ? nx[i] : 0.0,
+                                                                KIND == ACCSK_SQEUCLID ? ny[j] : 0.0, inv_s);
     }
 }
 
@@ -216,16 +154,7 @@ __global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, co
             const long long i = i0 + r, j = j0 + c;
             float pv = 0.f;
             if (i < n && j < m) {
-                double acc_c = 0.0;
-                for (long long k = 0; k < d; k++) {
-                    const double xv = xs[r * d + k], yv = ys[c * d + k];
-                    if (KIND == ACCSK_SQEUCLID) {
-                        const double t = xv - yv;
-                        acc_c = fma(t, t, acc_c);
-                    } else {
-                        acc_c = fma(xv, yv, acc_c);
-                    }
-                }
+                const double acc_c = cross_fp64<KIND>(xs + r * d, ys + c * d, d);
                 const double cij = (KIND == ACCSK_SQEUCLID ? acc_c : 1.0 - acc_c) * inv_s;
                 pv = (float)exp((f[i] + g[j] - cij) * inv_eps);
             }

@@ -1,420 +1,25 @@
-// Small-problem solver: one workgroup owns one dense problem (m <= 1024,
-// n <= 4096).  Used for batches of independent problems and by the serving
-// loop.  No grid-wide barrier: every reduction is inside the workgroup.
-//
-// Layout of the work inside a workgroup of NW waves:
-//  * a row is handled by LPR lanes (16 or 64); a wave therefore works on
-//    64/LPR rows at a time, the workgroup on NW*64/LPR rows;
-//  * lane li of a row owns the float4 column groups li, li+LPR, ... (NCL
-//    columns), so the loads of one row are contiguous;
-//  * row max and row sum are butterfly reductions over the LPR lanes (DPP
-//    inside a 16-lane row, xor shuffles across rows), so every lane of the
-//    row holds the result and no barrier is needed per row;
-//  * column sums are accumulated per lane in FP64 and combined across the
-//    rows of a wave (xor shuffles) and across waves (LDS, fixed order) once
-//    per Sinkhorn step.
-// The iterate x, the extrapolation variable w, log2 b, and the per-row
-// quantities live in LDS for the whole solve (paper Sec. 4, Algorithms A2MD
-// and A2MD-homotopy; Sec. 2 eq:u-update for the row solve).
+// Batched small-problem solver: one workgroup owns one dense problem (m <= 1024,
+// n <= 4096), no grid-wide barrier; every reduction is inside the workgroup.
+// The per-workgroup solve is small_body (small_body.h), also used by the
+// serving loop.
 
 #include <math.h>
 
 #include <algorithm>
 #include <vector>
 
-#include "accsk_common.h"
+#include "small_body.h"
 
 namespace accsk {
 namespace {
 
-struct SmallProb {
-    const float *C;
-    long long n, m, ldc;
-    const double *a, *b;
-    double *f, *g;
-    double eps;
-};
-
-struct SmallCtl {
-    double tol, tol_stop, mu0;
-    long long max_iter, m0;
-    int method, w_rule, flags;
-};
-
-// ---- butterfly reductions over the LPR lanes of a row (all lanes get the result)
-__device__ __forceinline__ float bfly16_max(float v) {
-    v = fmaxf(v, dpp_f32<0xB1, 0xf, 0xf>(v, v));   // quad_perm [1,0,3,2]
-    v = fmaxf(v, dpp_f32<0x4E, 0xf, 0xf>(v, v));   // quad_perm [2,3,0,1]
-    v = fmaxf(v, dpp_f32<0x141, 0xf, 0xf>(v, v));  // row_half_mirror
-    v = fmaxf(v, dpp_f32<0x140, 0xf, 0xf>(v, v));  // row_mirror
-    return v;
-}
-__device__ __forceinline__ double bfly16_sum(double v) {
-    v += dpp_f64<0xB1, 0xf, 0xf>(v, v);
-    v += dpp_f64<0x4E, 0xf, 0xf>(v, v);
-    v += dpp_f64<0x141, 0xf, 0xf>(v, v);
-    v += dpp_f64<0x140, 0xf, 0xf>(v, v);
-    return v;
-}
-template <int LPR>
-__device__ __forceinline__ float row_max(float v) {
-    v = bfly16_max(v);
-    if (LPR == 64) {
-        v = fmaxf(v, __shfl_xor(v, 16, 64));
-        v = fmaxf(v, __shfl_xor(v, 32, 64));
-    }
-    return v;
-}
-template <int LPR>
-__device__ __forceinline__ double row_sum(double v) {
-    v = bfly16_sum(v);
-    if (LPR == 64) {
-        v += __shfl_xor(v, 16, 64);
-        v += __shfl_xor(v, 32, 64);
-    }
-    return v;
-}
-
-// Deterministic workgroup sum: wave butterfly, then a fixed-order sum of the
-// per-wave values.  `red` holds NW doubles; every thread gets the total.
-template <int NW>
-__device__ __forceinline__ double wg_sum(double v, double *red) {
-    v = wave_sum(v);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; w++) s += red[w];
-    return s;
-}
-template <int NW>
-__device__ __forceinline__ double wg_max(double v, double *red) {
-    v = wave_max(v);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = -INFINITY;
-#pragma unroll
-    for (int w = 0; w < NW; w++) s = fmax(s, red[w]);
-    return s;
-}
-
 template <int NW, int LPR, int NCL, bool VEC>
 __global__ __launch_bounds__(64 * NW) void small_solve(const SmallProb *__restrict__ probs, SmallCtl ctl,
                                                        DevResult *__restrict__ results) {
-    constexpr int TPB = 64 * NW;
-    constexpr int RPW = 64 / LPR;  // rows per wave in flight
-    constexpr int RS = NW * RPW;   // rows per workgroup in flight
-    constexpr int NK = NCL / 4;    // float4 groups per lane
     extern __shared__ double lds[];
     __shared__ double red[NW];
     __shared__ int sflag;
-
-    const SmallProb P = probs[blockIdx.x];
-    DevResult *res = results + blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int li = lane % LPR, rg = lane / LPR, slot = wid * RPW + rg;
-    const int n = (int)P.n, m = (int)P.m;
-    const long long ldc = P.ldc;
-    const double eps = P.eps;
-    const double kap2 = kLog2e / eps;
-
-    double *xl = lds;           // [m] x log2 e
-    double *wl = xl + m;        // [m] w log2 e
-    double *lb2 = wl + m;       // [m] log2 b (normalized)
-    double *bn = lb2 + m;       // [m] b (normalized)
-    double *la2 = bn + m;       // [n] log2 a (normalized)
-    double *rowM = la2 + n;     // [n] row shift of the last strip
-    double *rowS = rowM + n;    // [n] row sum of the last strip
-    double *wpart = rowS + n;   // [NW][m] per-wave column sums
-
-    // ---------------- set-up: validation, unit mass (eq:Fc), logs ----------------
-    int bad = 0;
-    double sa = 0.0, sb = 0.0;
-    for (int i = tid; i < n; i += TPB) {
-        const double v = P.a[i];
-        bad |= !isfinite(v) ? 2 : (!(v > 0.0) ? 1 : 0);
-        sa += v;
-    }
-    for (int j = tid; j < m; j += TPB) {
-        const double v = P.b[j];
-        bad |= !isfinite(v) ? 2 : (!(v > 0.0) ? 1 : 0);
-        sb += v;
-    }
-    if (tid == 0) sflag = 0;
-    __syncthreads();
-    if (bad) atomicOr(&sflag, bad);
-    sa = wg_sum<NW>(sa, red);
-    sb = wg_sum<NW>(sb, red);
-    const int badall = sflag;
-    if (badall) {
-        if (tid == 0) {
-            DevResult r{};
-            r.err = NAN;
-            r.eot = NAN;
-            r.fval = NAN;
-            r.cost = NAN;
-            r.status = (badall & 2) ? ACCSK_NONFINITE : ACCSK_INVALID_ARG;
-            *res = r;
-        }
-        return;
-    }
-    double mx = -INFINITY;
-    for (int i = tid; i < n; i += TPB) {
-        const double l2 = log2(P.a[i] / sa);
-        la2[i] = l2;
-        mx = fmax(mx, l2);
-    }
-    for (int j = tid; j < m; j += TPB) {
-        const double v = P.b[j] / sb;
-        bn[j] = v;
-        lb2[j] = log2(v);
-        xl[j] = 0.0;
-        wl[j] = 0.0;
-    }
-    const double La2 = wg_max<NW>(mx, red);
-    const double maxa = exp2(La2);
-    __syncthreads();
-
-    double mu = ctl.mu0, alpha = sqrt(2.0 * ctl.mu0);
-    long long mstage = ctl.m0, kin = 0, it = 0, steps = 0, fallbacks = 0;
-    bool first = true;
-    int status = ACCSK_OK;
-    double err = 0.0, mass = 0.0, xb2 = 0.0;
-    const int nrows_iter = (n + RS - 1) / RS;
-
-    for (;;) {
-        // ---------------- strip: row solve and column sums from one read ----------------
-        double xr[NCL];
-#pragma unroll
-        for (int k = 0; k < NK; k++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int col = 4 * (li + LPR * k) + e;
-                xr[k * 4 + e] = col < m ? xl[col] : -INFINITY;
-            }
-        double colacc[NCL];
-#pragma unroll
-        for (int q = 0; q < NCL; q++) colacc[q] = 0.0;
-
-        auto load_row = [&](int r, float4 (&v)[NK]) {
-            const int i = min(r, n - 1);
-            const float *row = P.C + (long long)i * ldc;
-#pragma unroll
-            for (int k = 0; k < NK; k++) {
-                const int c0 = 4 * (li + LPR * k);
-                if (VEC) {
-                    v[k] = *reinterpret_cast<const float4 *>(row + min(c0, m - 4));
-                } else {
-                    v[k].x = row[min(c0 + 0, m - 1)];
-                    v[k].y = row[min(c0 + 1, m - 1)];
-                    v[k].z = row[min(c0 + 2, m - 1)];
-                    v[k].w = row[min(c0 + 3, m - 1)];
-                }
-            }
-        };
-        float4 nxt[NK];
-        load_row(slot, nxt);
-        for (int itr = 0; itr < nrows_iter; itr++) {
-            const int r = slot + itr * RS;
-            float4 cur[NK];
-#pragma unroll
-            for (int k = 0; k < NK; k++) cur[k] = nxt[k];
-            if (itr + 1 < nrows_iter) load_row(r + RS, nxt);
-            const bool rv = r < n;
-            double t[NCL];
-            double mloc = -INFINITY;
-#pragma unroll
-            for (int k = 0; k < NK; k++) {
-                const float cv[4] = {cur[k].x, cur[k].y, cur[k].z, cur[k].w};
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    t[k * 4 + e] = fma(-(double)cv[e], kap2, xr[k * 4 + e]);
-                    mloc = fmax(mloc, t[k * 4 + e]);
-                }
-            }
-            const double M = (double)row_max<LPR>((float)mloc);
-            float ev[NCL];
-#pragma unroll
-            for (int q = 0; q < NCL; q++) ev[q] = __builtin_amdgcn_exp2f((float)(t[q] - M));
-            float pv[NCL];
-#pragma unroll
-            for (int q = 0; q < NCL; q++) pv[q] = ev[q];
-#pragma unroll
-            for (int h = 1; h < NCL; h <<= 1)
-#pragma unroll
-                for (int q = 0; q + h < NCL; q += 2 * h) pv[q] += pv[q + h];
-            const double S = row_sum<LPR>((double)pv[0]);
-            // P_ij / max a = e_ij * 2^(log2 a_i - La2) / S_i   (u_i from eq:u-update)
-            const int ri = min(r, n - 1);
-            const float rfac = rv ? __builtin_amdgcn_exp2f((float)(la2[ri] - La2)) * __builtin_amdgcn_rcpf((float)S)
-                                  : 0.f;
-#pragma unroll
-            for (int q = 0; q < NCL; q++) colacc[q] += (double)(ev[q] * rfac);
-            if (li == 0 && rv) {
-                rowM[r] = M;
-                rowS[r] = S;
-            }
-        }
-        // combine the rows of a wave, then the waves (fixed order)
-#pragma unroll
-        for (int q = 0; q < NCL; q++) {
-            double v = colacc[q];
-            if (RPW >= 2) v += __shfl_xor(v, 16, 64);
-            if (RPW >= 4) v += __shfl_xor(v, 32, 64);
-            colacc[q] = v;
-        }
-        if (rg == 0) {
-#pragma unroll
-            for (int k = 0; k < NK; k++)
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int col = 4 * (li + LPR * k) + e;
-                    if (col < m) wpart[wid * m + col] = colacc[k * 4 + e];
-                }
-        }
-        __syncthreads();
-
-        // ---------------- column side: S^_j, error, mass ----------------
-        double aS = 0.0, aE = 0.0, aC = 0.0, aXB = 0.0;
-        int nfb = 0;
-        for (int j = tid; j < m; j += TPB) {
-            double s = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; w++) s += wpart[w * m + j];
-            nfb += (s < 0x1p-64) ? 1 : 0;
-            const double lc2 = La2 + log2(s);  // log2 c_j
-            const double c = s * maxa;
-            const double sh = lb2[j] - lc2 + xl[j];
-            wpart[j] = sh;  // wave 0's slot is free now: keep S^_j there
-            aS += sh;
-            aE += fabs(c - bn[j]);
-            aC += c;
-            aXB += xl[j] * bn[j];
-        }
-        __syncthreads();
-        if (tid == 0) sflag = 0;
-        __syncthreads();
-        if (nfb) atomicAdd(&sflag, nfb);
-        __syncthreads();
-        if (sflag > 0) {
-            // Exact column pass (a column with almost no mass): running max per column.
-            fallbacks++;
-            for (int i = tid; i < n; i += TPB) rowM[i] = la2[i] - (rowM[i] + log2(rowS[i]));  // u_i log2 e
-            __syncthreads();
-            aS = aE = aC = aXB = 0.0;
-            for (int j = tid; j < m; j += TPB) {
-                double cmx = -INFINITY, cs = 0.0;
-                for (int i = 0; i < n; i++) {
-                    const double a2 = fma(-(double)P.C[(long long)i * ldc + j], kap2, rowM[i]);
-                    if (a2 > cmx) {
-                        cs = cs * exp2(cmx - a2) + 1.0;
-                        cmx = a2;
-                    } else {
-                        cs += exp2(a2 - cmx);
-                    }
-                }
-                const double lc2 = cmx + log2(cs) + xl[j];
-                const double c = exp2(lc2);
-                const double sh = lb2[j] - lc2 + xl[j];
-                wpart[j] = sh;
-                aS += sh;
-                aE += fabs(c - bn[j]);
-                aC += c;
-                aXB += xl[j] * bn[j];
-            }
-            __syncthreads();
-            // restore the row shift/sum form: u = la2 - (M + log2 S) with M = la2 - u, S = 1
-            for (int i = tid; i < n; i += TPB) {
-                rowM[i] = la2[i] - rowM[i];
-                rowS[i] = 1.0;
-            }
-        }
-        const double sumS = wg_sum<NW>(aS, red);
-        err = wg_sum<NW>(aE, red);
-        mass = wg_sum<NW>(aC, red);
-        xb2 = wg_sum<NW>(aXB, red);
-        const double mean = sumS / (double)m;
-        steps++;
-        if (!isfinite(err)) {
-            status = (steps == 1) ? ACCSK_NONFINITE : ACCSK_DIVERGED;
-            break;
-        }
-        // ---------------- update (Sinkhorn or Algorithm A2MD with homotopy) ----------------
-        if (ctl.method == ACCSK_SINKHORN) {
-            if (err < ctl.tol_stop || it >= ctl.max_iter) break;
-            for (int j = tid; j < m; j += TPB) xl[j] = wpart[j] - mean;
-            it++;
-        } else {
-            if (!first) {
-                const double c2 = alpha * alpha - 2.0, inv = 1.0 / (1.0 + alpha);
-                for (int j = tid; j < m; j += TPB) wl[j] = (wl[j] + c2 * xl[j] + 2.0 * (wpart[j] - mean)) * inv;
-                it++;
-                kin++;
-            }
-            if (err < ctl.tol_stop || it >= ctl.max_iter) break;
-            if (!first && kin == mstage) {
-                const double mu_new = mu / 2.0;
-                if (ctl.w_rule == ACCSK_W_Y_CONTINUOUS) {
-                    const double ratio = sqrt(2.0 * mu_new) / alpha;
-                    for (int j = tid; j < m; j += TPB) wl[j] *= ratio;
-                }
-                mu = mu_new;
-                alpha = sqrt(2.0 * mu);
-                mstage = (long long)floor(1.4142135623730951 * (double)mstage) + 1;
-                kin = 0;
-            }
-            first = false;
-            const double inv = 1.0 / (1.0 + alpha);
-            for (int j = tid; j < m; j += TPB) xl[j] = (wl[j] + (wpart[j] - mean)) * inv;
-        }
-        __syncthreads();
-    }
-    __syncthreads();
-
-    // ---------------- outputs ----------------
-    double ua = 0.0;
-    for (int i = tid; i < n; i += TPB) {
-        const double u2 = la2[i] - (rowM[i] + log2(rowS[i]));
-        P.f[i] = eps * kLn2 * u2;
-        ua += exp2(la2[i]) * u2;
-        rowM[i] = u2;
-    }
-    for (int j = tid; j < m; j += TPB) P.g[j] = eps * kLn2 * xl[j];
-    ua = wg_sum<NW>(ua, red);
-    // <C,P> at the returned potentials (FP32 exponentials, FP64 sums)
-    double cst = 0.0;
-    if (!(ctl.flags & ACCSK_FLAG_NO_COST)) {
-        for (int i = wid; i < n; i += NW) {
-            const float *row = P.C + (long long)i * ldc;
-            const double u2 = rowM[i];
-            for (int j = lane; j < m; j += 64) {
-                const float c = row[j];
-                const float pij = __builtin_amdgcn_exp2f((float)(fma(-(double)c, kap2, u2 + xl[j])));
-                cst += (double)(c * pij);
-            }
-        }
-        cst = wg_sum<NW>(cst, red);
-    }
-    if (tid == 0) {
-        DevResult r;
-        r.iters = it;
-        r.steps = steps;
-        r.fallback = fallbacks;
-        r.err = err;
-        const double ua_ln = ua * kLn2, xb_ln = xb2 * kLn2;
-        r.fval = 1.0 - ua_ln - xb_ln;
-        r.eot = eps * (ua_ln + xb_ln - mass);
-        r.cost = (ctl.flags & ACCSK_FLAG_NO_COST) ? NAN : cst;
-        r.converged = (status == ACCSK_OK && err < ctl.tol_stop) ? 1 : 0;
-        r.status = status;
-        *res = r;
-    }
-}
-
-size_t small_lds_bytes(long long n, long long m, int nw) {
-    return (size_t)(4 * m + 3 * n + (long long)nw * m) * sizeof(double);
+    small_body<NW, LPR, NCL, VEC>(probs[blockIdx.x], ctl, results + blockIdx.x, lds, red, sflag);
 }
 
 template <int NW, int LPR, int NCL, bool VEC>
@@ -434,13 +39,7 @@ hipError_t launch_small_cfg(long long mmax, const SmallProb *d_probs, int count,
     return launch_small<4, 64, 16, VEC>(d_probs, count, ctl, d_res, lds, s);
 }
 
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
 }  // namespace
-
-// Shared with the serving loop: validates the parameters and fills SmallCtl.
-accsk_status small_ctl_from_params(const accsk_params *p, SmallCtl *c);
-
 }  // namespace accsk
 
 using namespace accsk;
@@ -448,23 +47,6 @@ using namespace accsk;
 // Persistent multi-problem solver of accsk_dense.hip (problems with m > 1024).
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
                                accsk_result *res, hipStream_t s);
-
-accsk_status accsk::small_ctl_from_params(const accsk_params *p, SmallCtl *c) {
-    if (!p) return ACCSK_INVALID_ARG;
-    if (!finite_pos(p->tol) || p->max_iter < 0) return ACCSK_INVALID_ARG;
-    if (p->method != ACCSK_SINKHORN && p->method != ACCSK_ACC) return ACCSK_INVALID_ARG;
-    if (p->method == ACCSK_ACC && !(p->mu0 > 0.0 && p->mu0 < 1.0 && p->m0 >= 1)) return ACCSK_INVALID_ARG;
-    if (p->w_rule != ACCSK_W_LITERAL && p->w_rule != ACCSK_W_Y_CONTINUOUS) return ACCSK_INVALID_ARG;
-    c->tol = p->tol;
-    c->tol_stop = p->tol * (1.0 - 1.0 / 16.0);
-    c->mu0 = p->mu0;
-    c->max_iter = p->max_iter;
-    c->m0 = p->m0;
-    c->method = p->method;
-    c->w_rule = p->w_rule;
-    c->flags = p->flags;
-    return ACCSK_OK;
-}
 
 static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, const SmallCtl &ctl,
                                       accsk_result *res, hipStream_t s) {
@@ -477,7 +59,7 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
         nmax = std::max<long long>(nmax, q.n);
         mmax = std::max<long long>(mmax, q.m);
         vec = vec && (q.m % 4 == 0) && (q.ldc % 4 == 0) && ((((uintptr_t)q.C) & 15) == 0);
-        hp[(size_t)k] = SmallProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps};
+        hp[(size_t)k] = SmallProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps, q.m - 4};
     }
     const size_t lds = small_lds_bytes(nmax, mmax, 4);
     if (lds > 150 * 1024) return ACCSK_SHAPE;
@@ -525,7 +107,7 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
     for (int64_t k = 0; k < count; k++) {
         const accsk_problem &q = probs[k];
         if (!q.C || !q.a || !q.b || !q.f || !q.g) return ACCSK_INVALID_ARG;
-        if (!finite_pos(q.eps)) return ACCSK_INVALID_ARG;
+        if (!small_finite_pos(q.eps)) return ACCSK_INVALID_ARG;
         if (q.n < 1 || q.m < 1 || q.ldc < q.m || q.m > 8192) return ACCSK_SHAPE;
         if (q.m <= 1024 && q.n <= 4096) {
             small.push_back(q);

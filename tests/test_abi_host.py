@@ -34,7 +34,7 @@ def test_struct_fields_match_header():
     text = open(os.path.join(ROOT, "include", "accsk.h")).read()
 
     def fields(struct_name):
-        body = re.search(r"typedef struct \{([^{}]*)\} %s;" % struct_name, text).group(1)
+        body = re.search(r"typedef struct (?:\w+ )?\{([^{}]*)\} %s;" % struct_name, text).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         out = []
         for decl in body.split(";"):
@@ -48,6 +48,7 @@ def test_struct_fields_match_header():
     assert fields("accsk_params") == [f for f, _ in accsk.Params._fields_]
     assert fields("accsk_result") == [f for f, _ in accsk.Result._fields_]
     assert fields("accsk_problem") == [f for f, _ in accsk.Problem._fields_]
+    assert fields("accsk_request") == [f for f, _ in accsk.Request._fields_]
 
 
 def test_defaults(lib):
@@ -88,3 +89,20 @@ def test_host_validation_batch(lib):
     arr3 = (accsk.Problem * 1)(accsk.Problem(1, 4, 4, 4, 1, 1, 1, 1, 0.0))
     assert lib.accsk_solve_batch(arr3, 1, ctypes.byref(p), res, None) == accsk.INVALID_ARG
     assert lib.accsk_solve_batch(arr, 0, ctypes.byref(p), res, None) == accsk.OK
+
+
+def test_host_validation_server(lib):
+    accsk._register_server(lib)
+    h = ctypes.c_void_p()
+    for kw, budget in ((dict(tol=0.0), 1 << 20), (dict(split=1), 1 << 20), (dict(method=5), 1 << 20), ({}, 0)):
+        p = accsk.default_params(**kw)
+        assert lib.accsk_server_create(budget, 0, ctypes.byref(p), ctypes.byref(h)) == accsk.INVALID_ARG
+        assert not h.value
+    req = accsk.Request()
+    t = ctypes.c_uint64()
+    assert lib.accsk_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == accsk.INVALID_ARG
+    done = ctypes.c_int()
+    assert lib.accsk_server_poll(None, 1, None, ctypes.byref(done), None) == accsk.INVALID_ARG
+    assert lib.accsk_server_destroy(None) == accsk.INVALID_ARG
+    t0 = lib.accsk_clock_seconds()
+    assert lib.accsk_clock_seconds() >= t0 > 0
