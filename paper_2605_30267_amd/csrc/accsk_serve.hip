@@ -49,7 +49,7 @@ constexpr int kRing = 4096;     // descriptor ring entries
 constexpr int kServeNW = 4;     // waves per workgroup
 constexpr int kServeTPB = 64 * kServeNW;
 constexpr long long kServeMaxN = 512, kServeMaxM = 512, kServeMaxD = 512;
-constexpr long long kServeKC = 128;  // features staged per chunk (FP64 cost path)
+constexpr int kServeKC = 32;  // features staged per chunk (FP64 cost path)
 constexpr size_t kArenaAlign = 256;
 
 struct ServeDesc {
@@ -101,34 +101,65 @@ __device__ __forceinline__ unsigned long long ld_dev(const unsigned long long *p
 }
 
 // Builds the request's cost matrix C (n x ldc, pad columns set to 0) with the
-// whole workgroup.  FP64 path: 16 x 16 tiles with chunks of the X and Y rows
-// staged in LDS (sm: 2 * 16 * kServeKC floats).  Matrix-core path: norms first (FP64, into sm
-// as doubles), then one 16 x 16 tile per wave.
+// whole workgroup.  FP64 path: 64 x 64 tiles with chunks of the X and Y rows
+// staged in LDS.  Matrix-core path: norms first (FP64, into sm as doubles),
+// then one 16 x 16 tile per wave.
 template <int KIND>
 __device__ void serve_build_cost(const ServeDesc &D, float *sm) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const long long n = D.n, m = D.m, d = D.d, ldc = D.ldc;
     const long long tn = (n + 15) / 16, tm = (m + 15) / 16;
     if (D.split == 0) {
-        // features staged kServeKC at a time; the FP64 sum runs over k in order
-        float *xs = sm, *ys = sm + 16 * kServeKC;
-        const int r = tid >> 4, c = tid & 15;
-        for (long long t = 0; t < tn * tm; t++) {
-            const long long i0 = (t / tm) * 16, j0 = (t % tm) * 16;
-            double acc = 0.0;
+        // 64 x 64 tiles, thread (tr, tc) owns rows tr + 16p and columns tc + 16q
+        // (p, q < 4); features staged kServeKC at a time (row stride kServeKC + 1
+        // against bank conflicts).  Each entry is the same in-order FP64 sum as
+        // in cross_fp64.
+        constexpr int LS = kServeKC + 1;
+        float *xs = sm, *ys = sm + 64 * LS;
+        const int tr = tid >> 4, tc = tid & 15;
+        const long long tn64 = (n + 63) / 64, tm64 = (m + 63) / 64;
+        for (long long t = 0; t < tn64 * tm64; t++) {
+            const long long i0 = (t / tm64) * 64, j0 = (t % tm64) * 64;
+            double acc[4][4];
+#pragma unroll
+            for (int p = 0; p < 4; p++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) acc[p][q] = 0.0;
             for (long long k0 = 0; k0 < d; k0 += kServeKC) {
-                const long long kc = std::min<long long>(kServeKC, d - k0);
+                const int kc = (int)std::min<long long>(kServeKC, d - k0);
                 __syncthreads();
-                for (long long e = tid; e < 16 * kc; e += kServeTPB) {
-                    const long long rr = e / kc, k = k0 + e % kc;
-                    xs[e] = (i0 + rr < n) ? D.X[(i0 + rr) * d + k] : 0.f;
-                    ys[e] = (j0 + rr < m) ? D.Y[(j0 + rr) * d + k] : 0.f;
+                for (int e = tid; e < 64 * kc; e += kServeTPB) {
+                    const int rr = e / kc, k = e % kc;
+                    xs[rr * LS + k] = (i0 + rr < n) ? D.X[(i0 + rr) * d + k0 + k] : 0.f;
+                    ys[rr * LS + k] = (j0 + rr < m) ? D.Y[(j0 + rr) * d + k0 + k] : 0.f;
                 }
                 __syncthreads();
-                acc = cross_fp64_acc<KIND>(xs + r * kc, ys + c * kc, kc, acc);
+                for (int k = 0; k < kc; k++) {
+                    double xv[4], yv[4];
+#pragma unroll
+                    for (int p = 0; p < 4; p++) xv[p] = xs[(tr + 16 * p) * LS + k];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) yv[q] = ys[(tc + 16 * q) * LS + k];
+#pragma unroll
+                    for (int p = 0; p < 4; p++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            if (KIND == ACCSK_SQEUCLID) {
+                                const double tt = xv[p] - yv[q];
+                                acc[p][q] = fma(tt, tt, acc[p][q]);
+                            } else {
+                                acc[p][q] = fma(xv[p], yv[q], acc[p][q]);
+                            }
+                        }
+                }
             }
-            const long long i = i0 + r, j = j0 + c;
-            if (i < n && j < ldc) D.C[i * ldc + j] = j < m ? finish_fp64<KIND>(acc, D.inv_s) : 0.f;
+#pragma unroll
+            for (int p = 0; p < 4; p++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const long long i = i0 + tr + 16 * p, j = j0 + tc + 16 * q;
+                    if (i < n && j < ldc) D.C[i * ldc + j] = j < m ? finish_fp64<KIND>(acc[p][q], D.inv_s) : 0.f;
+                }
         }
     } else {
         double *nx = reinterpret_cast<double *>(sm), *ny = nx + kServeMaxN;
@@ -175,6 +206,7 @@ __device__ void serve_build_cost(const ServeDesc &D, float *sm) {
 __device__ long long serve_claim(DevQueue *q, long long idle) {
     long long t0 = wall_clock64();
     unsigned long long seen = ld_dev(&q->avail);
+    int nap = 1;
     for (;;) {
         const unsigned long long h = ld_dev(&q->head);
         const unsigned long long av = __hip_atomic_load(&q->avail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -188,6 +220,7 @@ __device__ long long serve_claim(DevQueue *q, long long idle) {
         if (av != seen) {  // new work was published (taken by others): still busy
             seen = av;
             t0 = wall_clock64();
+            nap = 1;
         }
         if (__hip_atomic_load(&q->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
             // the final `avail` was stored before `stop`
@@ -196,7 +229,10 @@ __device__ long long serve_claim(DevQueue *q, long long idle) {
             continue;
         }
         if (wall_clock64() - t0 > idle) return -1;
-        __builtin_amdgcn_s_sleep(20);  // ~1 us between polls of the shared counters
+        // back off while idle (polls of the shared counters by hundreds of
+        // idle workgroups slow down the busy ones): ~3.4 us doubling to ~27 us
+        for (int k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(127);
+        nap = nap < 8 ? 2 * nap : 8;
     }
 }
 
@@ -274,7 +310,7 @@ static_assert(sizeof(DevResult) % 8 == 0, "result record is written as 64-bit wo
 
 size_t serve_lds_bytes() {
     const size_t solve = small_lds_bytes(kServeMaxN, kServeMaxM, kServeNW);
-    const size_t stage = 2 * 16 * (size_t)kServeKC * sizeof(float);
+    const size_t stage = 2 * 64 * (size_t)(kServeKC + 1) * sizeof(float);
     const size_t norms = 2 * (size_t)kServeMaxN * sizeof(double);
     return std::max(solve, std::max(stage, norms));
 }

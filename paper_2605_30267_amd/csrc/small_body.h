@@ -6,9 +6,10 @@
 //    64/LPR rows at a time, the workgroup on NW*64/LPR rows;
 //  * lane li of a row owns the float4 column groups li, li+LPR, ... (NCL
 //    columns), so the loads of one row are contiguous;
-//  * row max and row sum are butterfly reductions over the LPR lanes (DPP
-//    inside a 16-lane row, xor shuffles across rows), so every lane of the
-//    row holds the result and no barrier is needed per row;
+//  * row max and row sum are DPP reductions over the LPR lanes (a butterfly
+//    inside a 16-lane row; for a 64-lane row a chain into lane 63 and a
+//    readlane), so every lane of the row holds the result and no barrier is
+//    needed per row;
 //  * column sums are accumulated per lane in FP64 and combined across the
 //    rows of a wave (xor shuffles) and across waves (LDS, fixed order) once
 //    per Sinkhorn step.
@@ -54,23 +55,24 @@ __device__ __forceinline__ double bfly16_sum(double v) {
     v += dpp_f64<0x140, 0xf, 0xf>(v, v);
     return v;
 }
+// Row reductions over the LPR lanes of a row; every lane gets the result.
+// LPR = 16: DPP butterfly inside the 16-lane row.  LPR = 64 (the row is the
+// whole wave): DPP row_shr / row_bcast chain into lane 63, then readlane; no
+// LDS permutes, whose latency would dominate a row.
 template <int LPR>
 __device__ __forceinline__ float row_max(float v) {
-    v = bfly16_max(v);
-    if (LPR == 64) {
-        v = fmaxf(v, __shfl_xor(v, 16, 64));
-        v = fmaxf(v, __shfl_xor(v, 32, 64));
-    }
-    return v;
+    if (LPR == 64) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_l63(v)), 63));
+    return bfly16_max(v);
 }
 template <int LPR>
 __device__ __forceinline__ double row_sum(double v) {
-    v = bfly16_sum(v);
     if (LPR == 64) {
-        v += __shfl_xor(v, 16, 64);
-        v += __shfl_xor(v, 32, 64);
+        const long long b = __double_as_longlong(wave_sum_l63(v));
+        const int lo = __builtin_amdgcn_readlane((int)b, 63);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
     }
-    return v;
+    return bfly16_sum(v);
 }
 
 // Deterministic workgroup sum: wave butterfly, then a fixed-order sum of the
