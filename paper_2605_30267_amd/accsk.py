@@ -448,7 +448,7 @@ class Server:
         self._h = h
         self._live = {}
 
-    def submit(self, X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0):
+    def submit(self, X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, f_out=None, g_out=None):
         import torch
         _check_dev(X, torch.float32, "X", 2)
         _check_dev(Y, torch.float32, "Y", 2)
@@ -459,8 +459,12 @@ class Server:
         m = Y.shape[0]
         if Y.shape[1] != d or a.shape[0] != n or b.shape[0] != m:
             raise ValueError("inconsistent request shapes")
-        f = torch.empty(n, dtype=torch.float64, device=X.device)
-        g = torch.empty(m, dtype=torch.float64, device=X.device)
+        f = torch.empty(n, dtype=torch.float64, device=X.device) if f_out is None else f_out
+        g = torch.empty(m, dtype=torch.float64, device=X.device) if g_out is None else g_out
+        _check_dev(f, torch.float64, "f_out", 1)
+        _check_dev(g, torch.float64, "g_out", 1)
+        if f.shape[0] != n or g.shape[0] != m or not (f.is_contiguous() and g.is_contiguous()):
+            raise ValueError("f_out / g_out must be contiguous [n] / [m]")
         req = Request(X.data_ptr(), Y.data_ptr(), n, m, d, int(kind), 0, float(cost_scale), a.data_ptr(),
                       b.data_ptr(), float(eps), f.data_ptr(), g.data_ptr())
         t = ctypes.c_uint64()

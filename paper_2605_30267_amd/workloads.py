@@ -119,13 +119,16 @@ def word_requests(seed=4, count=4000, d=300, rate=None, eps_set=(1e-2, 3e-3, 1e-
         X = unit_rows(rng, n, d).astype(np.float32)
         Y = unit_rows(rng, m, d).astype(np.float32)
         reqs.append(dict(X=X, Y=Y, a=np.full(n, 1.0 / n), b=np.full(m, 1.0 / m), eps=eps))
-    arr = np.zeros(count)
-    if rate is not None:
-        gaps = np.random.default_rng(seed * 10).exponential(1.0 / rate, size=count)
-        arr = np.cumsum(gaps)
+    arr = np.zeros(count) if rate is None else poisson_arrivals(count, rate, seed * 10)
     for r, t in zip(reqs, arr):
         r["arrival"] = float(t)
     return reqs
+
+
+def poisson_arrivals(count, rate, seed=40):
+    """Arrival instants (seconds from 0) of a Poisson process: cumulative Exp(rate) gaps."""
+    gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
+    return np.cumsum(gaps)
 
 
 def gaussian_batch(seed=5, batch=64, n=2048, m=2048, d=64, eps=5e-3):
