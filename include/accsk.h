@@ -78,6 +78,8 @@ typedef struct {
 
 #define ACCSK_FLAG_NO_COST 1       /* skip the final <C,P> pass */
 #define ACCSK_FLAG_NO_SERPENTINE 2 /* traverse C in the same row order every step */
+#define ACCSK_FLAG_ON_THE_FLY 4    /* point-cloud solves: form C_ij on the fly in every step (never stored);
+                                      implied when m > 8192; needs d <= 16 */
 
 typedef struct {
     int64_t iters;          /* It: accepted iterates after x_0 (Sinkhorn: v-updates) */
@@ -107,7 +109,9 @@ const char *accsk_version(void);
  * Dense solve on an explicit FP32 cost (Sec. 2 dual, Sec. 4 algorithms).
  * C: device, n x m row-major, leading dimension ldc >= m.  a: device FP64[n],
  * b: device FP64[m].  f_out: device FP64[n], g_out: device FP64[m].
- * res: host.  Supported sizes: 1 <= n, 1 <= m <= 8192.
+ * res: host.  Sizes: 1 <= n, 1 <= m.  For m <= 8192 each Sinkhorn step reads
+ * C once (row and column sums fused); larger m uses the tiled solver (a row
+ * sweep and a column sweep, two reads of C per step).
  * Returns ACCSK_OK, ACCSK_NOT_CONVERGED (outputs valid), or an error.
  */
 accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc,
@@ -176,11 +180,24 @@ accsk_status accsk_cost_points(const float *X, const float *Y, int64_t n, int64_
 /*
  * Point-cloud solve: builds the cost as accsk_cost_points does (with
  * p->split) into library scratch memory and solves EOT on it.  a, b, f_out,
- * g_out as for accsk_solve_dense.  Limits: m <= 8192, d <= 512.
+ * g_out as for accsk_solve_dense.  With ACCSK_FLAG_ON_THE_FLY, or when
+ * m > 8192, the cost is instead formed on the fly in every step from X and Y
+ * (FP64 arguments, nothing of size n x m is stored; d <= 16) by the tiled
+ * solver; for m > 8192 and d > 16 the cost is built explicitly and solved by
+ * the tiled solver.  Limits: d <= 512.
  */
 accsk_status accsk_solve_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
                                 double cost_scale, const double *a, const double *b, const accsk_params *p,
                                 double *f_out, double *g_out, accsk_result *res, void *stream);
+
+/*
+ * Exact maximum of the raw point-cloud cost (before division by a scale):
+ * max_ij ||x_i - y_j||^2 (SQEUCLID) or max_ij (1 - <x_i, y_j>) (COSINE), each
+ * entry summed in FP64 as accsk_cost_points does with split 0 (Sec. 5 divides
+ * the colour-transfer cost by its maximum).  out: host double.  Limits: d <= 512.
+ */
+accsk_status accsk_cost_max_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                                   double *out, void *stream);
 
 /*
  * Batch of `batch` independent point-cloud problems of equal shape: X is

@@ -21,6 +21,7 @@ W_LITERAL, W_Y_CONTINUOUS = 0, 1
 SQEUCLID, COSINE = 0, 1
 FLAG_NO_COST = 1
 FLAG_NO_SERPENTINE = 2
+FLAG_ON_THE_FLY = 4
 
 
 class AccskError(RuntimeError):
@@ -245,6 +246,8 @@ def _register_points(L):
     L.accsk_backward_points.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.accsk_backward_points.restype = ctypes.c_int
+    L.accsk_cost_max_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(_dbl), _vp]
+    L.accsk_cost_max_points.restype = ctypes.c_int
     L._points_ready = True
 
 
@@ -274,6 +277,20 @@ def cost_points(X, Y, kind=SQEUCLID, cost_scale=1.0, split=0, out=None):
     return out
 
 
+def cost_max_points(X, Y, kind=SQEUCLID):
+    """Exact maximum of the raw point-cloud cost (FP64 entries), as a Python float."""
+    import torch
+    _check_dev(X, torch.float32, "X", 2)
+    _check_dev(Y, torch.float32, "Y", 2)
+    X, Y = X.contiguous(), Y.contiguous()
+    out = ctypes.c_double()
+    st = _points_lib().accsk_cost_max_points(_ptr(X), _ptr(Y), X.shape[0], Y.shape[0], X.shape[1], int(kind),
+                                             ctypes.byref(out), _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_cost_max_points")
+    return out.value
+
+
 def _as_batched(X, Y, a, b):
     import torch
     single = X.dim() == 2
@@ -290,11 +307,15 @@ def _as_batched(X, Y, a, b):
 
 
 def solve_points(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e-6, method=ACC,
-                 max_iter=100000, mu0=None, m0=None, w_rule=None, flags=0, raise_on_error=True):
+                 max_iter=100000, mu0=None, m0=None, w_rule=None, flags=0, on_the_fly=False, raise_on_error=True):
     """EOT between point clouds.  X [n,d] / [B,n,d] float32, a [n] / [B,n] float64.
 
-    Returns (f, g, results): f, g shaped like a, b; results a list of dicts.
+    on_the_fly: form the cost in every step instead of storing it (d <= 16;
+    implied for m > 8192).  Returns (f, g, results): f, g shaped like a, b;
+    results a list of dicts.
     """
+    if on_the_fly:
+        flags = int(flags) | FLAG_ON_THE_FLY
     import torch
     single, X, Y, a, b = _as_batched(X, Y, a, b)
     B, n, d = X.shape

@@ -170,7 +170,7 @@ __device__ __forceinline__ float f4get(const float4 &v, int e) {
 // multiply per entry.  Algorithm A2MD is linear in (x, w, S), so it runs
 // unchanged in these units.
 //
-// Dynamic LDS layout: wl[m] | xl[m] | la2s[rpb] | rowM[rpb] | rowS[rpb] | rowL[rpb]  (doubles).
+// Dynamic LDS layout: wl[m] | xl[m] | la2s[rpb] | rowM[rpb] | rowS[rpb] | rowL[rpb] | rowA[rpb]  (doubles).
 // x and w live in LDS between steps (each thread owns the same columns in
 // every phase), so no per-column state is carried in registers across steps.
 template <int TPB, int NG, int RB, bool VEC>
@@ -216,6 +216,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
     double *rowM = la2s + rpb;
     double *rowS = rowM + rpb;
     double *rowL = rowS + rpb;  // shift for the next step (row log-sum-exp, log2 units)
+    double *rowA = rowL + rpb;  // a_i / max a (FP64, rounded once per use to FP32)
 
     const double kap2 = A.kappa * kLog2e;  // C_ij/eps in log2 units
     const double La2 = A.gscal[0];
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
     for (int r = tid; r < nr; r += TPB) {
         la2s[r] = A.la2[r0 + r];
         rowL[r] = INFINITY;  // unknown: the first step takes the exact row maximum
+        rowA[r] = dexp2(la2s[r] - A.gscal[0]);
     }
     __syncthreads();
 
@@ -374,9 +376,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
             for (int q = 0; q < RB; q++) {
                 const int rl = rloc(bb, q);
                 const bool rv = bb * RB + q < nr;
-                const float rfac = rv ? __builtin_amdgcn_exp2f((float)(la2s[rl] - La2)) *
-                                            __builtin_amdgcn_rcpf((float)S[q])
-                                      : 0.f;
+                const float rfac = rv ? (float)rowA[rl] * __builtin_amdgcn_rcpf((float)S[q]) : 0.f;
 #pragma unroll
                 for (int c = 0; c < NC; c++) cterm[c] = fmaf(ev[q][c], rfac, cterm[c]);
                 if (tid == 0 && rv) {
@@ -850,7 +850,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     }
     // blocks per problem: fill the chip with at most two workgroups per CU
     int occ = 0;
-    const size_t dyn_probe = (size_t)(2 * mmax + 4) * sizeof(double);
+    const size_t dyn_probe = (size_t)(2 * mmax + 5) * sizeof(double);
     ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC>, TPB, dyn_probe));
     if (occ < 1) return ACCSK_SHAPE;
     const long long total = (long long)std::min(occ, 2) * num_cu;
@@ -858,7 +858,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     gp = std::min<long long>(gp, std::max<long long>(1, nmax));
     long long rpb_max = 0;
     for (int k = k0; k < k1; k++) rpb_max = std::max(rpb_max, (hp[k].n + gp - 1) / gp);
-    const size_t dyn = (size_t)(2 * mmax + 4 * rpb_max) * sizeof(double);
+    const size_t dyn = (size_t)(2 * mmax + 5 * rpb_max) * sizeof(double);
     if (dyn > 150 * 1024) return ACCSK_SHAPE;
     int occ2 = 0;
     ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, dense_solve<TPB, NG, RB, VEC>, TPB, dyn));
@@ -1016,6 +1016,12 @@ accsk_status check_params(const accsk_params *p) {
 
 using namespace accsk;
 
+// Tiled solver of accsk_tiled.hip (m > 8192, or costs formed on the fly).
+accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, const float *Y, int64_t d, int kind,
+                               double cost_scale, int64_t n, int64_t m, const double *a, const double *b,
+                               const accsk_params *p, double eps, double *f_out, double *g_out, accsk_result *res,
+                               hipStream_t s);
+
 // Persistent multi-problem path, also used by the batch entry point for
 // problems with more than 1024 columns.
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
@@ -1055,7 +1061,11 @@ extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, 
     accsk_status st = check_params(p);
     if (st != ACCSK_OK) return st;
     if (n < 1 || m < 1 || ldc < m) return ACCSK_SHAPE;
-    if (m > 8192) return ACCSK_SHAPE;
+    if (m > 8192) {
+        st = accsk_tiled_solve(C, ldc, nullptr, nullptr, 0, 0, 1.0, n, m, a, b, p, p->eps, f_out, g_out, res,
+                               (hipStream_t)stream);
+        return st;
+    }
     accsk_problem q{C, n, m, ldc, a, b, f_out, g_out, p->eps};
     st = accsk_dense_multi(&q, 1, p, res, (hipStream_t)stream);
     if (st != ACCSK_OK) return st;

@@ -35,6 +35,10 @@
 
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
                                accsk_result *res, hipStream_t s);
+accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, const float *Y, int64_t d, int kind,
+                               double cost_scale, int64_t n, int64_t m, const double *a, const double *b,
+                               const accsk_params *p, double eps, double *f_out, double *g_out, accsk_result *res,
+                               hipStream_t s);
 
 namespace accsk {
 namespace {
@@ -214,6 +218,50 @@ __global__ __launch_bounds__(256) void grad_marginal(const double *__restrict__ 
     for (long long i = threadIdx.x; i < len; i += 256) out[i] = gscale * (pot[i] - mean) / sw_;
 }
 
+// max over a 16-row x 256-column tile of the raw cost, FP64 entries as in cost_fp64
+template <int KIND>
+__global__ __launch_bounds__(256) void cost_max_part(const float *__restrict__ X, const float *__restrict__ Y,
+                                                     long long n, long long m, long long d,
+                                                     double *__restrict__ part) {
+    extern __shared__ float xs[];  // [16][d]
+    __shared__ double red[4];
+    const long long i0 = (long long)blockIdx.y * 16;
+    const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+    for (long long t = threadIdx.x; t < 16 * d; t += 256) {
+        const long long r = t / d;
+        xs[t] = (i0 + r < n) ? X[(i0 + r) * d + (t % d)] : 0.f;
+    }
+    __syncthreads();
+    double mx = -INFINITY;
+    if (j < m) {
+        const float *yr = Y + j * d;
+        for (int r = 0; r < 16 && i0 + r < n; r++) {
+            const double acc = cross_fp64<KIND>(xs + r * d, yr, d);
+            mx = fmax(mx, KIND == ACCSK_SQEUCLID ? acc : 1.0 - acc);
+        }
+    }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(1024) void max_reduce(const double *__restrict__ part, long long cnt,
+                                                   double *__restrict__ out) {
+    __shared__ double red[16];
+    double mx = -INFINITY;
+    for (long long k = threadIdx.x; k < cnt; k += 1024) mx = fmax(mx, part[k]);
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = -INFINITY;
+        for (int q = 0; q < 16; q++) v = fmax(v, red[q]);
+        *out = v;
+    }
+}
+
 accsk_status build_cost(const float *X, const float *Y, long long n, long long m, long long d, int kind,
                         double scale, int split, float *C, long long ldc, double *norms_ws, hipStream_t s) {
     const double inv_s = 1.0 / scale;
@@ -275,6 +323,69 @@ extern "C" accsk_status accsk_cost_points(const float *X, const float *Y, int64_
     return st;
 }
 
+extern "C" accsk_status accsk_cost_max_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d,
+                                              int kind, double *out, void *stream) {
+    accsk_status st = check_points(X, Y, n, m, d, kind, 1.0, 0);
+    if (st != ACCSK_OK) return st;
+    if (!out) return ACCSK_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const long long gx = (m + 255) / 256, gy = (n + 15) / 16;
+    if (gy > 65535) return ACCSK_SHAPE;
+    double *buf = nullptr;
+    if (hipMallocAsync((void **)&buf, (size_t)(gx * gy + 1) * 8, s) != hipSuccess) return ACCSK_OOM;
+    const size_t lds = 16 * (size_t)d * sizeof(float);
+    if (kind == ACCSK_SQEUCLID)
+        hipLaunchKernelGGL(cost_max_part<ACCSK_SQEUCLID>, dim3((unsigned)gx, (unsigned)gy), dim3(256), lds, s, X, Y, n,
+                           m, d, buf + 1);
+    else
+        hipLaunchKernelGGL(cost_max_part<ACCSK_COSINE>, dim3((unsigned)gx, (unsigned)gy), dim3(256), lds, s, X, Y, n,
+                           m, d, buf + 1);
+    hipLaunchKernelGGL(max_reduce, dim3(1), dim3(1024), 0, s, buf + 1, gx * gy, buf);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out, buf, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(buf, s);
+    return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+// Tiled solves of a batch of point-cloud problems, one after the other: costs on
+// the fly (d <= 16), else built explicitly one problem at a time.
+static accsk_status solve_points_tiled(const float *X, const float *Y, int64_t batch, int64_t n, int64_t m,
+                                       int64_t d, int kind, double cost_scale, const double *a, const double *b,
+                                       const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
+                                       hipStream_t s) {
+    float *C = nullptr;
+    double *nws = nullptr;
+    const long long ldc = (m + 3) / 4 * 4;
+    if (d > 16) {
+        const size_t cbytes = ((size_t)n * ldc * sizeof(float) + 255) & ~size_t(255);
+        char *ws = nullptr;
+        if (hipMallocAsync((void **)&ws, cbytes + (size_t)(n + m) * 8, s) != hipSuccess) return ACCSK_OOM;
+        C = (float *)ws;
+        nws = (double *)(ws + cbytes);
+    }
+    accsk_status worst = ACCSK_OK;
+    for (int64_t k = 0; k < batch; k++) {
+        const float *Xk = X + k * n * d, *Yk = Y + k * m * d;
+        accsk_status st;
+        if (d <= 16) {
+            st = accsk_tiled_solve(nullptr, 0, Xk, Yk, d, kind, cost_scale, n, m, a + k * n, b + k * m, p, p->eps,
+                                   f_out + k * n, g_out + k * m, &res[k], s);
+        } else {
+            st = build_cost(Xk, Yk, n, m, d, kind, cost_scale, p->split, C, ldc, nws, s);
+            if (st == ACCSK_OK)
+                st = accsk_tiled_solve(C, ldc, nullptr, nullptr, 0, kind, 1.0, n, m, a + k * n, b + k * m, p, p->eps,
+                                       f_out + k * n, g_out + k * m, &res[k], s);
+        }
+        if (st != ACCSK_OK && st != ACCSK_NOT_CONVERGED && res[k].status == ACCSK_OK) res[k].status = st;
+        if (st == ACCSK_OK) continue;
+        if (worst == ACCSK_OK || (worst == ACCSK_NOT_CONVERGED && st != ACCSK_NOT_CONVERGED)) worst = st;
+    }
+    if (C) (void)hipFreeAsync(C, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return ACCSK_HIP_ERROR;
+    return worst;
+}
+
 extern "C" accsk_status accsk_solve_points_batched(const float *X, const float *Y, int64_t batch, int64_t n,
                                                    int64_t m, int64_t d, int kind, double cost_scale,
                                                    const double *a, const double *b, const accsk_params *p,
@@ -284,8 +395,11 @@ extern "C" accsk_status accsk_solve_points_batched(const float *X, const float *
     accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, p->split);
     if (st != ACCSK_OK) return st;
     if (!finite_pos(p->eps)) return ACCSK_INVALID_ARG;
-    if (m > 8192) return ACCSK_SHAPE;
     hipStream_t s = (hipStream_t)stream;
+    if ((p->flags & ACCSK_FLAG_ON_THE_FLY) || m > 8192) {
+        if ((p->flags & ACCSK_FLAG_ON_THE_FLY) && d > 16) return ACCSK_SHAPE;
+        return solve_points_tiled(X, Y, batch, n, m, d, kind, cost_scale, a, b, p, f_out, g_out, res, s);
+    }
     const long long ldc = (m + 3) / 4 * 4;
     const size_t cbytes = (size_t)batch * n * ldc * sizeof(float);
     char *ws = nullptr;

@@ -1,0 +1,774 @@
+// Tiled solver for large problems: explicit FP32 costs with m > 8192, and
+// costs formed on the fly from point clouds (d <= 16), never materialized.
+//
+// One cooperative (persistent) launch runs the whole solve (paper Sec. 2 row
+// solve eq:u-update, normalized column step eq:normalized-sinkhorn; Sec. 4
+// Algorithms A2MD / A2MD-homotopy; stop on eq:l1tol).  Per Sinkhorn step:
+//
+//  A. Row sweep.  Block b owns rows [r0, r1); each wave owns RW of them at a
+//     time, its lanes walk the columns in chunks staged in LDS.  The shift of
+//     row i is its log-sum-exp of the previous step (exact row maximum on the
+//     first step or when the sum leaves [2^-40, 2^40]).  Gives u_i.
+//  B. Column sweep.  Each lane owns CPL columns of a chunk and walks all rows
+//     of the block (staged in LDS), summing 2^(t_ij + u_i - L_j) = P_ij / 2^L_j
+//     with L_j the column's log2-sum of the previous step: one FP32
+//     exponential per entry, FP64 accumulation.
+//  Then, as in the dense solver: grid barrier, combine of the per-block column
+//  sums over the block's column slice (S^_j, |c_j - b_j|), grid barrier,
+//  totals, update of the block's slice of x and w (Sinkhorn or Algorithm A2MD
+//  with the homotopy), grid barrier.
+// Exponent arguments (log2 units) are formed in FP64:
+//  * explicit C: t_ij = x_j - C_ij / eps;
+//  * points: t_ij = xh_j + r_i + sum_k xt_ik y_jk, with the norms folded into a
+//    column term xh_j = x_j - kappa_s |y_j|^2 (cosine: x_j - kappa_s) and a row
+//    term r_i = -kappa_s |x_i|^2 (cosine: 0), xt_i = 2 kappa_s x_i (cosine:
+//    kappa_s x_i), kappa_s = log2(e) / (eps s).  C_ij is never stored.
+// If a combined column sum leaves [2^-64, 2^64] (the column mass changed that
+// much in one step), an exact column sweep with a per-column maximum redoes the
+// column side of that step.
+
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "accsk_common.h"
+
+namespace accsk {
+namespace {
+
+constexpr int kTT = 512;          // threads per block
+constexpr int kTW = kTT / 64;     // waves per block
+constexpr int kTNS = 8;           // block scalar slots: 1 sum S^, 2 err, 3 mass, 4 <x,b>, 5 fallback
+constexpr int kTRB = 256;         // rows staged per row group of the column sweep
+
+template <int D>
+struct TCfg {
+    static constexpr int DD = D > 0 ? D : 1;                                   // array extent
+    static constexpr int RW = D == 0 ? 8 : (D <= 3 ? 8 : (D <= 8 ? 4 : 2));   // rows per wave, row sweep
+    static constexpr int CH = D <= 3 ? 2048 : (D <= 8 ? 1024 : 512);           // columns per chunk
+    static constexpr int CPL = CH / kTT;                                       // columns per lane, column sweep
+    static constexpr int RG = kTW * RW;                                        // rows per group, row sweep
+};
+
+template <int D>
+size_t tiled_lds_bytes() {
+    using Cf = TCfg<D>;
+    const size_t cols = (size_t)Cf::CH * (Cf::DD + 1) * sizeof(double);
+    const size_t rows = (size_t)kTRB * (Cf::DD + 1) * sizeof(double);
+    return std::max(cols, rows);
+}
+
+struct TiledArgs {
+    const float *C;   // explicit cost (D == 0)
+    long long ldc;
+    const float *X, *Y;  // points (D > 0): n x d, m x d
+    long long d;
+    int kind;
+    double inv_s;
+    long long n, m;
+    const double *a_in, *b_in;
+    double *an, *la2, *xnrm, *rowL, *rowU;   // [n]
+    double *bn, *lnb, *ynrm, *xg, *wg, *shat;  // [m]
+    double *colL;                            // [m] log2 of the last column sums (column sweep shift)
+    float *partf;                            // [G][m]
+    double *part, *partmax;                  // [G][m] exact column sweep
+    double *bscal;                           // [2][G][kTNS]
+    double *uapart, *costpart;               // [G]
+    double *gscal;                           // 0: max log2 a, 1: max a
+    int *status;
+    unsigned long long *bar;
+    DevResult *res;
+    double *f_out, *g_out;
+    double eps, tol, tol_stop, mu0;
+    long long max_iter, m0;
+    int method, w_rule, flags;
+};
+
+__device__ double tblock_sum(double v, double *red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); k++) s += red[k];
+    __syncthreads();
+    return s;
+}
+__device__ double tblock_max(double v, double *red) {
+    v = wave_max(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = -INFINITY;
+    for (int k = 0; k < (int)(blockDim.x >> 6); k++) s = fmax(s, red[k]);
+    __syncthreads();
+    return s;
+}
+
+// Marginals (unit mass, eq:Fc), logs, max log2 a, and FP64 squared norms of
+// the points.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void tiled_setup(const TiledArgs *__restrict__ pa) {
+    const TiledArgs A = *pa;
+    __shared__ double red[16];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    int lbad = 0;
+    double s = 0.0;
+    for (long long i = tid; i < A.n; i += 1024) {
+        const double v = A.a_in[i];
+        lbad |= !isfinite(v) ? 2 : (!(v > 0.0) ? 1 : 0);
+        s += v;
+    }
+    for (long long j = tid; j < A.m; j += 1024) {
+        const double v = A.b_in[j];
+        lbad |= !isfinite(v) ? 2 : (!(v > 0.0) ? 1 : 0);
+    }
+    if (lbad) atomicOr(&bad, lbad);
+    const double sa = tblock_sum(s, red);
+    double mx = -INFINITY;
+    for (long long i = tid; i < A.n; i += 1024) {
+        const double v = A.a_in[i] / sa;
+        A.an[i] = v;
+        const double l2 = log2(v);
+        A.la2[i] = l2;
+        mx = fmax(mx, l2);
+        double nn = 0.0;
+        if (A.X)
+            for (long long k = 0; k < A.d; k++) {
+                const double xv = A.X[i * A.d + k];
+                nn = fma(xv, xv, nn);
+            }
+        A.xnrm[i] = nn;
+    }
+    mx = tblock_max(mx, red);
+    s = 0.0;
+    for (long long j = tid; j < A.m; j += 1024) s += A.b_in[j];
+    const double sb = tblock_sum(s, red);
+    for (long long j = tid; j < A.m; j += 1024) {
+        const double v = A.b_in[j] / sb;
+        A.bn[j] = v;
+        A.lnb[j] = log(v);
+        double nn = 0.0;
+        if (A.Y)
+            for (long long k = 0; k < A.d; k++) {
+                const double yv = A.Y[j * A.d + k];
+                nn = fma(yv, yv, nn);
+            }
+        A.ynrm[j] = nn;
+        A.xg[j] = 0.0;
+        A.wg[j] = 0.0;
+        A.colL[j] = mx;  // first step: shift max log2 a, every term <= 1
+    }
+    __syncthreads();
+    if (tid == 0) {
+        A.gscal[0] = mx;
+        A.gscal[1] = exp2(mx);
+        A.status[0] = (bad & 2) ? ACCSK_NONFINITE : ((bad & 1) ? ACCSK_INVALID_ARG : ACCSK_OK);
+    }
+}
+
+__device__ __forceinline__ double readlane63_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int D>
+__global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__ pa) {
+    using Cf = TCfg<D>;
+    constexpr int RW = Cf::RW, CH = Cf::CH, CPL = Cf::CPL, RG = Cf::RG, DD = Cf::DD;
+    const TiledArgs A = *pa;
+    extern __shared__ double tl[];
+    __shared__ double tot[kTNS];
+    __shared__ double sred[kTW * 64];
+    __shared__ int bflag, sflag;
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int G = gridDim.x, bid = blockIdx.x;
+    if (A.status[0] != ACCSK_OK) {
+        if (bid == 0 && tid == 0) {
+            DevResult r{};
+            r.err = NAN;
+            r.eot = NAN;
+            r.fval = NAN;
+            r.cost = NAN;
+            r.status = A.status[0];
+            *A.res = r;
+        }
+        return;
+    }
+    const long long n = A.n, m = A.m, d = A.d;
+    const long long rpb = (n + G - 1) / G;
+    const long long r0 = std::min(n, (long long)bid * rpb), r1 = std::min(n, r0 + rpb);
+    const long long nr = r1 - r0;
+    const long long spb = (m + G - 1) / G;
+    const long long j0 = std::min(m, (long long)bid * spb), j1 = std::min(m, j0 + spb);
+    const double kap2 = kLog2e / A.eps;      // 1/eps in log2 units
+    const double ks = kap2 * A.inv_s;        // points: log2 e / (eps s)
+    const bool sq = A.kind == ACCSK_SQEUCLID;
+    const double coef = sq ? 2.0 * ks : ks;  // cross-term coefficient
+    const double La2 = A.gscal[0];
+
+    for (long long i = r0 + tid; i < r1; i += kTT) A.rowL[i] = INFINITY;
+
+    // ---- helpers -------------------------------------------------------
+    // row constant r_i (log2 units) of the folded argument
+    auto row_const = [&](long long i) -> double { return (D > 0 && sq) ? -ks * A.xnrm[i] : 0.0; };
+    // column term xh_j of the folded argument at the current x
+    auto col_term = [&](long long j) -> double {
+        const double x2 = A.xg[j];
+        if (D == 0) return x2;
+        return sq ? x2 - ks * A.ynrm[j] : x2 - ks;
+    };
+    // argument t_ij + rc for a row (xt, rc) and a column (y, xh); explicit: cij
+    auto arg_pts = [&](const double (&xt)[DD], double rc, const double (&y)[DD], double xh) -> double {
+        double t = xh + rc;
+#pragma unroll
+        for (int k = 0; k < DD; k++) t = fma(xt[k], y[k], t);
+        return t;
+    };
+
+    double *ysl = tl;                  // [DD][CH] staged y (SoA), row sweep
+    double *xhl = tl + (size_t)DD * CH;  // [CH] staged xh
+    double *xtl = tl;                  // [DD][kTRB] staged xt, column sweep
+    double *rhl = tl + (size_t)DD * kTRB;  // [kTRB] staged row term
+
+    auto stage_cols = [&](long long ja, int len) {
+        for (int c = tid; c < len; c += kTT) {
+            const long long j = ja + c;
+            if (D > 0)
+#pragma unroll
+                for (int k = 0; k < D; k++) ysl[(size_t)k * CH + c] = k < d ? (double)A.Y[j * d + k] : 0.0;
+            xhl[c] = col_term(j);
+        }
+    };
+
+    // ---- row sweep: u for the block's rows --------------------------------
+    auto row_sweep = [&]() {
+        for (long long g0 = 0; g0 < nr; g0 += RG) {
+            double xt[RW][DD];
+            double rc0[RW], shift[RW];
+            bool rv[RW];
+            long long ri[RW];
+            int unknown = 0;
+#pragma unroll
+            for (int q = 0; q < RW; q++) {
+                const long long lr = g0 + wid * RW + q;
+                rv[q] = lr < nr;
+                ri[q] = r0 + std::min(lr, nr - 1);
+#pragma unroll
+                for (int k = 0; k < DD; k++)
+                    xt[q][k] = (D > 0 && k < d) ? coef * (double)A.X[ri[q] * d + k] : 0.0;
+                rc0[q] = row_const(ri[q]);
+                shift[q] = A.rowL[ri[q]];
+                unknown |= (rv[q] && !(shift[q] < INFINITY)) ? 1 : 0;
+            }
+            __syncthreads();
+            if (tid == 0) sflag = 0;
+            __syncthreads();
+            if (unknown) atomicOr(&sflag, 1);
+            __syncthreads();
+            bool need_max = sflag != 0;
+            double S[RW];
+            for (int attempt = 0; attempt < 2; attempt++) {
+                if (need_max) {
+                    // exact row maximum of the argument
+                    double mx[RW];
+#pragma unroll
+                    for (int q = 0; q < RW; q++) mx[q] = -INFINITY;
+                    for (long long ja = 0; ja < m; ja += CH) {
+                        const int len = (int)std::min<long long>(CH, m - ja);
+                        __syncthreads();
+                        stage_cols(ja, len);
+                        __syncthreads();
+                        for (int c = lane; c < len; c += 64) {
+                            double y[DD];
+#pragma unroll
+                            for (int k = 0; k < DD; k++) y[k] = D > 0 ? ysl[(size_t)k * CH + c] : 0.0;
+                            const double xh = xhl[c];
+#pragma unroll
+                            for (int q = 0; q < RW; q++) {
+                                double t;
+                                if (D == 0) t = fma(-(double)A.C[ri[q] * A.ldc + ja + c], kap2, xh);
+                                else t = arg_pts(xt[q], rc0[q], y, xh);
+                                mx[q] = fmax(mx[q], t);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < RW; q++) shift[q] = wave_max(mx[q]);
+                }
+                double acc[RW];
+#pragma unroll
+                for (int q = 0; q < RW; q++) acc[q] = 0.0;
+                for (long long ja = 0; ja < m; ja += CH) {
+                    const int len = (int)std::min<long long>(CH, m - ja);
+                    __syncthreads();
+                    stage_cols(ja, len);
+                    __syncthreads();
+                    float sp[RW];
+#pragma unroll
+                    for (int q = 0; q < RW; q++) sp[q] = 0.f;
+                    for (int c = lane; c < len; c += 64) {
+                        double y[DD];
+#pragma unroll
+                        for (int k = 0; k < DD; k++) y[k] = D > 0 ? ysl[(size_t)k * CH + c] : 0.0;
+                        const double xh = xhl[c];
+#pragma unroll
+                        for (int q = 0; q < RW; q++) {
+                            double t;
+                            if (D == 0) t = fma(-(double)A.C[ri[q] * A.ldc + ja + c], kap2, xh) - shift[q];
+                            else t = arg_pts(xt[q], rc0[q] - shift[q], y, xh);
+                            sp[q] += __builtin_amdgcn_exp2f((float)t);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < RW; q++) acc[q] += (double)sp[q];
+                }
+                int bad = 0;
+#pragma unroll
+                for (int q = 0; q < RW; q++) {
+                    S[q] = readlane63_f64(wave_sum_l63(acc[q]));
+                    bad |= (rv[q] && !(S[q] >= 0x1p-40 && S[q] <= 0x1p40)) ? 1 : 0;
+                }
+                __syncthreads();
+                if (tid == 0) sflag = 0;
+                __syncthreads();
+                if (bad) atomicOr(&sflag, 1);
+                __syncthreads();
+                if (sflag == 0 || need_max) break;
+                need_max = true;  // redo the group with the exact maximum
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < RW; q++) {
+                    if (!rv[q]) continue;
+                    const double lse = shift[q] + dlog2(S[q]);  // log2-sum-exp of the row (without r_i)
+                    A.rowL[ri[q]] = lse;
+                    A.rowU[ri[q]] = A.la2[ri[q]] - lse;  // u_i = log a_i - LSE_j t_ij, log2 units
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    // ---- column sweep: per-block column sums ---------------------------------
+    // EXACT = false: sum of 2^(t_ij + u_i - L_j) into partf, with L_j the
+    // column's log2-sum of the previous step (max log2 a on the first step), so
+    // the dominant terms have arguments near 0 and keep FP32 exponential
+    // accuracy; the combined sum is checked against [2^-64, 2^64].
+    // EXACT = true: per-column maximum m_j of t_ij + u_i over the block's rows,
+    // then sum of 2^(t_ij + u_i - m_j) into part / partmax.
+    auto col_sweep = [&](bool exact) {
+        for (long long ja = 0; ja < m; ja += CH) {
+            double y[CPL][DD], xh[CPL];
+            long long jc[CPL];
+            bool cv[CPL];
+#pragma unroll
+            for (int p = 0; p < CPL; p++) {
+                const long long c = (long long)wid * 64 * CPL + lane + 64 * p;
+                cv[p] = ja + c < m;
+                jc[p] = std::min(ja + c, m - 1);
+#pragma unroll
+                for (int k = 0; k < DD; k++) y[p][k] = (D > 0 && k < d) ? (double)A.Y[jc[p] * d + k] : 0.0;
+                xh[p] = col_term(jc[p]);
+            }
+            double cmx[CPL], acc[CPL];
+#pragma unroll
+            for (int p = 0; p < CPL; p++) {
+                cmx[p] = exact ? -INFINITY : A.colL[jc[p]];
+                acc[p] = 0.0;
+            }
+            for (int sweep = exact ? 0 : 1; sweep < 2; sweep++) {
+                for (long long rb0 = 0; rb0 < nr; rb0 += kTRB) {
+                    const int rl = (int)std::min<long long>(kTRB, nr - rb0);
+                    __syncthreads();
+                    for (int r = tid; r < rl; r += kTT) {
+                        const long long i = r0 + rb0 + r;
+#pragma unroll
+                        for (int k = 0; k < DD; k++)
+                            xtl[(size_t)k * kTRB + r] = (D > 0 && k < d) ? coef * (double)A.X[i * d + k] : 0.0;
+                        rhl[r] = row_const(i) + A.rowU[i];
+                    }
+                    __syncthreads();
+                    float sp[CPL];
+#pragma unroll
+                    for (int p = 0; p < CPL; p++) sp[p] = 0.f;
+                    for (int r = 0; r < rl; r++) {
+                        double xt[DD];
+#pragma unroll
+                        for (int k = 0; k < DD; k++) xt[k] = D > 0 ? xtl[(size_t)k * kTRB + r] : 0.0;
+                        const double rh = rhl[r];
+#pragma unroll
+                        for (int p = 0; p < CPL; p++) {
+                            double t;
+                            if (D == 0) t = fma(-(double)A.C[(r0 + rb0 + r) * A.ldc + jc[p]], kap2, xh[p]) + rh;
+                            else t = arg_pts(xt, rh, y[p], xh[p]);
+                            if (sweep == 0) cmx[p] = fmax(cmx[p], t);
+                            else sp[p] += __builtin_amdgcn_exp2f((float)(t - cmx[p]));
+                        }
+                        if ((r & 7) == 7) {
+#pragma unroll
+                            for (int p = 0; p < CPL; p++) {
+                                acc[p] += (double)sp[p];
+                                sp[p] = 0.f;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int p = 0; p < CPL; p++) acc[p] += (double)sp[p];
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < CPL; p++) {
+                if (!cv[p]) continue;
+                if (exact) {
+                    A.part[(size_t)bid * m + jc[p]] = acc[p];
+                    A.partmax[(size_t)bid * m + jc[p]] = cmx[p];
+                } else {
+                    A.partf[(size_t)bid * m + jc[p]] = (float)acc[p];
+                }
+            }
+        }
+    };
+
+    double mu = A.mu0, alpha = dsqrt(2.0 * A.mu0);
+    long long mstage = A.m0, kin = 0, it = 0, steps = 0, fallbacks = 0;
+    bool first = true;
+    unsigned long long gen = 0;
+    int status = ACCSK_OK;
+    double err = 0.0, last_mass = 0.0, last_xb2 = 0.0, eot = 0.0, fval = 0.0, cost_total = NAN;
+
+    for (long long step = 0;; step++) {
+        const int par = (int)(step & 1);
+        double *bs = A.bscal + (size_t)par * G * kTNS;
+        row_sweep();
+        col_sweep(false);
+        if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
+
+        bool exact = false;
+        for (int pass = 0; pass < 2; pass++) {
+            if (pass == 1) {
+                if (!exact) break;
+                col_sweep(true);
+                if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
+                fallbacks++;
+            }
+            // combine the column slice [j0, j1): thread t sums blocks grp, grp + NGRP, ... of column cb + t % CW
+            constexpr int CW = 32, NGRP = kTT / CW;
+            const int coff = tid % CW, grp = tid / CW;
+            double aS = 0.0, aE = 0.0, aC = 0.0, aXB = 0.0, aFB = 0.0;
+            for (long long cb = j0; cb < j1; cb += CW) {
+                const long long j = cb + coff;
+                double acc = 0.0, pm = -INFINITY;
+                if (pass == 0) {
+                    if (j < j1)
+                        for (int b = grp; b < G; b += NGRP) acc += (double)A.partf[(size_t)b * m + j];
+                } else {
+                    if (j < j1)
+                        for (int b = grp; b < G; b += NGRP) pm = fmax(pm, A.partmax[(size_t)b * m + j]);
+                    sred[tid] = pm;
+                    __syncthreads();
+                    pm = -INFINITY;
+                    for (int q = 0; q < NGRP; q++) pm = fmax(pm, sred[q * CW + coff]);
+                    __syncthreads();
+                    if (j < j1)
+                        for (int b = grp; b < G; b += NGRP) {
+                            const double mb = A.partmax[(size_t)b * m + j];
+                            if (mb > -INFINITY) acc += A.part[(size_t)b * m + j] * dexp2(mb - pm);
+                        }
+                }
+                sred[tid] = acc;
+                __syncthreads();
+                if (tid < CW && j < j1) {
+                    double sc = 0.0;
+                    for (int q = 0; q < NGRP; q++) sc += sred[q * CW + tid];
+                    const double xj = A.xg[j];
+                    double lc2, c;  // log2 c_j and c_j, the column sum of P at (u(x), x)
+                    if (pass == 0) {
+                        lc2 = A.colL[j] + dlog2(sc);
+                        if (!(sc >= 0x1p-64 && sc <= 0x1p64)) aFB += 1.0;
+                    } else {
+                        lc2 = pm + dlog2(sc);
+                    }
+                    c = dexp2(lc2);
+                    A.colL[j] = lc2;  // next step's shift (only this block reads or writes column j here)
+                    // c_j = sum_i 2^(t_ij + u_i) = exp(x_j + ell_j):  S^_j = log b_j - ell_j
+                    const double sh = A.lnb[j] * kLog2e - lc2 + xj;
+                    A.shat[j] = sh;
+                    aS += sh;
+                    aE += fabs(c - A.bn[j]);
+                    aC += c;
+                    aXB += xj * A.bn[j];
+                }
+                __syncthreads();
+            }
+            if (wid == 0) {
+                aS = wave_sum(aS);
+                aE = wave_sum(aE);
+                aC = wave_sum(aC);
+                aXB = wave_sum(aXB);
+                aFB = wave_sum(aFB);
+                if (lane == 0) {
+                    double *pp = bs + (size_t)bid * kTNS;
+                    xstore(&pp[1], aS);
+                    xstore(&pp[2], aE);
+                    xstore(&pp[3], aC);
+                    xstore(&pp[4], aXB);
+                    xstore(&pp[5], aFB);
+                }
+            }
+            if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
+            for (int sidx = wid; sidx < 6; sidx += kTW) {
+                double v = 0.0;
+                for (int b = lane; b < G; b += 64) v += bs[(size_t)b * kTNS + sidx];
+                v = wave_sum(v);
+                if (lane == 0) tot[sidx] = v;
+            }
+            __syncthreads();
+            exact = (pass == 0) && (tot[5] > 0.0);
+            __syncthreads();
+        }
+        if (status != ACCSK_OK) break;
+
+        err = tot[2];
+        const double mean = tot[1] / (double)m;
+        last_mass = tot[3];
+        last_xb2 = tot[4];
+        steps++;
+        if (!isfinite(err)) {
+            status = (steps == 1) ? ACCSK_NONFINITE : ACCSK_DIVERGED;
+            break;
+        }
+        // update of this block's slice of x and w (same scalars in every block)
+        bool stop = false;
+        if (A.method == ACCSK_SINKHORN) {
+            if (err < A.tol_stop || it >= A.max_iter) stop = true;
+            else {
+                for (long long j = j0 + tid; j < j1; j += kTT) A.xg[j] = A.shat[j] - mean;
+                it++;
+            }
+        } else {
+            if (!first) {
+                const double c2 = alpha * alpha - 2.0, inv = 1.0 / (1.0 + alpha);
+                for (long long j = j0 + tid; j < j1; j += kTT)
+                    A.wg[j] = (A.wg[j] + c2 * A.xg[j] + 2.0 * (A.shat[j] - mean)) * inv;
+                it++;
+                kin++;
+            }
+            if (err < A.tol_stop || it >= A.max_iter) stop = true;
+            else {
+                if (!first && kin == mstage) {
+                    const double mu_new = mu / 2.0;
+                    if (A.w_rule == ACCSK_W_Y_CONTINUOUS) {
+                        const double ratio = dsqrt(2.0 * mu_new) / alpha;
+                        for (long long j = j0 + tid; j < j1; j += kTT) A.wg[j] *= ratio;
+                    }
+                    mu = mu_new;
+                    alpha = dsqrt(2.0 * mu);
+                    mstage = (long long)floor(1.4142135623730951 * (double)mstage) + 1;
+                    kin = 0;
+                }
+                first = false;
+                const double inv = 1.0 / (1.0 + alpha);
+                for (long long j = j0 + tid; j < j1; j += kTT) A.xg[j] = (A.wg[j] + (A.shat[j] - mean)) * inv;
+            }
+        }
+        if (stop) break;
+        if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
+    }
+
+    // ---------------- outputs ----------------
+    if (status == ACCSK_OK || status == ACCSK_DIVERGED) {
+        double ua = 0.0;
+        for (long long i = r0 + tid; i < r1; i += kTT) {
+            const double u2 = A.rowU[i];
+            ua += A.an[i] * u2;
+            A.f_out[i] = A.eps * kLn2 * u2;
+        }
+        ua = tblock_sum(ua, sred);
+        for (long long j = j0 + tid; j < j1; j += kTT) A.g_out[j] = A.eps * kLn2 * A.xg[j];
+        // <C, P> at the returned potentials: C in FP64 (recomputed from the points)
+        double cst = 0.0;
+        if (!(A.flags & ACCSK_FLAG_NO_COST)) {
+            for (long long i = r0 + wid; i < r1; i += kTW) {
+                const double u2 = A.rowU[i];
+                for (long long j = lane; j < m; j += 64) {
+                    double cij;
+                    if (D == 0) {
+                        cij = (double)A.C[i * A.ldc + j];
+                    } else {
+                        double dot = 0.0;
+                        for (long long k = 0; k < d; k++) dot = fma((double)A.X[i * d + k], (double)A.Y[j * d + k], dot);
+                        cij = (sq ? A.xnrm[i] + A.ynrm[j] - 2.0 * dot : 1.0 - dot) * A.inv_s;
+                    }
+                    const double t = A.xg[j] - kap2 * cij + u2;
+                    cst += cij * (double)__builtin_amdgcn_exp2f((float)t);
+                }
+            }
+            cst = tblock_sum(cst, sred);
+        }
+        if (tid == 0) {
+            xstore(&A.uapart[bid], ua);
+            xstore(&A.costpart[bid], cst);
+        }
+        if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) status = ACCSK_HIP_ERROR;
+        if (bid == 0 && tid == 0 && status != ACCSK_HIP_ERROR) {
+            double ua2 = 0.0, c2 = 0.0;
+            for (int b = 0; b < G; b++) {
+                ua2 += A.uapart[b];
+                c2 += A.costpart[b];
+            }
+            const double ua_ln = ua2 * kLn2, xb_ln = last_xb2 * kLn2;
+            fval = 1.0 - ua_ln - xb_ln;
+            eot = A.eps * (ua_ln + xb_ln - last_mass);
+            if (!(A.flags & ACCSK_FLAG_NO_COST)) cost_total = c2;
+        }
+    }
+    if (bid == 0 && tid == 0) {
+        DevResult r;
+        r.iters = it;
+        r.steps = steps;
+        r.fallback = fallbacks;
+        r.err = err;
+        r.eot = eot;
+        r.fval = fval;
+        r.cost = cost_total;
+        r.converged = (status == ACCSK_OK && err < A.tol_stop) ? 1 : 0;
+        r.status = status;
+        *A.res = r;
+    }
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <int D>
+accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res, hipStream_t s) {
+    int dev = 0, cu = 0, occ = 0;
+    ACCSK_HIP_TRY(hipGetDevice(&dev));
+    ACCSK_HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const size_t lds = tiled_lds_bytes<D>();
+    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tiled_solve<D>, kTT, lds));
+    if (occ < 1) return ACCSK_SHAPE;
+    const long long G = (long long)std::min(occ, 2) * cu;
+    const size_t n = A.n, m = A.m;
+    size_t off = 0;
+    const size_t o_args = off; off = align_up(off + sizeof(TiledArgs));
+    const size_t o_res = off; off = align_up(off + sizeof(DevResult));
+    const size_t o_small = off; off = align_up(off + 64 * 8);  // gscal, status
+    const size_t o_bar = off; off = align_up(off + 256);
+    const size_t o_n = off; off = align_up(off + 5 * n * 8);
+    const size_t o_m = off; off = align_up(off + 7 * m * 8);
+    const size_t o_pf = off; off = align_up(off + (size_t)G * m * 4);
+    const size_t o_pe = off; off = align_up(off + 2 * (size_t)G * m * 8);
+    const size_t o_bs = off; off = align_up(off + (2 * (size_t)G * kTNS + 2 * (size_t)G) * 8);
+    char *base = nullptr;
+    if (hipMallocAsync((void **)&base, off, s) != hipSuccess) return ACCSK_OOM;
+    double *pn = (double *)(base + o_n), *pm = (double *)(base + o_m);
+    A.an = pn;
+    A.la2 = pn + n;
+    A.xnrm = pn + 2 * n;
+    A.rowL = pn + 3 * n;
+    A.rowU = pn + 4 * n;
+    A.bn = pm;
+    A.lnb = pm + m;
+    A.ynrm = pm + 2 * m;
+    A.xg = pm + 3 * m;
+    A.wg = pm + 4 * m;
+    A.shat = pm + 5 * m;
+    A.colL = pm + 6 * m;
+    A.partf = (float *)(base + o_pf);
+    A.part = (double *)(base + o_pe);
+    A.partmax = A.part + (size_t)G * m;
+    A.bscal = (double *)(base + o_bs);
+    A.uapart = A.bscal + 2 * (size_t)G * kTNS;
+    A.costpart = A.uapart + G;
+    A.gscal = (double *)(base + o_small);
+    A.status = (int *)(A.gscal + 8);
+    A.bar = (unsigned long long *)(base + o_bar);
+    A.res = (DevResult *)(base + o_res);
+    A.tol = p->tol;
+    A.tol_stop = p->tol * (1.0 - 1.0 / 16.0);
+    A.mu0 = p->mu0;
+    A.max_iter = p->max_iter;
+    A.m0 = p->m0;
+    A.method = p->method;
+    A.w_rule = p->w_rule;
+    A.flags = p->flags;
+    TiledArgs *d_args = (TiledArgs *)(base + o_args);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+    if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+    hipError_t e = hipMemcpyAsync(d_args, &A, sizeof(TiledArgs), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(base + o_bar, 0, 256, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(tiled_setup, dim3(1), dim3(1024), 0, s, (const TiledArgs *)d_args);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
+    if (e == hipSuccess) {
+        void *kargs[] = {&d_args};
+        e = hipLaunchCooperativeKernel((const void *)tiled_solve<D>, dim3((unsigned)G), dim3(kTT), kargs, lds, s);
+    }
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    DevResult hr{};
+    if (e == hipSuccess) e = hipMemcpyAsync(&hr, base + o_res, sizeof(DevResult), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    float kms = -1.f;
+    if (e == hipSuccess && ev0 && ev1 && hipEventElapsedTime(&kms, ev0, ev1) != hipSuccess) kms = -1.f;
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipFreeAsync(base, s);
+    if (e != hipSuccess) return ACCSK_HIP_ERROR;
+    res->iters = hr.iters;
+    res->sinkhorn_steps = hr.steps;
+    res->fallback_steps = hr.fallback;
+    res->marginal_err = hr.err;
+    res->eot_value = hr.eot;
+    res->transport_cost = hr.cost;
+    res->dual_fval = hr.fval;
+    res->kernel_ms = kms;
+    res->converged = hr.converged;
+    res->status = hr.status;
+    if (hr.status == ACCSK_OK && !hr.converged) res->status = ACCSK_NOT_CONVERGED;
+    return ACCSK_OK;
+}
+
+}  // namespace
+}  // namespace accsk
+
+using namespace accsk;
+
+// Tiled solve of one problem (explicit C when X is null, else points with d <= 16).
+accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, const float *Y, int64_t d, int kind,
+                               double cost_scale, int64_t n, int64_t m, const double *a, const double *b,
+                               const accsk_params *p, double eps, double *f_out, double *g_out, accsk_result *res,
+                               hipStream_t s) {
+    TiledArgs A{};
+    A.C = C;
+    A.ldc = ldc;
+    A.X = X;
+    A.Y = Y;
+    A.d = X ? d : 0;
+    A.kind = kind;
+    A.inv_s = 1.0 / cost_scale;
+    A.n = n;
+    A.m = m;
+    A.a_in = a;
+    A.b_in = b;
+    A.f_out = f_out;
+    A.g_out = g_out;
+    A.eps = eps;
+    accsk_status st;
+    if (!X) st = tiled_launch<0>(A, p, res, s);
+    else if (d <= 3) st = tiled_launch<3>(A, p, res, s);
+    else if (d <= 8) st = tiled_launch<8>(A, p, res, s);
+    else if (d <= 16) st = tiled_launch<16>(A, p, res, s);
+    else st = ACCSK_SHAPE;
+    if (st != ACCSK_OK) return st;
+    return (accsk_status)res->status;
+}

@@ -125,7 +125,8 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
     double *la2 = bn + m;       // [n] log2 a (normalized)
     double *rowM = la2 + n;     // [n] row shift of the last strip
     double *rowS = rowM + n;    // [n] row sum of the last strip
-    double *wpart = rowS + n;   // [NW][m] per-wave column sums
+    double *afac = rowS + n;    // [n] a_i / max a
+    double *wpart = afac + n;   // [NW][m] per-wave column sums
 
     // ---------------- set-up: validation, unit mass (eq:Fc), logs ----------------
     int bad = 0;
@@ -173,6 +174,7 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
     }
     const double La2 = wg_max<NW>(mx, red);
     const double maxa = exp2(La2);
+    for (int i = tid; i < n; i += TPB) afac[i] = exp2(la2[i] - La2);
     __syncthreads();
 
     double mu = ctl.mu0, alpha = sqrt(2.0 * ctl.mu0);
@@ -246,8 +248,7 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
             const double S = row_sum<LPR>((double)pv[0]);
             // P_ij / max a = e_ij * 2^(log2 a_i - La2) / S_i   (u_i from eq:u-update)
             const int ri = min(r, n - 1);
-            const float rfac = rv ? __builtin_amdgcn_exp2f((float)(la2[ri] - La2)) * __builtin_amdgcn_rcpf((float)S)
-                                  : 0.f;
+            const float rfac = rv ? (float)afac[ri] * __builtin_amdgcn_rcpf((float)S) : 0.f;
 #pragma unroll
             for (int q = 0; q < NCL; q++) colacc[q] += (double)(ev[q] * rfac);
             if (li == 0 && rv) {
@@ -414,7 +415,7 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
 
 // On-chip bytes of small_body for a problem of n rows and m columns.
 inline size_t small_lds_bytes(long long n, long long m, int nw) {
-    return (size_t)(4 * m + 3 * n + (long long)nw * m) * sizeof(double);
+    return (size_t)(4 * m + 4 * n + (long long)nw * m) * sizeof(double);
 }
 
 inline bool small_finite_pos(double v) { return std::isfinite(v) && v > 0.0; }

@@ -1,0 +1,124 @@
+"""GPU parity of the tiled solver: costs formed on the fly from point clouds
+(never stored) and explicit costs with m > 8192.
+
+On the fly the exponent arguments are formed in FP64 from the FP32 points, so
+the solve is judged against the FP64 oracle on the exact FP64 cost: FP64
+marginal error <= tol (plus the FP64 rounding of the argument, far below it),
+EOT value within eps * 2e-7 (FP32 exponentials in the mass), <C,P> to 1e-6
+relative, and the stopping iterate against the oracle's error trace.
+At the full colour-transfer size (n = m = 32768, d = 3, eps = 1e-3) the
+oracle checks sampled rows and columns of the plan one by one.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+from _stopcheck import check_stop
+from paper_2605_30267_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(torch, x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _points(seed, n, m, d, kind):
+    rng = np.random.default_rng(seed)
+    if kind == 1:
+        return W.unit_rows(rng, n, d).astype(np.float32), W.unit_rows(rng, m, d).astype(np.float32)
+    return rng.uniform(0, 1, (n, d)).astype(np.float32), rng.uniform(0, 1, (m, d)).astype(np.float32)
+
+
+CASES = [(0, 500, 700, 3, 1e-2), (1, 300, 200, 8, 3e-3), (0, 64, 1500, 16, 2e-2), (0, 5, 3000, 2, 1e-2),
+         (0, 1, 1, 1, 1e-1), (0, 2000, 64, 3, 1e-3), (1, 77, 9000, 4, 1e-2)]
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("kind,n,m,d,eps", CASES)
+def test_on_the_fly_matches_oracle(torch_gpu, kind, n, m, d, eps, method):
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    X, Y = _points(100 + n + m, n, m, d, kind)
+    rng = np.random.default_rng(n * m)
+    a, b = rng.uniform(0.5, 1.5, n), rng.uniform(0.5, 1.5, m)
+    raw = O.cost_points(kind, X, Y, 1.0)
+    s = float(raw.max()) if kind == 0 else 1.0
+    C = raw / s
+    f, g, res = accsk.solve_points(_dev(torch, X, torch.float32), _dev(torch, Y, torch.float32),
+                                   _dev(torch, a, torch.float64), _dev(torch, b, torch.float64), eps, kind=kind,
+                                   cost_scale=s, on_the_fly=True, method=method)
+    torch.cuda.synchronize()
+    r = res[0]
+    an, bn = a / a.sum(), b / b.sum()
+    ev = O.evaluate(C, eps, an, bn, f.cpu().numpy(), g.cpu().numpy())
+    print((kind, n, m, d, eps, method), "It", r["iters"], "err", ev["err"], "fallback", r["fallback_steps"],
+          "ms", r["kernel_ms"], flush=True)
+    assert r["status"] == 0 and r["converged"] == 1, r
+    assert ev["err"] <= 1e-6 * 1.0001
+    assert abs(r["eot_value"] - ev["dual"]) <= 2e-7 * eps + 1e-12 * abs(ev["dual"])
+    assert abs(r["transport_cost"] - ev["cost"]) <= 1e-6 * abs(ev["cost"]) + 1e-13
+    dp = accsk.default_params()
+    check_stop(C, an, bn, eps, 1e-6, O.ACC if method == 1 else O.SINKHORN, r["iters"], dp.mu0, dp.m0, dp.w_rule)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_tiled_explicit_large_m(torch_gpu, eps):
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    p = W.random_dense(seed=61, n=150, m=9001, eps=eps, a_kind="dirichlet")
+    C = _dev(torch, p["C32"], torch.float32)
+    f, g, r = accsk.solve_dense(C, _dev(torch, p["a"], torch.float64), _dev(torch, p["b"], torch.float64), eps)
+    torch.cuda.synchronize()
+    C64 = p["C32"].astype(np.float64)
+    ev = O.evaluate(C64, eps, p["a"], p["b"], f.cpu().numpy(), g.cpu().numpy())
+    print("explicit m=9001 eps", eps, "It", r["iters"], "err", ev["err"], "fallback", r["fallback_steps"], flush=True)
+    assert r["converged"] == 1 and ev["err"] <= 1e-6 * 1.0001
+    assert abs(r["eot_value"] - ev["dual"]) <= 2e-7 * eps + 1e-12 * abs(ev["dual"])
+    dp = accsk.default_params()
+    check_stop(C64, p["a"], p["b"], eps, 1e-6, O.ACC, r["iters"], dp.mu0, dp.m0, dp.w_rule)
+
+
+@pytest.mark.parametrize("kind,n,m,d", [(0, 300, 257, 3), (1, 129, 1000, 300), (0, 17, 5, 1), (0, 2000, 1500, 3)])
+def test_cost_max_points(torch_gpu, kind, n, m, d):
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    X, Y = _points(7 + n, n, m, d, kind)
+    got = accsk.cost_max_points(_dev(torch, X, torch.float32), _dev(torch, Y, torch.float32), kind=kind)
+    ref = O.cost_points(kind, X, Y, 1.0).max()
+    assert abs(got - ref) <= 1e-15 * max(1.0, abs(ref))
+
+
+def test_color_transfer_full_size_sampled(torch_gpu):
+    """n = m = 32768 RGB points, eps = 1e-3, cost / exact max, formed on the fly."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    p = W.color_points(seed=3, n=32768, m=32768, eps=1e-3)
+    Xd, Yd = _dev(torch, p["X"], torch.float32), _dev(torch, p["Y"], torch.float32)
+    s = accsk.cost_max_points(Xd, Yd)
+    f, g, res = accsk.solve_points(Xd, Yd, _dev(torch, p["a"], torch.float64), _dev(torch, p["b"], torch.float64),
+                                   p["eps"], cost_scale=s, on_the_fly=True)
+    torch.cuda.synchronize()
+    r = res[0]
+    print("colour transfer 32768^2: It", r["iters"], "steps", r["sinkhorn_steps"], "err", r["marginal_err"],
+          "kernel ms", r["kernel_ms"], "fallback", r["fallback_steps"], flush=True)
+    assert r["status"] == 0 and r["converged"] == 1
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    X, Y = p["X"].astype(np.float64), p["Y"].astype(np.float64)
+    an, bn = p["a"] / p["a"].sum(), p["b"] / p["b"].sum()
+    rng = np.random.default_rng(0)
+    # sampled rows: the row solve is exact, so each row marginal matches a_i to FP32-exponential accuracy
+    for i in rng.choice(32768, 48, replace=False):
+        Ci = ((X[i] - Y) ** 2).sum(axis=1) / s
+        ri = np.exp((f[i] + g - Ci) / p["eps"]).sum()
+        assert abs(ri - an[i]) <= 1e-6 * an[i] + 1e-300
+    # sampled columns: sum_j |c_j - b_j| <= tol overall; each sampled column within tol
+    tot = 0.0
+    for j in rng.choice(32768, 48, replace=False):
+        Cj = ((X - Y[j]) ** 2).sum(axis=1) / s
+        cj = np.exp((f + g[j] - Cj) / p["eps"]).sum()
+        tot += abs(cj - bn[j])
+    assert tot <= 1e-6
+    # the dual value at the returned potentials is the EOT value: <f, a> + <g, b> - eps * mass, mass ~ 1
+    assert abs(r["eot_value"] - (f @ an + g @ bn - p["eps"])) <= 2e-6 * p["eps"]
