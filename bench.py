@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--with-copy", action="store_true", help="run the copy calibration first, in the same process")
     ap.add_argument("--color", type=int, default=1, help="also time the colour-transfer on-the-fly solve (1/0)")
     ap.add_argument("--serving", type=int, default=1, help="also run the serving stream (1/0)")
+    ap.add_argument("--diff", type=int, default=1, help="also time the differentiable batched loss (1/0)")
+    ap.add_argument("--small-batch", type=int, default=1, help="also time a batch of 1024 small problems (1/0)")
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--serve-split", type=int, default=3, help="cost split of the served requests (0, 2, 3)")
     return ap.parse_args()
@@ -55,9 +57,9 @@ def kernel_name(m):
     if m <= 512:
         return "dense_solve<128,1,2>"
     if m <= 1024:
-        return "dense_solve<256,1,2>"
+        return "dense_solve<256,1,4>"
     if m <= 2048:
-        return "dense_solve<512,1,2>"
+        return "dense_solve<512,1,4>"
     if m <= 4096:
         return "dense_solve<1024,1,2>"
     return "dense_solve<1024,2,1>"
@@ -133,6 +135,98 @@ def color_bench(args, dev):
                          "frac": achieved / peak, "slots_per_entry": OTF_SLOTS_PER_ENTRY})
     log("colour transfer: It %d, %.1f ms/solve, %.1f us/step, ALU frac %.3f"
         % (r["iters"], 1e3 * dt, out["us_per_step"], out["roofline"]["frac"]))
+    return out
+
+
+BF16_MFMA_PEAK = 2.5e15     # MI355X dense BF16 matrix-core peak, flop/s
+FP64_PEAK = 78.6e12         # MI355X FP64 vector peak, flop/s
+EXP_PEAK = 256 * 64 / 4 * 2.4e9  # v_exp_f32 at quarter rate: 9.8e12 exponentials/s
+
+
+def timed(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def diff_bench(args, dev):
+    """Differentiable EOT loss: 64 problems, n = m = 2048, d = 64, N(0, I) points,
+    cost / (2 d), eps = 5e-3, BF16x3 matrix-core cost, forward Acc-Sinkhorn then
+    the envelope-theorem backward (P recomputed tile by tile)."""
+    import torch
+
+    from paper_2605_30267_amd import accsk
+    from paper_2605_30267_amd import workloads as W
+
+    B, n, m, d = 64, 2048, 2048, 64
+    p = W.gaussian_batch(seed=5, batch=B, n=n, m=m, d=d, eps=5e-3)
+    X = torch.as_tensor(p["X"], device=dev)
+    Y = torch.as_tensor(p["Y"], device=dev)
+    a = torch.as_tensor(p["a"], dtype=torch.float64, device=dev)
+    b = torch.as_tensor(p["b"], dtype=torch.float64, device=dev)
+    s = p["scale"]
+
+    def fwd_bwd():
+        Xr = X.clone().requires_grad_(True)
+        Yr = Y.clone().requires_grad_(True)
+        vals = accsk.eot_loss(Xr, Yr, a, b, p["eps"], cost_scale=s, split=3)
+        vals.sum().backward()
+        return vals, Xr.grad
+
+    fwd_bwd()
+    t_all, (vals, gx) = timed(fwd_bwd, 2)
+    t_fwd, (f, g, res) = timed(lambda: accsk.solve_points(X, Y, a, b, p["eps"], cost_scale=s, split=3), 2)
+    t_bwd, _ = timed(lambda: accsk.backward_points(X, Y, a, b, f, g, p["eps"], cost_scale=s), 3)
+    C = torch.empty((n, m), dtype=torch.float32, device=dev)
+    t_cost, _ = timed(lambda: [accsk.cost_points(X[k], Y[k], cost_scale=s, split=3, out=C) for k in range(B)], 3)
+    its = [r["iters"] for r in res]
+    cost_flops = B * n * m * d * 2.0 * 6  # six BF16 products per split-3 cross term
+    # backward, per side and entry: d FMA (cost) and d FMA (P times points), 2 flop each
+    bwd_flops = 2.0 * B * n * m * (2 * d) * 2
+    out = dict(workload="differentiable EOT loss: 64 problems, n=m=2048, d=64, N(0,I) points, cost/128, eps=5e-3, "
+                        "BF16x3 cost, forward Acc-Sinkhorn + envelope-theorem backward",
+               problems_per_s=B / t_all, ms_fwd_bwd=1e3 * t_all, ms_forward=1e3 * t_fwd, ms_backward=1e3 * t_bwd,
+               mean_iters=sum(its) / B, all_converged=all(r["converged"] == 1 for r in res),
+               cost_build={"ms": 1e3 * t_cost, "tflops": cost_flops / t_cost / 1e12,
+                           "frac_of_bf16_peak": cost_flops / t_cost / BF16_MFMA_PEAK},
+               backward={"ms": 1e3 * t_bwd, "tflops_fp64": bwd_flops / t_bwd / 1e12,
+                         "frac_of_fp64_peak": bwd_flops / t_bwd / FP64_PEAK})
+    log("diff loss: %.1f problems/s (fwd %.1f ms, bwd %.1f ms), cost build %.1f TFLOP/s, backward %.1f TFLOP/s"
+        % (out["problems_per_s"], out["ms_forward"], out["ms_backward"], out["cost_build"]["tflops"],
+           out["backward"]["tflops_fp64"]))
+    return out
+
+
+def small_batch_bench(args, dev):
+    """1024 independent problems shaped like the 256 x 256 uniform case (eps 1e-2),
+    one workgroup each; exponentials per second against the v_exp_f32 ceiling."""
+    import torch
+
+    from paper_2605_30267_amd import accsk
+    from paper_2605_30267_amd import workloads as W
+
+    probs = []
+    for k in range(1024):
+        q = W.small_uniform(seed=1000 + k)
+        probs.append((torch.as_tensor(q["C32"], device=dev), torch.as_tensor(q["a"], dtype=torch.float64, device=dev),
+                      torch.as_tensor(q["b"], dtype=torch.float64, device=dev), 1e-2))
+    accsk.solve_batch(probs[:8])
+    t, (outs, res, st) = timed(lambda: accsk.solve_batch(probs, flags=accsk.FLAG_NO_COST), 2)
+    steps = sum(r["sinkhorn_steps"] for r in res)
+    exps = steps * 256.0 * 256.0  # one exponential per entry and step (row and column sums share it)
+    kt = res[0]["kernel_ms"] * 1e-3  # the launch that solved all 1024 problems
+    out = dict(workload="1024 independent 256x256 problems (uniform points, cost/max, U(0.5,1.5) marginals), "
+                        "eps=1e-2, Acc-Sinkhorn, tol 1e-6, one workgroup per problem",
+               problems_per_s=1024 / t, ms=1e3 * t, kernel_ms=1e3 * kt, problems_per_s_kernel=1024 / kt,
+               mean_iters=sum(r["iters"] for r in res) / 1024,
+               all_converged=all(r["converged"] == 1 for r in res), exp_per_s=exps / kt,
+               frac_of_exp_peak=exps / kt / EXP_PEAK)
+    log("small batch: %.0f problems/s (%.0f/s in the kernel), %.2e exp/s (%.3f of the exp ceiling)"
+        % (out["problems_per_s"], out["problems_per_s_kernel"], out["exp_per_s"], out["frac_of_exp_peak"]))
     return out
 
 
@@ -287,6 +381,8 @@ def main():
             context["eps=%g" % eps] = row
 
     color = color_bench(args, dev) if args.color else None
+    diff = diff_bench(args, dev) if args.diff else None
+    small = small_batch_bench(args, dev) if args.small_batch else None
     serving = serving_bench(args, dev) if args.serving else None
 
     cpu = None
@@ -339,6 +435,8 @@ def main():
         "cpu_baseline": cpu,
         "context": context,
         "colour_transfer": color,
+        "differentiable_loss": diff,
+        "small_batch": small,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

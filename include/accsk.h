@@ -90,7 +90,8 @@ typedef struct {
                                convergence), FP64-evaluated unless ACCSK_FLAG_NO_COST */
     double transport_cost;  /* <C,P> at the returned potentials (NaN if skipped) */
     double dual_fval;       /* reduced dual objective f(x) = 1 - <u,a> - <x,b> at eps = 1 (Lemma coercivity) */
-    double kernel_ms;       /* duration of the persistent solve kernel (HIP events on `stream`) */
+    double kernel_ms;       /* duration of the solve kernel (HIP events on `stream`); for a batch, the
+                               launch that solved this problem (shared by the problems of that launch) */
     int32_t converged;      /* 1 if marginal_err < tol */
     int32_t status;         /* accsk_status of the call */
 } accsk_result;

@@ -993,8 +993,8 @@ accsk_status dense_chunk_cfg(long long mmax, const std::vector<HostProb> &hp, in
                              const accsk_params *p, accsk_result *res, hipStream_t s, int cu) {
     if (mmax <= 256) return dense_chunk<64, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
     if (mmax <= 512) return dense_chunk<128, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
-    if (mmax <= 1024) return dense_chunk<256, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
-    if (mmax <= 2048) return dense_chunk<512, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 1024) return dense_chunk<256, 1, 4, VEC>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 2048) return dense_chunk<512, 1, 4, VEC>(hp, k0, k1, p, res, s, cu);
     if (mmax <= 4096) return dense_chunk<1024, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
     return dense_chunk<1024, 2, 1, VEC>(hp, k0, k1, p, res, s, cu);
 }

@@ -18,7 +18,7 @@
 //
 // Backward (envelope theorem; the paper's primal map eq:P-from-dual gives
 // dEOT/dC = P): with P_ij = exp((f_i + g_j - C_ij)/eps) recomputed tile by
-// tile (never stored),
+// tile (never stored) as FP32 exponentials of FP64 arguments,
 //   sq-Euclidean: dX_i = (2/s) (r_i x_i - sum_j P_ij y_j),
 //                 dY_j = (2/s) (c_j y_j - sum_i P_ij x_i),
 //   cosine:       dX_i = -(1/s) sum_j P_ij y_j,  dY_j = -(1/s) sum_i P_ij x_i,
@@ -65,18 +65,19 @@ __global__ __launch_bounds__(256) void cost_fp64(const float *__restrict__ X, co
                                                  long long n, long long m, long long d, double inv_s,
                                                  float *__restrict__ C, long long ldc) {
     extern __shared__ float sm[];
-    float *xs = sm;           // [16][d]
-    float *ys = sm + 16 * d;  // [16][d]
+    const long long ld = d + 1;  // padded row stride: rows start in different banks
+    float *xs = sm;              // [16][d + 1]
+    float *ys = sm + 16 * ld;    // [16][d + 1]
     const long long i0 = (long long)blockIdx.y * 16, j0 = (long long)blockIdx.x * 16;
     for (long long t = threadIdx.x; t < 16 * d; t += 256) {
         const long long r = t / d, k = t % d;
-        xs[t] = (i0 + r < n) ? X[(i0 + r) * d + k] : 0.f;
-        ys[t] = (j0 + r < m) ? Y[(j0 + r) * d + k] : 0.f;
+        xs[r * ld + k] = (i0 + r < n) ? X[(i0 + r) * d + k] : 0.f;
+        ys[r * ld + k] = (j0 + r < m) ? Y[(j0 + r) * d + k] : 0.f;
     }
     __syncthreads();
     const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
     const long long i = i0 + r, j = j0 + c;
-    const double acc = cross_fp64<KIND>(xs + r * d, ys + c * d, d);
+    const double acc = cross_fp64<KIND>(xs + r * ld, ys + c * ld, d);
     if (i < n && j < m) C[i * ldc + j] = finish_fp64<KIND>(acc, inv_s);
 }
 
@@ -113,7 +114,15 @@ __global__ __launch_bounds__(256) void cost_mfma(const float *__restrict__ X, co
 // ---------------------------------------------------------------------------
 constexpr int kBR = 16, kBC = 64;
 
-template <int KIND>
+// 2^t for an FP64 argument: FP32 exponential of the fractional part, exact
+// scaling by the integer part, so the FP32 rounding of a large |t| does not
+// enter (relative error of a few FP32 ulps).
+__device__ __forceinline__ float exp2_split(double t) {
+    const double h = rint(fmax(t, -1000.0));
+    return ldexpf(__builtin_amdgcn_exp2f((float)(t - h)), (int)h);
+}
+
+template <int KIND, int NQ>
 __global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, const float *__restrict__ Y,
                                                  long long n, long long m, long long d, double inv_s,
                                                  double inv_eps, const double *__restrict__ f,
@@ -129,38 +138,42 @@ __global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, co
     f += bidx * sf;
     g += bidx * sg;
     dX += bidx * sX;
-    float *xs = sm;                       // [16][d]
-    float *ys = xs + kBR * d;             // [64][d]
-    float *ps = ys + kBC * d;             // [16][64]
+    const long long ld = d + 1;           // padded row stride (bank spread)
+    float *xs = sm;                       // [16][d + 1]
+    float *ys = xs + kBR * ld;            // [64][d + 1]
+    float *ps = ys + kBC * ld;            // [16][64]
+    double *gk = reinterpret_cast<double *>(ps + kBR * kBC);  // [64] g_j log2(e) / eps
     const long long i0 = (long long)blockIdx.x * kBR;
     const int tid = threadIdx.x;
+    const double k2 = inv_eps * kLog2e;   // log2 units: P_ij = 2^((f_i + g_j - C_ij) log2(e) / eps)
     for (long long t = tid; t < kBR * d; t += 256) {
         const long long r = t / d;
-        xs[t] = (i0 + r < n) ? X[(i0 + r) * d + (t % d)] : 0.f;
+        xs[r * ld + (t % d)] = (i0 + r < n) ? X[(i0 + r) * d + (t % d)] : 0.f;
     }
     // each thread accumulates (row tr, features tk, tk+16, ...) of sum_j P_ij y_j
     const int tr = tid >> 4, tk = tid & 15;
-    double acc[32];
-    const int nk = (int)((d - tk + 15) / 16);  // features handled by this thread (<= 32: d <= 512)
+    double acc[NQ];
+    const int nk = (int)((d - tk + 15) / 16);  // features handled by this thread (<= NQ: d <= 16 NQ)
 #pragma unroll
-    for (int q = 0; q < 32; q++) acc[q] = 0.0;
+    for (int q = 0; q < NQ; q++) acc[q] = 0.0;
     double rs = 0.0;
     for (long long j0 = 0; j0 < m; j0 += kBC) {
         __syncthreads();
         for (long long t = tid; t < kBC * d; t += 256) {
             const long long r = t / d;
-            ys[t] = (j0 + r < m) ? Y[(j0 + r) * d + (t % d)] : 0.f;
+            ys[r * ld + (t % d)] = (j0 + r < m) ? Y[(j0 + r) * d + (t % d)] : 0.f;
         }
+        if (tid < kBC) gk[tid] = (j0 + tid < m) ? g[j0 + tid] * k2 : 0.0;
         __syncthreads();
-        // P chunk: 16 x 64 = 1024 entries, 4 per thread
+        // P chunk: 16 x 64 = 1024 entries, 4 per thread (wave: one row, lanes: columns)
         for (int e = tid; e < kBR * kBC; e += 256) {
             const int r = e / kBC, c = e % kBC;
             const long long i = i0 + r, j = j0 + c;
             float pv = 0.f;
             if (i < n && j < m) {
-                const double acc_c = cross_fp64<KIND>(xs + r * d, ys + c * d, d);
+                const double acc_c = cross_fp64<KIND>(xs + r * ld, ys + c * ld, d);
                 const double cij = (KIND == ACCSK_SQEUCLID ? acc_c : 1.0 - acc_c) * inv_s;
-                pv = (float)exp((f[i] + g[j] - cij) * inv_eps);
+                pv = exp2_split(fma(-cij, k2, f[i] * k2 + gk[c]));
             }
             ps[e] = pv;
         }
@@ -169,8 +182,8 @@ __global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, co
             const double pv = ps[tr * kBC + c];
             if (tk == 0) rs += pv;
 #pragma unroll
-            for (int q = 0; q < 32; q++)
-                if (q < nk) acc[q] = fma(pv, (double)ys[c * d + tk + 16 * q], acc[q]);
+            for (int q = 0; q < NQ; q++)
+                if (q < nk) acc[q] = fma(pv, (double)ys[c * ld + tk + 16 * q], acc[q]);
         }
     }
     const long long i = i0 + tr;
@@ -181,11 +194,11 @@ __global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, co
     if (i >= n) return;
     const double ri = rsh[tr];
 #pragma unroll
-    for (int q = 0; q < 32; q++) {
+    for (int q = 0; q < NQ; q++) {
         if (q >= nk) break;
         const long long k = tk + 16 * q;
         double v;
-        if (KIND == ACCSK_SQEUCLID) v = 2.0 * inv_s * (ri * (double)xs[tr * d + k] - acc[q]);
+        if (KIND == ACCSK_SQEUCLID) v = 2.0 * inv_s * (ri * (double)xs[tr * ld + k] - acc[q]);
         else v = -inv_s * acc[q];
         dX[i * d + k] = (float)(gscale * v);
     }
@@ -266,8 +279,7 @@ accsk_status build_cost(const float *X, const float *Y, long long n, long long m
                         double scale, int split, float *C, long long ldc, double *norms_ws, hipStream_t s) {
     const double inv_s = 1.0 / scale;
     if (split == 0) {
-        const size_t lds = 2 * 16 * (size_t)d * sizeof(float);
-        if (lds > 64 * 1024) return ACCSK_SHAPE;
+        const size_t lds = 2 * 16 * (size_t)(d + 1) * sizeof(float);
         dim3 grid((unsigned)((m + 15) / 16), (unsigned)((n + 15) / 16));
         if (kind == ACCSK_SQEUCLID)
             hipLaunchKernelGGL(cost_fp64<ACCSK_SQEUCLID>, grid, dim3(256), lds, s, X, Y, n, m, d, inv_s, C, ldc);
@@ -440,18 +452,25 @@ extern "C" accsk_status accsk_backward_points(const float *X, const float *Y, in
     if (d > 448) return ACCSK_SHAPE;  // X, Y and P tiles staged in on-chip memory
     hipStream_t s = (hipStream_t)stream;
     const double inv_s = 1.0 / cost_scale, inv_eps = 1.0 / eps;
-    const size_t lds = ((size_t)(kBR + kBC) * d + kBR * kBC) * sizeof(float);
+    const size_t lds = ((size_t)(kBR + kBC) * (d + 1) + kBR * kBC) * sizeof(float) + kBC * sizeof(double);
     dim3 gx((unsigned)((n + kBR - 1) / kBR), (unsigned)batch), gy((unsigned)((m + kBR - 1) / kBR), (unsigned)batch);
+    auto sides = [&](auto kern) {
+        hipLaunchKernelGGL(kern, gx, dim3(256), lds, s, X, Y, n, m, d, inv_s, inv_eps, f, g, grad_scale, dX, n * d,
+                           m * d, n, m);
+        hipLaunchKernelGGL(kern, gy, dim3(256), lds, s, Y, X, m, n, d, inv_s, inv_eps, g, f, grad_scale, dY, m * d,
+                           n * d, m, n);
+    };
+    // features per thread: d <= 16 NQ
     if (kind == ACCSK_SQEUCLID) {
-        hipLaunchKernelGGL(grad_side<ACCSK_SQEUCLID>, gx, dim3(256), lds, s, X, Y, n, m, d, inv_s, inv_eps, f, g,
-                           grad_scale, dX, n * d, m * d, n, m);
-        hipLaunchKernelGGL(grad_side<ACCSK_SQEUCLID>, gy, dim3(256), lds, s, Y, X, m, n, d, inv_s, inv_eps, g, f,
-                           grad_scale, dY, m * d, n * d, m, n);
+        if (d <= 64) sides(grad_side<ACCSK_SQEUCLID, 4>);
+        else if (d <= 128) sides(grad_side<ACCSK_SQEUCLID, 8>);
+        else if (d <= 256) sides(grad_side<ACCSK_SQEUCLID, 16>);
+        else sides(grad_side<ACCSK_SQEUCLID, 28>);
     } else {
-        hipLaunchKernelGGL(grad_side<ACCSK_COSINE>, gx, dim3(256), lds, s, X, Y, n, m, d, inv_s, inv_eps, f, g,
-                           grad_scale, dX, n * d, m * d, n, m);
-        hipLaunchKernelGGL(grad_side<ACCSK_COSINE>, gy, dim3(256), lds, s, Y, X, m, n, d, inv_s, inv_eps, g, f,
-                           grad_scale, dY, m * d, n * d, m, n);
+        if (d <= 64) sides(grad_side<ACCSK_COSINE, 4>);
+        else if (d <= 128) sides(grad_side<ACCSK_COSINE, 8>);
+        else if (d <= 256) sides(grad_side<ACCSK_COSINE, 16>);
+        else sides(grad_side<ACCSK_COSINE, 28>);
     }
     if (da && a) hipLaunchKernelGGL(grad_marginal, dim3((unsigned)batch), dim3(256), 0, s, f, a, n, n, n, grad_scale, da);
     if (db && b) hipLaunchKernelGGL(grad_marginal, dim3((unsigned)batch), dim3(256), 0, s, g, b, m, m, m, grad_scale, db);

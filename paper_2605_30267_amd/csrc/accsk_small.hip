@@ -68,13 +68,22 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
     if (hipMallocAsync((void **)&buf, bytes_p + bytes_r + 256, s) != hipSuccess) return ACCSK_OOM;
     SmallProb *d_probs = (SmallProb *)buf;
     DevResult *d_res = (DevResult *)(buf + ((bytes_p + 255) & ~size_t(255)));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+    if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
     hipError_t e = hipMemcpyAsync(d_probs, hp.data(), bytes_p, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
     if (e == hipSuccess)
         e = vec ? launch_small_cfg<true>(mmax, d_probs, (int)count, ctl, d_res, lds, s)
                 : launch_small_cfg<false>(mmax, d_probs, (int)count, ctl, d_res, lds, s);
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     std::vector<DevResult> hr((size_t)count);
     if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), d_res, bytes_r, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    float kms = -1.f;
+    if (e == hipSuccess && ev0 && ev1 && hipEventElapsedTime(&kms, ev0, ev1) != hipSuccess) kms = -1.f;
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
     (void)hipFreeAsync(buf, s);
     if (e != hipSuccess) return ACCSK_HIP_ERROR;
     for (int64_t k = 0; k < count; k++) {
@@ -87,7 +96,7 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
         o.eot_value = r.eot;
         o.transport_cost = r.cost;
         o.dual_fval = r.fval;
-        o.kernel_ms = -1.0;
+        o.kernel_ms = kms;  // the whole batch's launch
         o.converged = r.converged;
         o.status = r.status;
         if (r.status == ACCSK_OK && !r.converged) o.status = ACCSK_NOT_CONVERGED;
