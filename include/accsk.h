@@ -192,6 +192,17 @@ accsk_status accsk_solve_points(const float *X, const float *Y, int64_t n, int64
                                 double *f_out, double *g_out, accsk_result *res, void *stream);
 
 /*
+ * Transport plan rows [row0, row0+rows) for point clouds (eq:P-from-dual):
+ * P_ij = exp((f_i + g_j - C_ij)/eps) with C_ij formed in FP64 from X and Y
+ * (as accsk_cost_points with split 0; cost_scale s divides the raw cost),
+ * written as FP32 to P (device, rows x m, leading dimension ldp >= m).
+ * f: device FP64[n], g: device FP64[m].  Limits: d <= 512.
+ */
+accsk_status accsk_plan_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                               double cost_scale, double eps, const double *f, const double *g, int64_t row0,
+                               int64_t rows, float *P, int64_t ldp, void *stream);
+
+/*
  * Exact maximum of the raw point-cloud cost (before division by a scale):
  * max_ij ||x_i - y_j||^2 (SQEUCLID) or max_ij (1 - <x_i, y_j>) (COSINE), each
  * entry summed in FP64 as accsk_cost_points does with split 0 (Sec. 5 divides

@@ -248,6 +248,9 @@ def _register_points(L):
     L.accsk_backward_points.restype = ctypes.c_int
     L.accsk_cost_max_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(_dbl), _vp]
     L.accsk_cost_max_points.restype = ctypes.c_int
+    L.accsk_plan_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp, _i64, _i64, _vp,
+                                    _i64, _vp]
+    L.accsk_plan_points.restype = ctypes.c_int
     L._points_ready = True
 
 
@@ -289,6 +292,25 @@ def cost_max_points(X, Y, kind=SQEUCLID):
     if st != OK:
         raise AccskError(st, "accsk_cost_max_points")
     return out.value
+
+
+def plan_points(X, Y, f, g, eps, kind=SQEUCLID, cost_scale=1.0, row0=0, rows=None, out=None):
+    """FP32 rows of the plan P_ij = exp((f_i + g_j - C_ij)/eps), C from the points in FP64."""
+    import torch
+    _check_dev(X, torch.float32, "X", 2)
+    _check_dev(Y, torch.float32, "Y", 2)
+    X, Y, f, g = X.contiguous(), Y.contiguous(), f.contiguous(), g.contiguous()
+    n, d = X.shape
+    m = Y.shape[0]
+    rows = n - row0 if rows is None else rows
+    if out is None:
+        out = torch.empty((rows, m), dtype=torch.float32, device=X.device)
+    st = _points_lib().accsk_plan_points(_ptr(X), _ptr(Y), n, m, d, int(kind), float(cost_scale), float(eps),
+                                         _ptr(f), _ptr(g), int(row0), int(rows), _ptr(out), out.stride(0),
+                                         _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_plan_points")
+    return out
 
 
 def _as_batched(X, Y, a, b):

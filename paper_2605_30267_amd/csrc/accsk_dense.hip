@@ -36,6 +36,13 @@ namespace {
 
 constexpr int kNS = 8;  // block scalar slots: 0 <u,a>, 1 sum S^, 2 err, 3 mass, 4 <x,b>, 5 fallback
 
+// Scalars carried from one Sinkhorn step to the next (identical in every thread).
+struct LoopState {
+    double mu, alpha, err, mass, xb2;
+    long long mstage, kin, it, steps, fallbacks;
+    int first;
+};
+
 struct DenseArgs {
     const float *C;
     long long n, m, ldc;
@@ -238,12 +245,20 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
     }
     __syncthreads();
 
-    double mu = A.mu0, alpha = dsqrt(2.0 * A.mu0);
-    long long mstage = A.m0, kin = 0, it = 0, steps = 0, fallbacks = 0;
-    bool first = true;
+    // Loop-carried scalars (the same in every thread) stay in LDS between update
+    // phases, so they occupy no registers during the streaming pass.
+    __shared__ LoopState ls;
+    if (tid == 0) {
+        ls.mu = A.mu0;
+        ls.alpha = dsqrt(2.0 * A.mu0);
+        ls.err = ls.mass = ls.xb2 = 0.0;
+        ls.mstage = A.m0;
+        ls.kin = ls.it = ls.steps = ls.fallbacks = 0;
+        ls.first = 1;
+    }
+    __syncthreads();
     unsigned long long gen = 0;
     int status = ACCSK_OK;
-    double err = 0.0, eot = 0.0, fval = 0.0, last_mass = 0.0, last_xb2 = 0.0;
 
     // u_i log2 e = log2 a_i - (M_i + log2 S_i) for this block's rows, from the
     // shift and sum of the last strip pass (needed by the exact column pass and
@@ -465,7 +480,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                         }
                     }
                 if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
-                fallbacks++;
+                if (tid == 0) ls.fallbacks++;
             }
             double aS = 0.0, aE = 0.0, aC = 0.0, aXB = 0.0, aFB = 0.0;
             // columns of the slice in chunks of CW; thread t sums the partials of
@@ -550,27 +565,30 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
         if (status != ACCSK_OK) break;
 
         // ---------------- update (every block, identical) ----------------
-        err = tot[2];
+        LoopState st = ls;  // uniform copy, live only in this phase
+        st.err = tot[2];
         const double mean = tot[1] / (double)m;
-        const double mass = tot[3];
-        last_mass = mass;
-        last_xb2 = tot[4];
-        steps++;
-        if (!isfinite(err)) {
-            status = (steps == 1) ? ACCSK_NONFINITE : ACCSK_DIVERGED;
-            break;
-        }
-        if (A.method == ACCSK_SINKHORN) {
+        st.mass = tot[3];
+        st.xb2 = tot[4];
+        st.steps++;
+        bool stop = false;
+        if (!isfinite(st.err)) {
+            status = (st.steps == 1) ? ACCSK_NONFINITE : ACCSK_DIVERGED;
+            stop = true;
+        } else if (A.method == ACCSK_SINKHORN) {
             // plain Sinkhorn, eq:normalized-sinkhorn: x <- S(x)
-            if (err < A.tol_stop || it >= A.max_iter) break;
+            if (st.err < A.tol_stop || st.it >= A.max_iter) {
+                stop = true;
+            } else {
 #pragma unroll
-            for (int k = 0; k < NG; k++)
+                for (int k = 0; k < NG; k++)
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const long long col = 4ll * (ctid + k * TPB) + e;
-                    if (col < m) xl_lds[col] = L.shat[col] - mean;
-                }
-            it++;
+                    for (int e = 0; e < 4; e++) {
+                        const long long col = 4ll * (ctid + k * TPB) + e;
+                        if (col < m) xl_lds[col] = L.shat[col] - mean;
+                    }
+                st.it++;
+            }
         } else {
             // Algorithm A2MD: S is Sinkhorn(x) at the current x; the w update
             // below uses it as Sinkhorn(x_{k+1}) and the next x update reuses it.
@@ -582,8 +600,8 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                     const long long col = 4ll * (ctid + k * TPB) + e;
                     S[k * 4 + e] = (col < m) ? L.shat[col] - mean : 0.0;
                 }
-            if (!first) {
-                const double c2 = alpha * alpha - 2.0, inv = 1.0 / (1.0 + alpha);
+            if (!st.first) {
+                const double c2 = st.alpha * st.alpha - 2.0, inv = 1.0 / (1.0 + st.alpha);
 #pragma unroll
                 for (int k = 0; k < NG; k++)
 #pragma unroll
@@ -591,41 +609,51 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                         const long long col = 4ll * (ctid + k * TPB) + e;
                         if (col < m) wl_lds[col] = (wl_lds[col] + c2 * xl_lds[col] + 2.0 * S[k * 4 + e]) * inv;
                     }
-                it++;
-                kin++;
+                st.it++;
+                st.kin++;
             }
-            if (err < A.tol_stop || it >= A.max_iter) break;
-            if (!first && kin == mstage) {
-                // Algorithm A2MD-homotopy: mu <- mu/2, m <- floor(sqrt(2) m) + 1
-                const double mu_new = mu / 2.0;
-                if (A.w_rule == ACCSK_W_Y_CONTINUOUS) {
-                    const double ratio = dsqrt(2.0 * mu_new) / alpha;
+            if (st.err < A.tol_stop || st.it >= A.max_iter) {
+                stop = true;
+            } else {
+                if (!st.first && st.kin == st.mstage) {
+                    // Algorithm A2MD-homotopy: mu <- mu/2, m <- floor(sqrt(2) m) + 1
+                    const double mu_new = st.mu / 2.0;
+                    if (A.w_rule == ACCSK_W_Y_CONTINUOUS) {
+                        const double ratio = dsqrt(2.0 * mu_new) / st.alpha;
 #pragma unroll
-                    for (int k = 0; k < NG; k++)
+                        for (int k = 0; k < NG; k++)
 #pragma unroll
-                        for (int e = 0; e < 4; e++) {
-                            const long long col = 4ll * (ctid + k * TPB) + e;
-                            if (col < m) wl_lds[col] *= ratio;
-                        }
+                            for (int e = 0; e < 4; e++) {
+                                const long long col = 4ll * (ctid + k * TPB) + e;
+                                if (col < m) wl_lds[col] *= ratio;
+                            }
+                    }
+                    st.mu = mu_new;
+                    st.alpha = dsqrt(2.0 * st.mu);
+                    st.mstage = (long long)floor(1.4142135623730951 * (double)st.mstage) + 1;
+                    st.kin = 0;
                 }
-                mu = mu_new;
-                alpha = dsqrt(2.0 * mu);
-                mstage = (long long)floor(1.4142135623730951 * (double)mstage) + 1;
-                kin = 0;
+                st.first = 0;
+                const double inv = 1.0 / (1.0 + st.alpha);
+#pragma unroll
+                for (int k = 0; k < NG; k++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const long long col = 4ll * (ctid + k * TPB) + e;
+                        if (col < m) xl_lds[col] = (wl_lds[col] + S[k * 4 + e]) * inv;
+                    }
             }
-            first = false;
-            const double inv = 1.0 / (1.0 + alpha);
-#pragma unroll
-            for (int k = 0; k < NG; k++)
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const long long col = 4ll * (ctid + k * TPB) + e;
-                    if (col < m) xl_lds[col] = (wl_lds[col] + S[k * 4 + e]) * inv;
-                }
         }
+        __syncthreads();  // every thread has read ls
+        if (tid == 0) ls = st;
+        __syncthreads();
+        if (stop) break;
     }
 
     // ---------------- outputs ----------------
+    __syncthreads();
+    const LoopState fin = ls;
+    double eot = 0.0, fval = 0.0;
     if (status == ACCSK_OK || status == ACCSK_DIVERGED) {
         const double ua_blk = materialize_u();  // u at the returned iterate, this block's rows
         if (tid == 0) xstore(&A.uapart[bid], ua_blk);
@@ -643,21 +671,21 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
         if (bid == 0 && tid == 0 && status != ACCSK_HIP_ERROR) {
             double ua2 = 0.0;
             for (int b = 0; b < G; b++) ua2 += A.uapart[b];
-            const double ua_ln = ua2 * kLn2, xb_ln = last_xb2 * kLn2;
+            const double ua_ln = ua2 * kLn2, xb_ln = fin.xb2 * kLn2;
             fval = 1.0 - ua_ln - xb_ln;               // f(x) = 1 - <u,a> - <x,b>
-            eot = A.eps * (ua_ln + xb_ln - last_mass);  // <f,a> + <g,b> - eps sum P
+            eot = A.eps * (ua_ln + xb_ln - fin.mass);  // <f,a> + <g,b> - eps sum P
         }
     }
     if (bid == 0 && tid == 0) {
         DevResult r;
-        r.iters = it;
-        r.steps = steps;
-        r.fallback = fallbacks;
-        r.err = err;
+        r.iters = fin.it;
+        r.steps = fin.steps;
+        r.fallback = fin.fallbacks;
+        r.err = fin.err;
         r.eot = eot;
         r.fval = fval;
         r.cost = NAN;
-        r.converged = (status == ACCSK_OK && err < A.tol_stop) ? 1 : 0;
+        r.converged = (status == ACCSK_OK && fin.err < A.tol_stop) ? 1 : 0;
         r.status = status;
         *A.res = r;
     }

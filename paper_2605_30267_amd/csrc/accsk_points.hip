@@ -231,6 +231,33 @@ __global__ __launch_bounds__(256) void grad_marginal(const double *__restrict__ 
     for (long long i = threadIdx.x; i < len; i += 256) out[i] = gscale * (pot[i] - mean) / sw_;
 }
 
+// Plan rows from points (eq:P-from-dual): 16 x 16 tiles of
+// P_ij = exp((f_i + g_j - C_ij) / eps), C_ij in FP64 as in cost_fp64, FP64
+// exponential, FP32 output.  Tile row r covers plan row row0 + r.
+template <int KIND>
+__global__ __launch_bounds__(256) void plan_points_k(const float *__restrict__ X, const float *__restrict__ Y,
+                                                     long long m, long long d, double inv_s, double inv_eps,
+                                                     const double *__restrict__ f, const double *__restrict__ g,
+                                                     long long row0, long long rows, float *__restrict__ P,
+                                                     long long ldp) {
+    extern __shared__ float sm[];
+    const long long ld = d + 1;
+    float *xs = sm, *ys = sm + 16 * ld;
+    const long long r0 = (long long)blockIdx.y * 16, j0 = (long long)blockIdx.x * 16;
+    for (long long t = threadIdx.x; t < 16 * d; t += 256) {
+        const long long r = t / d, k = t % d;
+        xs[r * ld + k] = (r0 + r < rows) ? X[(row0 + r0 + r) * d + k] : 0.f;
+        ys[r * ld + k] = (j0 + r < m) ? Y[(j0 + r) * d + k] : 0.f;
+    }
+    __syncthreads();
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    const long long rr = r0 + r, j = j0 + c;
+    if (rr >= rows || j >= m) return;
+    const double acc = cross_fp64<KIND>(xs + r * ld, ys + c * ld, d);
+    const double cij = (KIND == ACCSK_SQEUCLID ? acc : 1.0 - acc) * inv_s;
+    P[rr * ldp + j] = (float)exp((f[row0 + rr] + g[j] - cij) * inv_eps);
+}
+
 // max over a 16-row x 256-column tile of the raw cost, FP64 entries as in cost_fp64
 template <int KIND>
 __global__ __launch_bounds__(256) void cost_max_part(const float *__restrict__ X, const float *__restrict__ Y,
@@ -333,6 +360,29 @@ extern "C" accsk_status accsk_cost_points(const float *X, const float *Y, int64_
     st = build_cost(X, Y, n, m, d, kind, cost_scale, split, C, ldc, ws, s);
     if (ws) (void)hipFreeAsync(ws, s);
     return st;
+}
+
+extern "C" accsk_status accsk_plan_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                                          double cost_scale, double eps, const double *f, const double *g,
+                                          int64_t row0, int64_t rows, float *P, int64_t ldp, void *stream) {
+    accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, 0);
+    if (st != ACCSK_OK) return st;
+    if (!f || !g || !P || !finite_pos(eps)) return ACCSK_INVALID_ARG;
+    if (ldp < m || row0 < 0 || rows < 0 || row0 + rows > n) return ACCSK_SHAPE;
+    if (rows == 0) return ACCSK_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t lds = 2 * 16 * (size_t)(d + 1) * sizeof(float);
+    for (int64_t r = 0; r < rows; r += 16 * 65535) {  // grid.y limit
+        const int64_t rc = std::min<int64_t>(16 * 65535, rows - r);
+        dim3 grid((unsigned)((m + 15) / 16), (unsigned)((rc + 15) / 16));
+        if (kind == ACCSK_SQEUCLID)
+            hipLaunchKernelGGL(plan_points_k<ACCSK_SQEUCLID>, grid, dim3(256), lds, s, X, Y, m, d, 1.0 / cost_scale,
+                               1.0 / eps, f, g, row0 + r, rc, P + r * ldp, ldp);
+        else
+            hipLaunchKernelGGL(plan_points_k<ACCSK_COSINE>, grid, dim3(256), lds, s, X, Y, m, d, 1.0 / cost_scale,
+                               1.0 / eps, f, g, row0 + r, rc, P + r * ldp, ldp);
+    }
+    return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
 }
 
 extern "C" accsk_status accsk_cost_max_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d,

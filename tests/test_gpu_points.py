@@ -251,3 +251,28 @@ def test_eot_loss_autograd(torch_gpu):
         for got, ref in ((Xd.grad[k], rX), (Yd.grad[k], rY), (ad.grad[k], ra), (bd.grad[k], rb)):
             got = got.detach().cpu().numpy().astype(np.float64) / w
             assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("kind,n,m,d", [(0, 70, 133, 3), (1, 40, 90, 300), (0, 1, 1, 1)])
+def test_plan_points(torch_gpu, kind, n, m, d):
+    """P rows on demand from the points at the oracle's potentials (row range with an offset)."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    X, Y = _clouds(51 + n, n, m, d, kind)
+    rng = np.random.default_rng(n)
+    a, b = rng.uniform(0.5, 1.5, n), rng.uniform(0.5, 1.5, m)
+    s = float(d) if kind == 0 else 1.0
+    eps = 2e-2
+    C = O.cost_points(kind, X, Y, s)
+    o = O.solve(C, a, b, eps, tol=1e-10, method=O.ACC, mu0=0.25, m0=5, w_rule=O.W_Y_CONTINUOUS)
+    row0 = n // 3
+    rows = n - row0
+    P = accsk.plan_points(_dev(torch, X, torch.float32), _dev(torch, Y, torch.float32),
+                          _dev(torch, o["f"], torch.float64), _dev(torch, o["g"], torch.float64), eps, kind=kind,
+                          cost_scale=s, row0=row0, rows=rows)
+    torch.cuda.synchronize()
+    ref = O.plan(C, eps, o["f"], o["g"], row0, rows)
+    got = P.cpu().numpy().astype(np.float64)
+    big = ref > 1e-30
+    assert np.all(np.abs(got[big] - ref[big]) <= 2.0 ** -23 * ref[big])
+    assert abs(got.sum() - ref.sum()) <= 1e-6 * ref.sum()
