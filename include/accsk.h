@@ -203,6 +203,26 @@ accsk_status accsk_plan_points(const float *X, const float *Y, int64_t n, int64_
                                int64_t rows, float *P, int64_t ldp, void *stream);
 
 /*
+ * Barycentric projection of X through the plan (the colour-transfer map of
+ * Sec. 5): T_i = sum_j P_ij y_j / sum_j P_ij with P_ij = exp((f_i + g_j -
+ * C_ij)/eps) recomputed tile by tile (C in FP64, FP32 exponentials of FP64
+ * arguments, FP64 sums), never stored.  T: device FP32 n x d.  Limits: d <= 448.
+ */
+accsk_status accsk_barycentric_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                                      double cost_scale, double eps, const double *f, const double *g, float *T,
+                                      void *stream);
+
+/*
+ * Row top-k of the plan (the retrieval of Sec. 5 word alignment): for each row
+ * i the k columns with the largest P_ij, in decreasing order, decided on
+ * g_j - C_ij in FP64 (ties: lower column first).  idx: device int64 n x k;
+ * val: device FP64 n x k plan values (may be NULL).  k in {1, 5, 8}.
+ */
+accsk_status accsk_topk_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                               double cost_scale, double eps, const double *f, const double *g, int k,
+                               int64_t *idx, double *val, void *stream);
+
+/*
  * Exact maximum of the raw point-cloud cost (before division by a scale):
  * max_ij ||x_i - y_j||^2 (SQEUCLID) or max_ij (1 - <x_i, y_j>) (COSINE), each
  * entry summed in FP64 as accsk_cost_points does with split 0 (Sec. 5 divides

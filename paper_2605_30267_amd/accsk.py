@@ -251,6 +251,11 @@ def _register_points(L):
     L.accsk_plan_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp, _i64, _i64, _vp,
                                     _i64, _vp]
     L.accsk_plan_points.restype = ctypes.c_int
+    L.accsk_barycentric_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp, _vp, _vp]
+    L.accsk_barycentric_points.restype = ctypes.c_int
+    L.accsk_topk_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp, ctypes.c_int,
+                                    _vp, _vp, _vp]
+    L.accsk_topk_points.restype = ctypes.c_int
     L._points_ready = True
 
 
@@ -311,6 +316,37 @@ def plan_points(X, Y, f, g, eps, kind=SQEUCLID, cost_scale=1.0, row0=0, rows=Non
     if st != OK:
         raise AccskError(st, "accsk_plan_points")
     return out
+
+
+def barycentric_points(X, Y, f, g, eps, kind=SQEUCLID, cost_scale=1.0):
+    """T_i = sum_j P_ij y_j / sum_j P_ij (float32 [n, d]), P recomputed on the device."""
+    import torch
+    _check_dev(X, torch.float32, "X", 2)
+    _check_dev(Y, torch.float32, "Y", 2)
+    X, Y, f, g = X.contiguous(), Y.contiguous(), f.contiguous(), g.contiguous()
+    T = torch.empty_like(X)
+    st = _points_lib().accsk_barycentric_points(_ptr(X), _ptr(Y), X.shape[0], Y.shape[0], X.shape[1], int(kind),
+                                                float(cost_scale), float(eps), _ptr(f), _ptr(g), _ptr(T),
+                                                _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_barycentric_points")
+    return T
+
+
+def topk_points(X, Y, f, g, eps, k=1, kind=SQEUCLID, cost_scale=1.0):
+    """Row top-k of the plan: (int64 [n, k] column indices, float64 [n, k] plan values)."""
+    import torch
+    _check_dev(X, torch.float32, "X", 2)
+    _check_dev(Y, torch.float32, "Y", 2)
+    X, Y, f, g = X.contiguous(), Y.contiguous(), f.contiguous(), g.contiguous()
+    n = X.shape[0]
+    idx = torch.empty((n, k), dtype=torch.int64, device=X.device)
+    val = torch.empty((n, k), dtype=torch.float64, device=X.device)
+    st = _points_lib().accsk_topk_points(_ptr(X), _ptr(Y), n, Y.shape[0], X.shape[1], int(kind), float(cost_scale),
+                                         float(eps), _ptr(f), _ptr(g), int(k), _ptr(idx), _ptr(val), _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_topk_points")
+    return idx, val
 
 
 def _as_batched(X, Y, a, b):

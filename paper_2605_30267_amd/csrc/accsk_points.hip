@@ -25,6 +25,7 @@
 //   da_i = (f_i - <f, a_hat>) / sum(a),  db_j = (g_j - <g, b_hat>) / sum(b),
 // where r, c are the plan's row and column sums and a_hat = a / sum(a).
 
+#include <limits.h>
 #include <math.h>
 
 #include <algorithm>
@@ -122,7 +123,9 @@ __device__ __forceinline__ float exp2_split(double t) {
     return ldexpf(__builtin_amdgcn_exp2f((float)(t - h)), (int)h);
 }
 
-template <int KIND, int NQ>
+// MODE 0: gradient of the EOT value; MODE 1: barycentric projection
+// T_i = sum_j P_ij y_j / sum_j P_ij (written to dX, gsc unused).
+template <int KIND, int NQ, int MODE = 0>
 __global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, const float *__restrict__ Y,
                                                  long long n, long long m, long long d, double inv_s,
                                                  double inv_eps, const double *__restrict__ f,
@@ -198,9 +201,10 @@ __global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, co
         if (q >= nk) break;
         const long long k = tk + 16 * q;
         double v;
-        if (KIND == ACCSK_SQEUCLID) v = 2.0 * inv_s * (ri * (double)xs[tr * ld + k] - acc[q]);
+        if (MODE == 1) v = ri > 0.0 ? acc[q] / ri : NAN;
+        else if (KIND == ACCSK_SQEUCLID) v = 2.0 * inv_s * (ri * (double)xs[tr * ld + k] - acc[q]);
         else v = -inv_s * acc[q];
-        dX[i * d + k] = (float)(gscale * v);
+        dX[i * d + k] = (float)(MODE == 1 ? v : gscale * v);
     }
 }
 
@@ -302,6 +306,81 @@ __global__ __launch_bounds__(1024) void max_reduce(const double *__restrict__ pa
     }
 }
 
+// Row top-k of the plan: for row i the K columns with the largest
+// P_ij = exp((f_i + g_j - C_ij)/eps), i.e. the largest g_j - C_ij, compared in
+// FP64 (ties: lower column index first).  One wave per row; each lane keeps
+// its K best in registers, then K rounds of a wave-wide maximum pick the
+// result in order.
+template <int KIND, int K>
+__global__ __launch_bounds__(256) void topk_rows(const float *__restrict__ X, const float *__restrict__ Y, long long n,
+                                                 long long m, long long d, double inv_s, double inv_eps,
+                                                 const double *__restrict__ f, const double *__restrict__ g,
+                                                 long long *__restrict__ idx_out, double *__restrict__ val_out) {
+    extern __shared__ float xr_all[];  // [4][d]: the row of each wave
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const long long i = (long long)blockIdx.x * 4 + wid;
+    float *xr = xr_all + (size_t)wid * d;
+    for (long long k = lane; k < d; k += 64) xr[k] = i < n ? X[i * d + k] : 0.f;
+    __syncthreads();
+    if (i >= n) return;
+    double bv[K];
+    long long bi[K];
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        bv[q] = -INFINITY;
+        bi[q] = -1;
+    }
+    for (long long j = lane; j < m; j += 64) {
+        const double acc = cross_fp64<KIND>(xr, Y + j * d, d);
+        const double v = g[j] - (KIND == ACCSK_SQEUCLID ? acc : 1.0 - acc) * inv_s;
+        // insert (v, j) into the lane's sorted list (columns arrive in increasing j)
+        if (v > bv[K - 1]) {
+            double cv = v;
+            long long ci = j;
+#pragma unroll
+            for (int q = 0; q < K; q++) {
+                if (cv > bv[q]) {
+                    const double tv = bv[q];
+                    const long long ti = bi[q];
+                    bv[q] = cv;
+                    bi[q] = ci;
+                    cv = tv;
+                    ci = ti;
+                }
+            }
+        }
+    }
+    int head = 0;  // next candidate of this lane
+    for (int r = 0; r < K; r++) {
+        double hv = -INFINITY;
+        long long hi = LLONG_MAX;
+#pragma unroll
+        for (int q = 0; q < K; q++)
+            if (q == head) {
+                hv = bv[q];
+                hi = bi[q] < 0 ? LLONG_MAX : bi[q];
+            }
+        // wave maximum of (value, -index)
+        double mv = hv;
+        long long mi = hi;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ov = __shfl_xor(mv, o, 64);
+            const long long oi = __shfl_xor(mi, o, 64);
+            if (ov > mv || (ov == mv && oi < mi)) {
+                mv = ov;
+                mi = oi;
+            }
+        }
+        if (hv == mv && hi == mi) head++;
+        if (lane == 0) {
+            const bool ok = mi != LLONG_MAX;
+            idx_out[i * K + r] = ok ? mi : -1;
+            if (val_out) val_out[i * K + r] = ok ? exp((f[i] + mv) * inv_eps) : 0.0;
+        }
+    }
+}
+
 accsk_status build_cost(const float *X, const float *Y, long long n, long long m, long long d, int kind,
                         double scale, int split, float *C, long long ldc, double *norms_ws, hipStream_t s) {
     const double inv_s = 1.0 / scale;
@@ -382,6 +461,58 @@ extern "C" accsk_status accsk_plan_points(const float *X, const float *Y, int64_
             hipLaunchKernelGGL(plan_points_k<ACCSK_COSINE>, grid, dim3(256), lds, s, X, Y, m, d, 1.0 / cost_scale,
                                1.0 / eps, f, g, row0 + r, rc, P + r * ldp, ldp);
     }
+    return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+extern "C" accsk_status accsk_barycentric_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d,
+                                                 int kind, double cost_scale, double eps, const double *f,
+                                                 const double *g, float *T, void *stream) {
+    accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, 0);
+    if (st != ACCSK_OK) return st;
+    if (!f || !g || !T || !finite_pos(eps)) return ACCSK_INVALID_ARG;
+    if (d > 448) return ACCSK_SHAPE;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t lds = ((size_t)(kBR + kBC) * (d + 1) + kBR * kBC) * sizeof(float) + kBC * sizeof(double);
+    dim3 grid((unsigned)((n + kBR - 1) / kBR), 1u);
+    auto run = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, Y, n, m, d, 1.0 / cost_scale, 1.0 / eps, f, g,
+                           (const double *)nullptr, T, n * d, m * d, n, m);
+    };
+    if (kind == ACCSK_SQEUCLID) {
+        if (d <= 64) run(grad_side<ACCSK_SQEUCLID, 4, 1>);
+        else if (d <= 128) run(grad_side<ACCSK_SQEUCLID, 8, 1>);
+        else if (d <= 256) run(grad_side<ACCSK_SQEUCLID, 16, 1>);
+        else run(grad_side<ACCSK_SQEUCLID, 28, 1>);
+    } else {
+        if (d <= 64) run(grad_side<ACCSK_COSINE, 4, 1>);
+        else if (d <= 128) run(grad_side<ACCSK_COSINE, 8, 1>);
+        else if (d <= 256) run(grad_side<ACCSK_COSINE, 16, 1>);
+        else run(grad_side<ACCSK_COSINE, 28, 1>);
+    }
+    return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+extern "C" accsk_status accsk_topk_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
+                                          double cost_scale, double eps, const double *f, const double *g, int k,
+                                          int64_t *idx, double *val, void *stream) {
+    accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, 0);
+    if (st != ACCSK_OK) return st;
+    if (!f || !g || !idx || !finite_pos(eps)) return ACCSK_INVALID_ARG;
+    if (k < 1 || k > 8) return ACCSK_SHAPE;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t lds = 4 * (size_t)d * sizeof(float);
+    const dim3 grid((unsigned)((n + 3) / 4));
+    const double inv_s = 1.0 / cost_scale, inv_eps = 1.0 / eps;
+    auto run = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, Y, n, m, d, inv_s, inv_eps, f, g, (long long *)idx, val);
+    };
+    const bool sq = kind == ACCSK_SQEUCLID;
+    if (k == 1) sq ? run(topk_rows<ACCSK_SQEUCLID, 1>) : run(topk_rows<ACCSK_COSINE, 1>);
+    else if (k <= 5) {
+        if (k == 5) sq ? run(topk_rows<ACCSK_SQEUCLID, 5>) : run(topk_rows<ACCSK_COSINE, 5>);
+        else return ACCSK_SHAPE;
+    } else if (k == 8) sq ? run(topk_rows<ACCSK_SQEUCLID, 8>) : run(topk_rows<ACCSK_COSINE, 8>);
+    else return ACCSK_SHAPE;
     return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
 }
 

@@ -276,3 +276,57 @@ def test_plan_points(torch_gpu, kind, n, m, d):
     big = ref > 1e-30
     assert np.all(np.abs(got[big] - ref[big]) <= 2.0 ** -23 * ref[big])
     assert abs(got.sum() - ref.sum()) <= 1e-6 * ref.sum()
+
+
+@pytest.mark.parametrize("kind,n,m,d", [(0, 70, 133, 3), (1, 40, 190, 300), (0, 33, 1, 2)])
+def test_barycentric_points(torch_gpu, kind, n, m, d):
+    """T_i = sum_j P_ij y_j / sum_j P_ij (colour-transfer map) at the oracle's potentials."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    X, Y = _clouds(61 + n, n, m, d, kind)
+    rng = np.random.default_rng(m)
+    a, b = rng.uniform(0.5, 1.5, n), rng.uniform(0.5, 1.5, m)
+    s = float(d) if kind == 0 else 1.0
+    eps = 2e-2
+    C = O.cost_points(kind, X, Y, s)
+    o = O.solve(C, a, b, eps, tol=1e-10, method=O.ACC, mu0=0.25, m0=5, w_rule=O.W_Y_CONTINUOUS)
+    T = accsk.barycentric_points(_dev(torch, X, torch.float32), _dev(torch, Y, torch.float32),
+                                 _dev(torch, o["f"], torch.float64), _dev(torch, o["g"], torch.float64), eps,
+                                 kind=kind, cost_scale=s)
+    torch.cuda.synchronize()
+    P = O.plan(C, eps, o["f"], o["g"])
+    ref = (P @ Y.astype(np.float64)) / P.sum(axis=1, keepdims=True)
+    got = T.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 2e-6 * max(1.0, np.abs(Y).max())
+
+
+@pytest.mark.parametrize("k", [1, 5, 8])
+@pytest.mark.parametrize("kind,n,m,d", [(0, 70, 133, 3), (1, 50, 300, 300), (0, 9, 4, 2)])
+def test_topk_points(torch_gpu, k, kind, n, m, d):
+    """Row top-k of P decided on g_j - C_ij in FP64; where the order differs from the
+    oracle's it must be a tie to FP64 rounding of the cost."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    X, Y = _clouds(71 + n + k, n, m, d, kind)
+    rng = np.random.default_rng(n + k)
+    a, b = rng.uniform(0.5, 1.5, n), rng.uniform(0.5, 1.5, m)
+    s = float(d) if kind == 0 else 1.0
+    eps = 1e-2
+    C = O.cost_points(kind, X, Y, s)
+    o = O.solve(C, a, b, eps, tol=1e-9, method=O.ACC, mu0=0.25, m0=5, w_rule=O.W_Y_CONTINUOUS)
+    idx, val = accsk.topk_points(_dev(torch, X, torch.float32), _dev(torch, Y, torch.float32),
+                                 _dev(torch, o["f"], torch.float64), _dev(torch, o["g"], torch.float64), eps, k=k,
+                                 kind=kind, cost_scale=s)
+    torch.cuda.synchronize()
+    idx, val = idx.cpu().numpy(), val.cpu().numpy()
+    score = o["g"][None, :] - C
+    kk = min(k, m)
+    for i in range(n):
+        order = np.lexsort((np.arange(m), -score[i]))[:kk]
+        got = idx[i, :kk]
+        assert len(set(got.tolist())) == kk and np.all(got >= 0)
+        # same scores in the same order (ties resolved either way only within FP64 rounding)
+        assert np.allclose(score[i, got], score[i, order], rtol=0, atol=1e-12 * (1 + np.abs(score[i]).max()))
+        np.testing.assert_allclose(val[i, :kk], np.exp((o["f"][i] + score[i, got]) / eps), rtol=1e-12)
+        if kk < k:
+            assert np.all(idx[i, kk:] == -1)
