@@ -80,11 +80,18 @@ typedef struct {
 #define ACCSK_FLAG_NO_SERPENTINE 2 /* traverse C in the same row order every step */
 #define ACCSK_FLAG_ON_THE_FLY 4    /* point-cloud solves: form C_ij on the fly in every step (never stored);
                                       implied when m > 8192; needs d <= 16 */
+#define ACCSK_FLAG_RESTART 8       /* Acc-Sinkhorn: when the reduced dual objective f(x) = 1 - <u,a> - <x,b>
+                                      rises (stability monitor), reset the extrapolation w <- alpha x.  A
+                                      safeguard of this library (function-value restart), not the paper's
+                                      algorithm; off by default */
 
 typedef struct {
     int64_t iters;          /* It: accepted iterates after x_0 (Sinkhorn: v-updates) */
     int64_t sinkhorn_steps; /* Sinkhorn steps evaluated (= iters + 1) */
     int64_t fallback_steps; /* steps that needed the exact column-max pass */
+    int64_t fval_increases; /* stability monitor: steps at which f(x) = 1 - <u,a> - <x,b> (Lemma coercivity)
+                               rose by more than 1e-8 + 1e-12 |f| over the previous iterate */
+    int64_t restarts;       /* extrapolation resets done under ACCSK_FLAG_RESTART */
     double marginal_err;    /* eq:l1tol at the returned iterate, column part (row part is 0 by the exact row solve) */
     double eot_value;       /* dual value <f,a> + <g,b> - eps*sum P (equals the EOT optimum at
                                convergence), FP64-evaluated unless ACCSK_FLAG_NO_COST */

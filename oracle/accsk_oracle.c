@@ -151,12 +151,31 @@ enum { ORACLE_W_LITERAL = 0, ORACLE_W_Y_CONTINUOUS = 1 };
  * trace_x (length (max_iter+1)*m, may be NULL): the iterate x per It.
  * Returns 1 if converged (err < tol), 0 otherwise.
  */
-int oracle_solve(int method, const double *C, int64_t n, int64_t m, double eps,
-                 const double *a, const double *b, double tol, int64_t max_iter,
-                 double mu0, int64_t m0, int w_rule,
-                 double *f, double *g, int64_t *iters, int64_t *steps, double *err_out,
-                 double *trace_err, double *trace_fval, double *trace_x)
+/*
+ * Stability monitor (not part of the paper's algorithm; a safeguard of this
+ * build, off unless `restart` is set).  The reduced dual objective
+ * f(x) = 1 - <u(x),a> - <x,b> (Lemma coercivity, App. A) decreases along plain
+ * Sinkhorn (Lemma sinkhorn-descent); Acc-Sinkhorn need not decrease it at every
+ * step.  After each accepted Acc iterate, f(x_k) > f(x_{k-1}) + delta counts as
+ * an increase, delta = 1e-8 + 1e-12 |f(x_k)| (above the rounding of f computed
+ * from FP32 exponentials).  With `restart`, an increase also resets the
+ * extrapolation variable to the current iterate, w <- alpha x (y = x), the
+ * function-value restart of accelerated methods.  Counts go to *n_increase and
+ * *n_restart (either may be NULL).
+ */
+static int stability_increase(double fval, double fprev)
 {
+    return fval > fprev + (1e-8 + 1e-12 * fabs(fval));
+}
+
+int oracle_solve_ex(int method, const double *C, int64_t n, int64_t m, double eps,
+                    const double *a, const double *b, double tol, int64_t max_iter,
+                    double mu0, int64_t m0, int w_rule, int restart,
+                    double *f, double *g, int64_t *iters, int64_t *steps, double *err_out,
+                    double *trace_err, double *trace_fval, double *trace_x,
+                    int64_t *n_increase, int64_t *n_restart)
+{
+    int64_t ninc = 0, nrst = 0;
     double *x = (double *)calloc((size_t)m, sizeof(double));
     double *w = (double *)calloc((size_t)m, sizeof(double));
     double *S = (double *)malloc(sizeof(double) * (size_t)m);
@@ -168,6 +187,7 @@ int oracle_solve(int method, const double *C, int64_t n, int64_t m, double eps,
 
     oracle_sstep(C, n, m, eps, a, b, x, u, ell, S, &err, &fval);
     nsteps = 1;
+    double fprev = fval;
     if (trace_err) trace_err[0] = err;
     if (trace_fval) trace_fval[0] = fval;
     if (trace_x) memcpy(trace_x, x, sizeof(double) * (size_t)m);
@@ -178,6 +198,8 @@ int oracle_solve(int method, const double *C, int64_t n, int64_t m, double eps,
             it++;
             oracle_sstep(C, n, m, eps, a, b, x, u, ell, S, &err, &fval);
             nsteps++;
+            if (stability_increase(fval, fprev)) ninc++;
+            fprev = fval;
             if (trace_err) trace_err[it] = err;
             if (trace_fval) trace_fval[it] = fval;
             if (trace_x) memcpy(trace_x + it * m, x, sizeof(double) * (size_t)m);
@@ -194,6 +216,14 @@ int oracle_solve(int method, const double *C, int64_t n, int64_t m, double eps,
                 nsteps++;
                 for (int64_t j = 0; j < m; j++)
                     w[j] = (w[j] + (alpha * alpha - 2.0) * x[j] + 2.0 * S[j]) / (1.0 + alpha);
+                if (stability_increase(fval, fprev)) {
+                    ninc++;
+                    if (restart) {
+                        for (int64_t j = 0; j < m; j++) w[j] = alpha * x[j];
+                        nrst++;
+                    }
+                }
+                fprev = fval;
                 it++;
                 if (trace_err) trace_err[it] = err;
                 if (trace_fval) trace_fval[it] = fval;
@@ -217,8 +247,20 @@ int oracle_solve(int method, const double *C, int64_t n, int64_t m, double eps,
     *iters = it;
     *steps = nsteps;
     *err_out = err;
+    if (n_increase) *n_increase = ninc;
+    if (n_restart) *n_restart = nrst;
     free(x); free(w); free(S); free(ell); free(u);
     return converged;
+}
+
+int oracle_solve(int method, const double *C, int64_t n, int64_t m, double eps,
+                 const double *a, const double *b, double tol, int64_t max_iter,
+                 double mu0, int64_t m0, int w_rule,
+                 double *f, double *g, int64_t *iters, int64_t *steps, double *err_out,
+                 double *trace_err, double *trace_fval, double *trace_x)
+{
+    return oracle_solve_ex(method, C, n, m, eps, a, b, tol, max_iter, mu0, m0, w_rule, 0, f, g, iters, steps,
+                           err_out, trace_err, trace_fval, trace_x, NULL, NULL);
 }
 
 /*

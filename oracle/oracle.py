@@ -69,6 +69,11 @@ def _load():
                                      _d, _d, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _d,
                                      _d, _d, _d]
         lib.oracle_solve.restype = ctypes.c_int
+        lib.oracle_solve_ex.argtypes = [ctypes.c_int, _d, _i64, _i64, ctypes.c_double, _d, _d,
+                                        ctypes.c_double, _i64, ctypes.c_double, _i64, ctypes.c_int, ctypes.c_int,
+                                        _d, _d, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _d,
+                                        _d, _d, _d, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+        lib.oracle_solve_ex.restype = ctypes.c_int
         lib.oracle_eval.argtypes = [_d, _i64, _i64, ctypes.c_double, _d, _d, _d, _d, _d, _d, _d, _d, _d]
         lib.oracle_eval.restype = None
         lib.oracle_plan.argtypes = [_d, _i64, _i64, ctypes.c_double, _d, _d, _i64, _i64, _d]
@@ -126,7 +131,7 @@ def sstep(C, eps, a, b, x):
 
 
 def solve(C, a, b, eps, tol=1e-6, max_iter=100000, method=ACC, mu0=0.5, m0=1,
-          w_rule=W_LITERAL, trace=False, trace_x=False, normalize_marginals=True):
+          w_rule=W_LITERAL, trace=False, trace_x=False, normalize_marginals=True, restart=False):
     """Solve EOT(C, a, b, eps) with plain Sinkhorn or Acc-Sinkhorn (FP64).
 
     Returns a dict with f, g (potentials in cost units, g centred), iters, steps,
@@ -147,13 +152,14 @@ def solve(C, a, b, eps, tol=1e-6, max_iter=100000, method=ACC, mu0=0.5, m0=1,
     tf = np.empty(max_iter + 1) if trace else None
     tx = np.empty((max_iter + 1, m)) if trace_x else None
     null = ctypes.cast(None, _d)
-    conv = _load().oracle_solve(int(method), _p(C), n, m, float(eps), _p(a), _p(b), float(tol),
-                                int(max_iter), float(mu0), int(m0), int(w_rule), _p(f), _p(g),
-                                ctypes.byref(it), ctypes.byref(st), ctypes.byref(err),
-                                _p(te) if trace else null, _p(tf) if trace else null,
-                                _p(tx) if trace_x else null)
+    ninc, nrst = _i64(), _i64()
+    conv = _load().oracle_solve_ex(int(method), _p(C), n, m, float(eps), _p(a), _p(b), float(tol),
+                                   int(max_iter), float(mu0), int(m0), int(w_rule), int(bool(restart)), _p(f),
+                                   _p(g), ctypes.byref(it), ctypes.byref(st), ctypes.byref(err),
+                                   _p(te) if trace else null, _p(tf) if trace else null,
+                                   _p(tx) if trace_x else null, ctypes.byref(ninc), ctypes.byref(nrst))
     out = dict(f=f, g=g, iters=it.value, steps=st.value, err=err.value, converged=bool(conv),
-               a=a, b=b)
+               a=a, b=b, fval_increases=ninc.value, restarts=nrst.value)
     if trace:
         out["trace_err"] = te[: it.value + 1].copy()
         out["trace_fval"] = tf[: it.value + 1].copy()

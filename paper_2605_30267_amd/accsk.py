@@ -22,6 +22,7 @@ SQEUCLID, COSINE = 0, 1
 FLAG_NO_COST = 1
 FLAG_NO_SERPENTINE = 2
 FLAG_ON_THE_FLY = 4
+FLAG_RESTART = 8
 
 
 class AccskError(RuntimeError):
@@ -38,7 +39,8 @@ class Params(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("sinkhorn_steps", ctypes.c_int64),
-                ("fallback_steps", ctypes.c_int64), ("marginal_err", ctypes.c_double),
+                ("fallback_steps", ctypes.c_int64), ("fval_increases", ctypes.c_int64),
+                ("restarts", ctypes.c_int64), ("marginal_err", ctypes.c_double),
                 ("eot_value", ctypes.c_double), ("transport_cost", ctypes.c_double),
                 ("dual_fval", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("converged", ctypes.c_int32),

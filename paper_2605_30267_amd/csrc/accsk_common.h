@@ -168,11 +168,21 @@ __device__ __forceinline__ double xload(const double *p) {
     return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Stability monitor: the reduced dual objective f(x) = 1 - <u,a> - <x,b>
+// (Lemma coercivity, App. A) falls along plain Sinkhorn (Lemma
+// sinkhorn-descent) but not necessarily along Acc-Sinkhorn.  A rise above the
+// rounding of f computed from FP32 exponentials counts as an increase.
+__device__ __forceinline__ bool fval_rose(double fval, double fprev) {
+    return fval > fprev + (1e-8 + 1e-12 * fabs(fval));
+}
+
 // Device-side result record copied back to the host accsk_result.
 struct DevResult {
     long long iters;
     long long steps;
     long long fallback;
+    long long incr;      // steps at which the reduced dual objective rose (stability monitor)
+    long long restarts;  // extrapolation resets (ACCSK_FLAG_RESTART)
     double err;
     double eot;
     double fval;

@@ -38,8 +38,8 @@ constexpr int kNS = 8;  // block scalar slots: 0 <u,a>, 1 sum S^, 2 err, 3 mass,
 
 // Scalars carried from one Sinkhorn step to the next (identical in every thread).
 struct LoopState {
-    double mu, alpha, err, mass, xb2;
-    long long mstage, kin, it, steps, fallbacks;
+    double mu, alpha, err, mass, xb2, fprev;
+    long long mstage, kin, it, steps, fallbacks, incr, restarts;
     int first;
 };
 
@@ -63,7 +63,7 @@ struct DenseArgs {
     double *f_out, *g_out;
     double eps, kappa, tol, tol_stop, mu0;
     long long max_iter, m0;
-    int method, w_rule, serpentine;
+    int method, w_rule, serpentine, restart;
 };
 
 // ---------------------------------------------------------------------------
@@ -251,9 +251,9 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
     if (tid == 0) {
         ls.mu = A.mu0;
         ls.alpha = dsqrt(2.0 * A.mu0);
-        ls.err = ls.mass = ls.xb2 = 0.0;
+        ls.err = ls.mass = ls.xb2 = ls.fprev = 0.0;
         ls.mstage = A.m0;
-        ls.kin = ls.it = ls.steps = ls.fallbacks = 0;
+        ls.kin = ls.it = ls.steps = ls.fallbacks = ls.incr = ls.restarts = 0;
         ls.first = 1;
     }
     __syncthreads();
@@ -536,6 +536,12 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                 __syncthreads();
             }
             if (wid == 0) {
+                // <u,a> over this block's rows (log2 units) for the reduced dual objective:
+                // u_i = log2 a_i - rowL_i, rowL_i = M_i + log2 S_i with an FP32 log2 of a row
+                // sum near 1 (the shift is the previous step's log-sum-exp)
+                double aU = 0.0;  // a_i = rowA_i max a: on-chip, no load after the barrier
+                for (int r = lane; r < nr; r += 64) aU += rowA[r] * (la2s[r] - rowL[r]);
+                aU = wave_sum(aU) * A.gscal[1];
                 aS = wave_sum(aS);
                 aE = wave_sum(aE);
                 aC = wave_sum(aC);
@@ -543,6 +549,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                 aFB = wave_sum(aFB);
                 if (lane == 0) {
                     double *p = bs + (size_t)bid * kNS;
+                    xstore(&p[0], aU);
                     xstore(&p[1], aS);
                     xstore(&p[2], aE);
                     xstore(&p[3], aC);
@@ -571,12 +578,14 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
         st.mass = tot[3];
         st.xb2 = tot[4];
         st.steps++;
+        const double fval = 1.0 - (tot[0] + tot[4]) * kLn2;  // f(x) = 1 - <u,a> - <x,b> at this step's x
         bool stop = false;
         if (!isfinite(st.err)) {
             status = (st.steps == 1) ? ACCSK_NONFINITE : ACCSK_DIVERGED;
             stop = true;
         } else if (A.method == ACCSK_SINKHORN) {
             // plain Sinkhorn, eq:normalized-sinkhorn: x <- S(x)
+            if (st.steps > 1 && fval_rose(fval, st.fprev)) st.incr++;
             if (st.err < A.tol_stop || st.it >= A.max_iter) {
                 stop = true;
             } else {
@@ -611,6 +620,19 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                     }
                 st.it++;
                 st.kin++;
+                if (fval_rose(fval, st.fprev)) {
+                    st.incr++;
+                    if (A.restart) {  // safeguard: reset the extrapolation, w <- alpha x
+#pragma unroll
+                        for (int k = 0; k < NG; k++)
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                const long long col = 4ll * (ctid + k * TPB) + e;
+                                if (col < m) wl_lds[col] = st.alpha * xl_lds[col];
+                            }
+                        st.restarts++;
+                    }
+                }
             }
             if (st.err < A.tol_stop || st.it >= A.max_iter) {
                 stop = true;
@@ -644,6 +666,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                     }
             }
         }
+        st.fprev = fval;
         __syncthreads();  // every thread has read ls
         if (tid == 0) ls = st;
         __syncthreads();
@@ -681,6 +704,8 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
         r.iters = fin.it;
         r.steps = fin.steps;
         r.fallback = fin.fallbacks;
+        r.incr = fin.incr;
+        r.restarts = fin.restarts;
         r.err = fin.err;
         r.eot = eot;
         r.fval = fval;
@@ -938,6 +963,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         A.method = p->method;
         A.w_rule = p->w_rule;
         A.serpentine = (p->flags & ACCSK_FLAG_NO_SERPENTINE) ? 0 : 1;
+        A.restart = (p->flags & ACCSK_FLAG_RESTART) ? 1 : 0;
         char *q0 = base + o_prob[q];
         A.an = (double *)q0;
         A.la2 = A.an + n;
@@ -1004,6 +1030,8 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         o.iters = r.iters;
         o.sinkhorn_steps = r.steps;
         o.fallback_steps = r.fallback;
+        o.fval_increases = r.incr;
+        o.restarts = r.restarts;
         o.marginal_err = r.err;
         o.eot_value = r.eot;
         o.transport_cost = r.cost;

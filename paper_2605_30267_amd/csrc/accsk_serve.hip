@@ -409,6 +409,8 @@ struct accsk_server {
             r.res.iters = d.iters;
             r.res.sinkhorn_steps = d.steps;
             r.res.fallback_steps = d.fallback;
+            r.res.fval_increases = d.incr;
+            r.res.restarts = d.restarts;
             r.res.marginal_err = d.err;
             r.res.eot_value = d.eot;
             r.res.transport_cost = d.cost;

@@ -92,6 +92,8 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
         o.iters = r.iters;
         o.sinkhorn_steps = r.steps;
         o.fallback_steps = r.fallback;
+        o.fval_increases = r.incr;
+        o.restarts = r.restarts;
         o.marginal_err = r.err;
         o.eot_value = r.eot;
         o.transport_cost = r.cost;

@@ -39,7 +39,7 @@ namespace {
 
 constexpr int kTT = 512;          // threads per block
 constexpr int kTW = kTT / 64;     // waves per block
-constexpr int kTNS = 8;           // block scalar slots: 1 sum S^, 2 err, 3 mass, 4 <x,b>, 5 fallback
+constexpr int kTNS = 8;           // block scalar slots: 0 <u,a>, 1 sum S^, 2 err, 3 mass, 4 <x,b>, 5 fallback
 constexpr int kTRB = 256;         // rows staged per row group of the column sweep
 
 template <int D>
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                             double t;
                             if (D == 0) t = fma(-(double)A.C[(r0 + rb0 + r) * A.ldc + jc[p]], kap2, xh[p]) + rh;
                             else t = arg_pts(xt, rh, y[p], xh[p]);
-                            if (sweep == 0) cmx[p] = fmax(cmx[p], t);
+                            if (sweep == 0) cmx[p] = (t > cmx[p] || t != t) ? t : cmx[p];  // NaN propagates
                             else sp[p] += __builtin_amdgcn_exp2f((float)(t - cmx[p]));
                         }
                         if ((r & 7) == 7) {
@@ -437,7 +437,8 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
     };
 
     double mu = A.mu0, alpha = dsqrt(2.0 * A.mu0);
-    long long mstage = A.m0, kin = 0, it = 0, steps = 0, fallbacks = 0;
+    long long mstage = A.m0, kin = 0, it = 0, steps = 0, fallbacks = 0, incr = 0, restarts = 0;
+    double fprev = 0.0;
     bool first = true;
     unsigned long long gen = 0;
     int status = ACCSK_OK;
@@ -479,7 +480,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                     if (j < j1)
                         for (int b = grp; b < G; b += NGRP) {
                             const double mb = A.partmax[(size_t)b * m + j];
-                            if (mb > -INFINITY) acc += A.part[(size_t)b * m + j] * dexp2(mb - pm);
+                            if (mb != -INFINITY) acc += A.part[(size_t)b * m + j] * dexp2(mb - pm);  // NaN kept
                         }
                 }
                 sred[tid] = acc;
@@ -491,7 +492,8 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                     double lc2, c;  // log2 c_j and c_j, the column sum of P at (u(x), x)
                     if (pass == 0) {
                         lc2 = A.colL[j] + dlog2(sc);
-                        if (!(sc >= 0x1p-64 && sc <= 0x1p64)) aFB += 1.0;
+                        // out of range -> exact sweep; NaN (a non-finite input) goes on to the error test
+                        if (sc < 0x1p-64 || sc > 0x1p64) aFB += 1.0;
                     } else {
                         lc2 = pm + dlog2(sc);
                     }
@@ -508,6 +510,10 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                 __syncthreads();
             }
             if (wid == 0) {
+                // <u,a> over this block's rows (log2 units) for the reduced dual objective
+                double aU = 0.0;
+                for (long long i = r0 + lane; i < r1; i += 64) aU += A.an[i] * A.rowU[i];
+                aU = wave_sum(aU);
                 aS = wave_sum(aS);
                 aE = wave_sum(aE);
                 aC = wave_sum(aC);
@@ -515,6 +521,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                 aFB = wave_sum(aFB);
                 if (lane == 0) {
                     double *pp = bs + (size_t)bid * kTNS;
+                    xstore(&pp[0], aU);
                     xstore(&pp[1], aS);
                     xstore(&pp[2], aE);
                     xstore(&pp[3], aC);
@@ -545,8 +552,12 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
             break;
         }
         // update of this block's slice of x and w (same scalars in every block)
+        const double fval = 1.0 - (tot[0] + tot[4]) * kLn2;  // f(x) = 1 - <u,a> - <x,b>
+        const double fp = fprev;
+        fprev = fval;
         bool stop = false;
         if (A.method == ACCSK_SINKHORN) {
+            if (steps > 1 && fval_rose(fval, fp)) incr++;
             if (err < A.tol_stop || it >= A.max_iter) stop = true;
             else {
                 for (long long j = j0 + tid; j < j1; j += kTT) A.xg[j] = A.shat[j] - mean;
@@ -559,6 +570,13 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                     A.wg[j] = (A.wg[j] + c2 * A.xg[j] + 2.0 * (A.shat[j] - mean)) * inv;
                 it++;
                 kin++;
+                if (fval_rose(fval, fp)) {
+                    incr++;
+                    if (A.flags & ACCSK_FLAG_RESTART) {  // safeguard: reset the extrapolation, w <- alpha x
+                        for (long long j = j0 + tid; j < j1; j += kTT) A.wg[j] = alpha * A.xg[j];
+                        restarts++;
+                    }
+                }
             }
             if (err < A.tol_stop || it >= A.max_iter) stop = true;
             else {
@@ -634,6 +652,8 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         r.iters = it;
         r.steps = steps;
         r.fallback = fallbacks;
+        r.incr = incr;
+        r.restarts = restarts;
         r.err = err;
         r.eot = eot;
         r.fval = fval;
@@ -727,6 +747,8 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     res->iters = hr.iters;
     res->sinkhorn_steps = hr.steps;
     res->fallback_steps = hr.fallback;
+    res->fval_increases = hr.incr;
+    res->restarts = hr.restarts;
     res->marginal_err = hr.err;
     res->eot_value = hr.eot;
     res->transport_cost = hr.cost;

@@ -178,7 +178,8 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
     __syncthreads();
 
     double mu = ctl.mu0, alpha = sqrt(2.0 * ctl.mu0);
-    long long mstage = ctl.m0, kin = 0, it = 0, steps = 0, fallbacks = 0;
+    long long mstage = ctl.m0, kin = 0, it = 0, steps = 0, fallbacks = 0, incr = 0, restarts = 0;
+    double fprev = 0.0;
     bool first = true;
     int status = ACCSK_OK;
     double err = 0.0, mass = 0.0, xb2 = 0.0;
@@ -334,6 +335,10 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
         err = wg_sum<NW>(aE, red);
         mass = wg_sum<NW>(aC, red);
         xb2 = wg_sum<NW>(aXB, red);
+        // <u,a> (log2 units) for the reduced dual objective f(x) = 1 - <u,a> - <x,b>
+        double aU = 0.0;
+        for (int i = tid; i < n; i += TPB) aU += afac[i] * maxa * (la2[i] - (rowM[i] + log2(rowS[i])));
+        const double fval = 1.0 - (wg_sum<NW>(aU, red) + xb2) * kLn2;
         const double mean = sumS / (double)m;
         steps++;
         if (!isfinite(err)) {
@@ -341,7 +346,10 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
             break;
         }
         // ---------------- update (Sinkhorn or Algorithm A2MD with homotopy) ----------------
+        const double fp = fprev;
+        fprev = fval;
         if (ctl.method == ACCSK_SINKHORN) {
+            if (steps > 1 && fval_rose(fval, fp)) incr++;
             if (err < ctl.tol_stop || it >= ctl.max_iter) break;
             for (int j = tid; j < m; j += TPB) xl[j] = wpart[j] - mean;
             it++;
@@ -351,6 +359,13 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
                 for (int j = tid; j < m; j += TPB) wl[j] = (wl[j] + c2 * xl[j] + 2.0 * (wpart[j] - mean)) * inv;
                 it++;
                 kin++;
+                if (fval_rose(fval, fp)) {
+                    incr++;
+                    if (ctl.flags & ACCSK_FLAG_RESTART) {  // safeguard: reset the extrapolation, w <- alpha x
+                        for (int j = tid; j < m; j += TPB) wl[j] = alpha * xl[j];
+                        restarts++;
+                    }
+                }
             }
             if (err < ctl.tol_stop || it >= ctl.max_iter) break;
             if (!first && kin == mstage) {
@@ -401,6 +416,8 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
         r.iters = it;
         r.steps = steps;
         r.fallback = fallbacks;
+        r.incr = incr;
+        r.restarts = restarts;
         r.err = err;
         const double ua_ln = ua * kLn2, xb_ln = xb2 * kLn2;
         r.fval = 1.0 - ua_ln - xb_ln;

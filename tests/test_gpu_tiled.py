@@ -122,3 +122,66 @@ def test_color_transfer_full_size_sampled(torch_gpu):
     assert tot <= 1e-6
     # the dual value at the returned potentials is the EOT value: <f, a> + <g, b> - eps * mass, mass ~ 1
     assert abs(r["eot_value"] - (f @ an + g @ bn - p["eps"])) <= 2e-6 * p["eps"]
+
+
+def test_tiled_errors_and_limits(torch_gpu):
+    """Invalid and non-finite inputs on both tiled paths, and the iteration cap."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    p = W.random_dense(seed=62, n=40, m=9001, eps=1e-2)
+    Cd = _dev(torch, p["C32"], torch.float32)
+    a, b = _dev(torch, p["a"], torch.float64), _dev(torch, p["b"], torch.float64)
+    bad = a.clone()
+    bad[3] = 0.0
+    assert accsk.solve_dense(Cd, bad, b, 1e-2, raise_on_error=False)[2]["status"] == accsk.INVALID_ARG
+    bad[3] = float("nan")
+    assert accsk.solve_dense(Cd, bad, b, 1e-2, raise_on_error=False)[2]["status"] == accsk.NONFINITE
+    Cn = Cd.clone()
+    Cn[5, 7] = float("nan")
+    assert accsk.solve_dense(Cn, a, b, 1e-2, raise_on_error=False)[2]["status"] == accsk.NONFINITE
+    r = accsk.solve_dense(Cd, a, b, 1e-2, tol=1e-300, max_iter=3, raise_on_error=False)[2]
+    assert r["status"] == accsk.NOT_CONVERGED and r["iters"] == 3 and r["sinkhorn_steps"] == 4
+    # on the fly: a NaN point, a zero weight, the cap
+    X, Y = _points(5, 30, 50, 3, 0)
+    Xd, Yd = _dev(torch, X, torch.float32), _dev(torch, Y, torch.float32)
+    aa = _dev(torch, np.full(30, 1 / 30), torch.float64)
+    bb = _dev(torch, np.full(50, 1 / 50), torch.float64)
+    Xn = Xd.clone()
+    Xn[2, 1] = float("nan")
+    r = accsk.solve_points(Xn, Yd, aa, bb, 1e-2, on_the_fly=True, raise_on_error=False)[2][0]
+    assert r["status"] == accsk.NONFINITE
+    a0 = aa.clone()
+    a0[0] = 0.0
+    r = accsk.solve_points(Xd, Yd, a0, bb, 1e-2, on_the_fly=True, raise_on_error=False)[2][0]
+    assert r["status"] == accsk.INVALID_ARG
+    r = accsk.solve_points(Xd, Yd, aa, bb, 1e-2, on_the_fly=True, tol=1e-300, max_iter=0, raise_on_error=False)[2][0]
+    assert r["status"] == accsk.NOT_CONVERGED and r["iters"] == 0 and r["sinkhorn_steps"] == 1
+    with pytest.raises(accsk.AccskError) as e:  # d = 17 > 16 on the fly
+        accsk.solve_points(_dev(torch, np.zeros((30, 17), np.float32), torch.float32),
+                           _dev(torch, np.zeros((50, 17), np.float32), torch.float32), aa, bb, 1e-2, on_the_fly=True)
+    assert e.value.status == accsk.SHAPE
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_on_the_fly_small_eps_fallback(torch_gpu, method):
+    """eps = 1e-4 on unit-cube points: early steps have columns with almost no
+    mass (exact column sweep), later steps the carried shifts; parity at tol."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    X, Y = _points(8, 200, 300, 3, 0)
+    rng = np.random.default_rng(9)
+    a, b = rng.uniform(0.5, 1.5, 200), rng.uniform(0.5, 1.5, 300)
+    raw = O.cost_points(0, X, Y, 1.0)
+    s = float(raw.max())
+    eps = 1e-4
+    f, g, res = accsk.solve_points(_dev(torch, X, torch.float32), _dev(torch, Y, torch.float32),
+                                   _dev(torch, a, torch.float64), _dev(torch, b, torch.float64), eps, cost_scale=s,
+                                   on_the_fly=True, method=method, max_iter=400000)
+    torch.cuda.synchronize()
+    r = res[0]
+    C = raw / s
+    an, bn = a / a.sum(), b / b.sum()
+    ev = O.evaluate(C, eps, an, bn, f.cpu().numpy(), g.cpu().numpy())
+    print("eps 1e-4 method", method, "It", r["iters"], "fallback", r["fallback_steps"], "err", ev["err"], flush=True)
+    assert r["converged"] == 1 and ev["err"] <= 1e-6 * 1.0001
+    assert abs(r["eot_value"] - ev["dual"]) <= 2e-7 * eps + 1e-12 * abs(ev["dual"])
