@@ -461,3 +461,28 @@ def test_planted_mistake_is_caught():
     st = O.sstep(C, eps, a, b, x)
     P = np.exp(st["u"][:, None] + x[None, :] - C / eps)
     assert np.abs(P.sum(1) - a).sum() < 1e-12
+
+
+def test_stability_monitor_pins():
+    """The monitor's count on plain Sinkhorn is 0 (Lemma sinkhorn-descent: f falls at
+    every step); on Acc-Sinkhorn it equals the rises of the traced f(x_k) above
+    1e-8 + 1e-12|f|; the restart safeguard reaches the same optimum as Sinkhorn."""
+    for seed in (1, 2):
+        C, a, b = _problem(seed, 60, 45)
+        p = dict(a=a, b=b)
+        for eps in (1e-2, 1e-3):
+            sk = O.solve(C, p["a"], p["b"], eps, tol=1e-12, method=O.SINKHORN, trace=True, max_iter=200000)
+            assert sk["fval_increases"] == 0
+            tf = sk["trace_fval"]
+            assert np.all(np.diff(tf) <= 1e-12 * np.abs(tf[1:]))  # the descent itself, in FP64
+            acc = O.solve(C, p["a"], p["b"], eps, tol=1e-9, method=O.ACC, mu0=0.25, m0=5, w_rule=O.W_LITERAL,
+                          trace=True, max_iter=50000)
+            tf = acc["trace_fval"]
+            rises = int(np.sum(tf[1:] > tf[:-1] + (1e-8 + 1e-12 * np.abs(tf[1:]))))
+            assert acc["fval_increases"] == rises
+            rst = O.solve(C, p["a"], p["b"], eps, tol=1e-12, method=O.ACC, mu0=0.25, m0=5, w_rule=O.W_LITERAL,
+                          restart=True, max_iter=50000)
+            assert rst["converged"] and rst["restarts"] == rst["fval_increases"]
+            # same optimum (gauge: g centred on both sides), as Sinkhorn's
+            assert np.allclose(rst["g"], sk["g"], rtol=0, atol=1e-8 * eps * 1e3)
+            assert np.allclose(rst["f"], sk["f"], rtol=0, atol=1e-8 * eps * 1e3)
