@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--serving", type=int, default=1, help="also run the serving stream (1/0)")
     ap.add_argument("--diff", type=int, default=1, help="also time the differentiable batched loss (1/0)")
     ap.add_argument("--small-batch", type=int, default=1, help="also time a batch of 1024 small problems (1/0)")
+    ap.add_argument("--paper", type=int, default=1,
+                    help="also run the Sec. 5 experiment shapes: synthetic, colour and word tables (1/0)")
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--serve-split", type=int, default=3, help="cost split of the served requests (0, 2, 3)")
     return ap.parse_args()
@@ -230,6 +232,101 @@ def small_batch_bench(args, dev):
     return out
 
 
+# Iteration counts of the paper's Sec. 5 tables, (Acc-Sinkhorn, Sinkhorn) per eps,
+# measured on its own photographs and word vectors: context beside the stand-ins.
+PAPER_COLOUR_IT = {1.0: (3, 1), 1e-1: (5, 4), 1e-2: (18, 37), 1e-3: (46, 359), 1e-4: (239, 3507)}
+PAPER_WORD_IT = {1.0: (4, 1), 1e-1: (6, 4), 1e-2: (234, 5085), 1e-3: (268, 8254), 1e-4: (667, 20320)}
+PAPER_WORD_TOP = {1.0: (76.7, 94.0), 1e-1: (78.0, 94.8), 1e-2: (82.8, 95.3), 1e-3: (81.9, 95.7), 1e-4: (82.8, 94.8)}
+
+
+def paper_bench(args, dev):
+    """The shapes of the Sec. 5 experiments on seeded stand-ins, both methods.
+
+    * synthetic: n = 100, m = 50 and n = m = 100, eps = 1e-8, entries U[0,1]; It and
+      solve time to tol 1e-3 .. 1e-6, plus the spread of It over mu0 x m0 at 1e-6;
+    * colour table: n = 1000 RGB points, uniform marginals, tol = 2/n, eps 1 .. 1e-4;
+    * word table: n = 500 unit vectors (d = 300) with a planted alignment, cosine
+      cost / max, tol = 0.02/n, eps 1 .. 1e-4, top-1 / top-5 accuracy of the plan.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2605_30267_amd import accsk
+    from paper_2605_30267_amd import workloads as W
+
+    def solve(C, a, b, eps, tol, method, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f, g, r = accsk.solve_dense(C, a, b, eps, tol=tol, method=method, max_iter=2000000, raise_on_error=False,
+                                    **kw)
+        torch.cuda.synchronize()
+        return f, g, dict(iters=r["iters"], converged=r["converged"], kernel_ms=round(r["kernel_ms"], 4),
+                          ms=round(1e3 * (time.perf_counter() - t0), 4))
+
+    def dev3(C, a, b):
+        return (torch.as_tensor(np.ascontiguousarray(C), dtype=torch.float32, device=dev),
+                torch.as_tensor(a, dtype=torch.float64, device=dev), torch.as_tensor(b, dtype=torch.float64, device=dev))
+
+    out = {"synthetic": {}, "colour_table": {}, "word_table": {}}
+    for n, m in ((100, 50), (100, 100)):
+        p = W.paper_synthetic(n=n, m=m, eps=1e-8)
+        C, a, b = dev3(p["C"].astype(np.float32), p["a"], p["b"])
+        solve(C, a, b, 1e-8, 1e-3, accsk.ACC)
+        rows = {}
+        for tol in (1e-3, 1e-4, 1e-5, 1e-6):
+            ra = solve(C, a, b, 1e-8, tol, accsk.ACC)[2]
+            rs = solve(C, a, b, 1e-8, tol, accsk.SINKHORN)[2]
+            rows["tol=%g" % tol] = dict(acc=ra, sinkhorn=rs, it_ratio=round(rs["iters"] / max(ra["iters"], 1), 2),
+                                        time_ratio=round(rs["kernel_ms"] / ra["kernel_ms"], 2))
+            log("paper synthetic %dx%d tol %g: Acc It %d (%.2f ms), Sinkhorn It %d (%.2f ms)"
+                % (n, m, tol, ra["iters"], ra["kernel_ms"], rs["iters"], rs["kernel_ms"]))
+        sweep = {}
+        for mu0 in (0.5, 0.25, 0.1):
+            for m0 in (2, 5, 10):
+                sweep["mu0=%g,m0=%d" % (mu0, m0)] = solve(C, a, b, 1e-8, 1e-6, accsk.ACC, mu0=mu0, m0=m0)[2]["iters"]
+        rows["acc_it_over_mu0_m0_at_1e-6"] = sweep
+        out["synthetic"]["%dx%d" % (n, m)] = rows
+
+    c = W.color_table(n=1000)
+    C, a, b = dev3(c["C32"], c["a"], c["b"])
+    for eps in (1.0, 1e-1, 1e-2, 1e-3, 1e-4):
+        ra = solve(C, a, b, eps, 2e-3, accsk.ACC)[2]
+        rs = solve(C, a, b, eps, 2e-3, accsk.SINKHORN)[2]
+        out["colour_table"]["eps=%g" % eps] = dict(acc=ra, sinkhorn=rs, paper_it=PAPER_COLOUR_IT[eps])
+        log("paper colour n=1000 eps %g: Acc It %d (%.2f ms), Sinkhorn It %d (%.2f ms)"
+            % (eps, ra["iters"], ra["kernel_ms"], rs["iters"], rs["kernel_ms"]))
+
+    w = W.word_table(n=500)
+    Xd = torch.as_tensor(w["X"], device=dev)
+    Yd = torch.as_tensor(w["Y"], device=dev)
+    ad = torch.as_tensor(w["a"], dtype=torch.float64, device=dev)
+    bd = torch.as_tensor(w["b"], dtype=torch.float64, device=dev)
+    s = accsk.cost_max_points(Xd, Yd, kind=accsk.COSINE)
+    truth = w["truth"]
+    for eps in (1.0, 1e-1, 1e-2, 1e-3, 1e-4):
+        row = {}
+        for name, method in (("acc", accsk.ACC), ("sinkhorn", accsk.SINKHORN)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f, g, res = accsk.solve_points(Xd, Yd, ad, bd, eps, kind=accsk.COSINE, cost_scale=s, tol=0.02 / 500,
+                                           method=method, max_iter=2000000)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            idx, _ = accsk.topk_points(Xd, Yd, f, g, eps, k=5, kind=accsk.COSINE, cost_scale=s)
+            idx = idx.cpu().numpy()
+            row[name] = dict(iters=res[0]["iters"], converged=res[0]["converged"],
+                             kernel_ms=round(res[0]["kernel_ms"], 4), ms=round(ms, 4),
+                             top1=round(100.0 * float(np.mean(idx[:, 0] == truth)), 1),
+                             top5=round(100.0 * float(np.mean([truth[i] in idx[i] for i in range(500)])), 1))
+        row["paper_it"] = PAPER_WORD_IT[eps]
+        row["paper_top1_top5"] = PAPER_WORD_TOP[eps]
+        out["word_table"]["eps=%g" % eps] = row
+        log("paper word n=500 eps %g: Acc It %d (%.2f ms) top1 %.1f top5 %.1f, Sinkhorn It %d (%.2f ms)"
+            % (eps, row["acc"]["iters"], row["acc"]["kernel_ms"], row["acc"]["top1"], row["acc"]["top5"],
+               row["sinkhorn"]["iters"], row["sinkhorn"]["kernel_ms"]))
+    return out
+
+
 def serving_bench(args, dev):
     """Word-alignment-shaped request stream through the serving loop.
 
@@ -384,6 +481,7 @@ def main():
     diff = diff_bench(args, dev) if args.diff else None
     small = small_batch_bench(args, dev) if args.small_batch else None
     serving = serving_bench(args, dev) if args.serving else None
+    paper = paper_bench(args, dev) if args.paper else None
 
     cpu = None
     if args.cpu_baseline:
@@ -438,6 +536,7 @@ def main():
         "differentiable_loss": diff,
         "small_batch": small,
         "serving": serving,
+        "paper_experiments": paper,
     }
     print(json.dumps(out), flush=True)
 

@@ -94,8 +94,10 @@ typedef struct {
     int64_t restarts;       /* extrapolation resets done under ACCSK_FLAG_RESTART */
     double marginal_err;    /* eq:l1tol at the returned iterate, column part (row part is 0 by the exact row solve) */
     double eot_value;       /* dual value <f,a> + <g,b> - eps*sum P (equals the EOT optimum at
-                               convergence), FP64-evaluated unless ACCSK_FLAG_NO_COST */
-    double transport_cost;  /* <C,P> at the returned potentials (NaN if skipped) */
+                               convergence), FP64-evaluated unless ACCSK_FLAG_NO_COST; problems that
+                               accsk_solve_batch gives one workgroup sum FP32 exponentials in FP64
+                               instead (sum P to ~1e-8 relative) */
+    double transport_cost;  /* <C,P> at the returned potentials (NaN if skipped), evaluated as eot_value */
     double dual_fval;       /* reduced dual objective f(x) = 1 - <u,a> - <x,b> at eps = 1 (Lemma coercivity) */
     double kernel_ms;       /* duration of the solve kernel (HIP events on `stream`); for a batch, the
                                launch that solved this problem (shared by the problems of that launch) */
@@ -117,9 +119,12 @@ const char *accsk_version(void);
  * Dense solve on an explicit FP32 cost (Sec. 2 dual, Sec. 4 algorithms).
  * C: device, n x m row-major, leading dimension ldc >= m.  a: device FP64[n],
  * b: device FP64[m].  f_out: device FP64[n], g_out: device FP64[m].
- * res: host.  Sizes: 1 <= n, 1 <= m.  For m <= 8192 each Sinkhorn step reads
- * C once (row and column sums fused); larger m uses the tiled solver (a row
- * sweep and a column sweep, two reads of C per step).
+ * res: host.  Sizes: 1 <= n, 1 <= m.  For m <= 8192 this is accsk_solve_batch
+ * with one problem: n*m <= 65536 is solved by one workgroup; larger problems by
+ * cooperating workgroups that each own a block of about 16 rows, and every
+ * Sinkhorn step reads C once (row and column sums fused).
+ * Larger m, or a row block too large for on-chip memory, uses the tiled
+ * solver (a row sweep and a column sweep, two reads of C per step).
  * Returns ACCSK_OK, ACCSK_NOT_CONVERGED (outputs valid), or an error.
  */
 accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc,
@@ -157,12 +162,14 @@ typedef struct {
 
 /*
  * Batched solve of independent dense problems (Sec. 2 dual, Sec. 4
- * algorithms, stopping rule eq:l1tol per problem).  Problems with m <= 1024
- * and n <= 4096 are each owned by one workgroup: iterate, extrapolation state
- * and homotopy counters stay in on-chip memory and no grid-wide barrier is
- * used.  Larger problems (m <= 8192) share one persistent launch, a group of
- * workgroups per problem with its own barrier.  Every problem stops on its
- * own test.  probs: host array of `count` descriptors (the library copies it);
+ * algorithms, stopping rule eq:l1tol per problem).  A problem that fits one
+ * workgroup (m <= 1024, n <= 4096 and (8m + 4n) * 8 bytes <= 150 KiB) is
+ * owned by one workgroup when n*m <= 65536 or the batch has more than 64
+ * problems: iterate, extrapolation state and homotopy counters stay in
+ * on-chip memory and no grid-wide barrier is used.  Other problems
+ * (m <= 8192) share persistent launches, a group of workgroups per problem
+ * with its own barrier (a problem whose row blocks do not fit on chip goes to
+ * the tiled solver).  Every problem stops on its own test.  probs: host array of `count` descriptors (the library copies it);
  * res: host array of `count` results.  p supplies method, tol, max_iter,
  * mu0, m0, w_rule and flags (p->eps is ignored; each problem has its own).
  * Limits per problem: 1 <= m <= 8192, 1 <= n.

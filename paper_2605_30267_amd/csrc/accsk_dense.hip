@@ -833,6 +833,21 @@ __global__ __launch_bounds__(1024) void eval_final(long long n, long long m, int
     }
 }
 
+// an = a / sum a, bn = b / sum b (one workgroup; FP64 sums).
+__global__ __launch_bounds__(1024) void normalize_pair(const double *__restrict__ a, long long n,
+                                                       const double *__restrict__ b, long long m,
+                                                       double *__restrict__ an, double *__restrict__ bn) {
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    double sa = 0.0, sb = 0.0;
+    for (long long i = tid; i < n; i += 1024) sa += a[i];
+    for (long long j = tid; j < m; j += 1024) sb += b[j];
+    sa = block_sum_1024(sa, red);
+    sb = block_sum_1024(sb, red);
+    for (long long i = tid; i < n; i += 1024) an[i] = a[i] / sa;
+    for (long long j = tid; j < m; j += 1024) bn[j] = b[j] / sb;
+}
+
 // ---------------------------------------------------------------------------
 // Plan rows from potentials.
 // ---------------------------------------------------------------------------
@@ -901,14 +916,19 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         mmax = std::max(mmax, hp[k].m);
         nmin = std::min(nmin, hp[k].n);
     }
-    // blocks per problem: fill the chip with at most two workgroups per CU
+    // Blocks per problem.  A step costs the streaming of the block's rows plus
+    // two grid barriers and a combine of gp column partials, both of which
+    // grow with gp: about 16 rows and at most 64K entries of C per block, at
+    // most one block per CU, was the measured optimum from 100 x 50 to
+    // 8192 x 8192.  The problems of one launch must all be co-resident.
     int occ = 0;
     const size_t dyn_probe = (size_t)(2 * mmax + 5) * sizeof(double);
     ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC>, TPB, dyn_probe));
     if (occ < 1) return ACCSK_SHAPE;
     const long long total = (long long)std::min(occ, 2) * num_cu;
-    long long gp = std::max<long long>(1, total / cnt);
-    gp = std::min<long long>(gp, std::max<long long>(1, nmax));
+    const long long want = std::max((nmax + 15) / 16, (nmax * mmax + 65535) / 65536);
+    long long gp = std::min<long long>({want, (long long)num_cu, total / cnt, nmax});
+    gp = std::max<long long>(gp, 1);
     long long rpb_max = 0;
     for (int k = k0; k < k1; k++) rpb_max = std::max(rpb_max, (hp[k].n + gp - 1) / gp);
     const size_t dyn = (size_t)(2 * mmax + 5 * rpb_max) * sizeof(double);
@@ -1072,6 +1092,9 @@ accsk_status check_params(const accsk_params *p) {
 
 using namespace accsk;
 
+// Routing rule of the batch solver (accsk_small.hip).
+bool accsk_on_one_workgroup(int64_t n, int64_t m, int64_t count);
+
 // Tiled solver of accsk_tiled.hip (m > 8192, or costs formed on the fly).
 accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, const float *Y, int64_t d, int kind,
                                double cost_scale, int64_t n, int64_t m, const double *a, const double *b,
@@ -1086,20 +1109,41 @@ accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const 
     const int cu = device_cu_count();
     if (cu <= 0) return ACCSK_HIP_ERROR;
     std::vector<HostProb> hp((size_t)count);
-    long long mmax = 0;
-    bool vec = true;
     for (int64_t k = 0; k < count; k++) {
         const accsk_problem &q = probs[k];
         hp[(size_t)k] = HostProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps};
-        mmax = std::max<long long>(mmax, q.m);
-        vec = vec && (q.ldc % 4) == 0 && (q.m % 4) == 0 && (((uintptr_t)q.C) & 15) == 0;
     }
-    // at most 256 problems per cooperative launch (one block group each at minimum)
-    for (int64_t k0 = 0; k0 < count; k0 += cu) {
-        const int k1 = (int)std::min<int64_t>(count, k0 + cu);
-        accsk_status st = vec ? dense_chunk_cfg<true>(mmax, hp, (int)k0, k1, p, res, s, cu)
-                              : dense_chunk_cfg<false>(mmax, hp, (int)k0, k1, p, res, s, cu);
+    // At most one CU's worth of problems per cooperative launch.  A launch
+    // whose row blocks do not fit on chip (many rows per block) is split in
+    // halves; a single problem that still does not fit goes to the tiled
+    // solver, whose on-chip footprint does not depend on n or m.
+    int64_t k0 = 0;
+    while (k0 < count) {
+        int64_t k1 = std::min<int64_t>(count, k0 + cu);
+        accsk_status st = ACCSK_SHAPE;
+        while (true) {
+            long long mmax = 0;
+            bool vec = true;
+            for (int64_t k = k0; k < k1; k++) {
+                const HostProb &h = hp[(size_t)k];
+                mmax = std::max(mmax, h.m);
+                vec = vec && (h.ldc % 4) == 0 && (h.m % 4) == 0 && (((uintptr_t)h.C) & 15) == 0;
+            }
+            st = vec ? dense_chunk_cfg<true>(mmax, hp, (int)k0, (int)k1, p, res, s, cu)
+                     : dense_chunk_cfg<false>(mmax, hp, (int)k0, (int)k1, p, res, s, cu);
+            if (st != ACCSK_SHAPE || k1 - k0 == 1) break;
+            k1 = k0 + (k1 - k0) / 2;
+        }
+        if (st == ACCSK_SHAPE) {
+            const HostProb &h = hp[(size_t)k0];
+            st = accsk_tiled_solve(h.C, h.ldc, nullptr, nullptr, 0, 0, 1.0, h.n, h.m, h.a, h.b, p, h.eps, h.f, h.g,
+                                   &res[k0], s);
+            // per-problem outcomes are in res[k0]; only call failures stop the batch
+            if (st == ACCSK_OOM || st == ACCSK_HIP_ERROR || st == ACCSK_SHAPE) return st;
+            st = ACCSK_OK;
+        }
         if (st != ACCSK_OK) return st;
+        k0 = k1;
     }
     return ACCSK_OK;
 }
@@ -1122,10 +1166,34 @@ extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, 
                                (hipStream_t)stream);
         return st;
     }
+    // A batch of one: one workgroup up to 256 x 256 entries, else a group of
+    // cooperating workgroups (or the tiled solver when its row blocks do not
+    // fit on chip).
     accsk_problem q{C, n, m, ldc, a, b, f_out, g_out, p->eps};
-    st = accsk_dense_multi(&q, 1, p, res, (hipStream_t)stream);
-    if (st != ACCSK_OK) return st;
-    return (accsk_status)res->status;
+    st = accsk_solve_batch(&q, 1, p, res, stream);
+    if ((st != ACCSK_OK && st != ACCSK_NOT_CONVERGED) || (p->flags & ACCSK_FLAG_NO_COST) ||
+        !accsk_on_one_workgroup(n, m, 1))
+        return st;
+    // The workgroup reports <C,P> and the dual value from its FP32 exponentials;
+    // re-evaluate both in FP64 at the returned potentials, as the other solvers do.
+    hipStream_t s = (hipStream_t)stream;
+    double *buf = nullptr;
+    if (hipMallocAsync((void **)&buf, (size_t)(n + m + 8) * 8, s) != hipSuccess) return ACCSK_OOM;
+    double *an = buf, *bn = buf + n, *out = buf + n + m;
+    hipLaunchKernelGGL(normalize_pair, dim3(1), dim3(1024), 0, s, a, n, b, m, an, bn);
+    accsk_status se = hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+    if (se == ACCSK_OK) se = run_eval(C, n, m, ldc, p->eps, an, bn, f_out, g_out, out, nullptr, s);
+    double h[5] = {0, 0, 0, 0, 0};
+    if (se == ACCSK_OK) {
+        hipError_t e = hipMemcpyAsync(h, out, 5 * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) se = ACCSK_HIP_ERROR;
+    }
+    (void)hipFreeAsync(buf, s);
+    if (se != ACCSK_OK) return se;
+    res->eot_value = h[2];
+    res->transport_cost = h[3];
+    return st;
 }
 
 extern "C" accsk_status accsk_plan_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,

@@ -44,25 +44,45 @@ hipError_t launch_small_cfg(long long mmax, const SmallProb *d_probs, int count,
 
 using namespace accsk;
 
-// Persistent multi-problem solver of accsk_dense.hip (problems with m > 1024).
+// Persistent multi-problem solver of accsk_dense.hip (problems that do not fit
+// one workgroup).
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
                                accsk_result *res, hipStream_t s);
+
+// Dynamic on-chip memory one workgroup may take (of 160 KiB per CU).
+static constexpr size_t kSmallLdsMax = 150 * 1024;
+
+// A problem is solved by one workgroup when its whole state (potentials,
+// marginals, row shifts, per-wave column sums) fits that workgroup's on-chip
+// memory and its columns fit one row strip of the widest configuration.
+bool accsk_small_fits(int64_t n, int64_t m) {
+    return n >= 1 && m >= 1 && m <= 1024 && n <= 4096 && small_lds_bytes(n, m, 4) <= kSmallLdsMax;
+}
+
+// Up to 256 x 256 entries one workgroup per problem is the fastest way to
+// solve it.  Above that a group of cooperating workgroups per problem is
+// faster as long as the groups are not squeezed to a few workgroups each,
+// i.e. for batches of up to 64 problems (measured per step on 500 x 500 and
+// 1000 x 1000 problems).
+bool accsk_on_one_workgroup(int64_t n, int64_t m, int64_t count) {
+    return accsk_small_fits(n, m) && (n * m <= 65536 || count > 64);
+}
 
 static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, const SmallCtl &ctl,
                                       accsk_result *res, hipStream_t s) {
     const int64_t count = (int64_t)probs.size();
-    long long nmax = 0, mmax = 0;
+    long long mmax = 0;
+    size_t lds = 0;  // each workgroup lays out its own problem: the launch needs the largest one
     bool vec = true;
     std::vector<SmallProb> hp((size_t)count);
     for (int64_t k = 0; k < count; k++) {
         const accsk_problem &q = probs[(size_t)k];
-        nmax = std::max<long long>(nmax, q.n);
         mmax = std::max<long long>(mmax, q.m);
+        lds = std::max(lds, small_lds_bytes(q.n, q.m, 4));
         vec = vec && (q.m % 4 == 0) && (q.ldc % 4 == 0) && ((((uintptr_t)q.C) & 15) == 0);
         hp[(size_t)k] = SmallProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps, q.m - 4};
     }
-    const size_t lds = small_lds_bytes(nmax, mmax, 4);
-    if (lds > 150 * 1024) return ACCSK_SHAPE;
+    if (lds > kSmallLdsMax) return ACCSK_SHAPE;
     const size_t bytes_p = sizeof(SmallProb) * (size_t)count, bytes_r = sizeof(DevResult) * (size_t)count;
     char *buf = nullptr;
     if (hipMallocAsync((void **)&buf, bytes_p + bytes_r + 256, s) != hipSuccess) return ACCSK_OOM;
@@ -120,7 +140,7 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
         if (!q.C || !q.a || !q.b || !q.f || !q.g) return ACCSK_INVALID_ARG;
         if (!small_finite_pos(q.eps)) return ACCSK_INVALID_ARG;
         if (q.n < 1 || q.m < 1 || q.ldc < q.m || q.m > 8192) return ACCSK_SHAPE;
-        if (q.m <= 1024 && q.n <= 4096) {
+        if (accsk_on_one_workgroup(q.n, q.m, count)) {
             small.push_back(q);
             small_idx.push_back(k);
         } else {

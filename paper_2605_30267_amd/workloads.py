@@ -26,6 +26,14 @@ MUSE dictionary of Sec. 5 -- are not available, so these stand in for them):
                         uniform marginals, eps = 5e-3.
 * ``paper_synthetic``   Sec. 5 "Synthetic Datasets": a, b, C with entries
                         U[0,1], a and b normalized to unit sum, C scaled to sum 1.
+* ``color_table``       n = 1000 RGB points per side as in ``color_points``,
+                        uniform marginals, explicit sq-Euclidean / max cost: the
+                        size and marginals of Sec. 5's colour-transfer table.
+* ``word_table``        n = 500 unit vectors in d = 300 and a hidden permutation:
+                        y_pi(i) is x_i plus Gaussian noise, renormalized; uniform
+                        marginals, cosine cost: the size of Sec. 5's
+                        word-alignment table, with a known ground truth for the
+                        top-1 / top-5 readout.
 """
 from __future__ import annotations
 
@@ -148,6 +156,42 @@ def paper_synthetic(seed=6, n=100, m=50, eps=1e-8):
     b = rng.uniform(0.0, 1.0, size=m)
     C = rng.uniform(0.0, 1.0, size=(n, m))
     return dict(C=C / C.sum(), a=a / a.sum(), b=b / b.sum(), eps=eps)
+
+
+def color_table(seed=7, n=1000):
+    """Draw order: X clusters then Y clusters (as ``color_points``); a = b = 1/n.
+
+    Returns float32 X, Y [n,3], C32 = ||x - y||^2 / max over the FP32 points
+    (FP64, rounded to FP32), a, b.
+    """
+    rng = np.random.default_rng(seed)
+    X, _ = _rgb_clusters(rng, n)
+    Y, _ = _rgb_clusters(rng, n)
+    X32, Y32 = X.astype(np.float32), Y.astype(np.float32)
+    C = _sq_dist_over_max(X32.astype(np.float64), Y32.astype(np.float64)).astype(np.float32)
+    return dict(X=X32, Y=Y32, C32=C, a=np.full(n, 1.0 / n), b=np.full(n, 1.0 / n))
+
+
+WORD_NOISE = 4.5  # nearest-neighbour top-1 of the stand-in is about 3/4
+
+
+def word_table(seed=8, n=500, d=300, noise=WORD_NOISE):
+    """Draw order: X [n,d] ~ N(0,I) rows, a permutation pi of n, Z [n,d] ~ N(0,I).
+
+    x_i = X_i/|X_i|; y_pi(i) = u/|u| with u = x_i + noise * Z_i / sqrt(d).
+    Returns float32 X, Y (unit rows), truth = pi (row i's partner is column
+    pi[i]), a = b = 1/n.  The cost is the cosine distance 1 - <x, y> divided
+    by its maximum (see ``accsk.cost_max_points``).
+    """
+    rng = np.random.default_rng(seed)
+    X = unit_rows(rng, n, d)
+    perm = rng.permutation(n)
+    Z = rng.standard_normal(size=(n, d)) / np.sqrt(d)
+    U = X + noise * Z
+    Y = np.empty_like(X)
+    Y[perm] = U / np.linalg.norm(U, axis=1, keepdims=True)
+    return dict(X=X.astype(np.float32), Y=Y.astype(np.float32), truth=perm, a=np.full(n, 1.0 / n),
+                b=np.full(n, 1.0 / n))
 
 
 def random_dense(seed, n, m, eps=1e-2, a_kind="uniform"):

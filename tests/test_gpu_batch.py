@@ -110,7 +110,9 @@ def test_batch_errors(torch_gpu):
 
 
 def test_batch_tall(torch_gpu):
-    """n = 4096 rows (the largest the workgroup keeps in LDS) with few columns."""
+    """n = 4096 rows with few columns: 4096 x 16 on one workgroup (the most rows it
+    keeps on chip), 4096 x 64 on a group of cooperating workgroups (a batch of
+    two problems above 256 x 256 entries)."""
     probs = [W.random_dense(300, 4096, 16, eps=1e-2), W.random_dense(301, 4096, 64, eps=3e-3)]
     print("case batch tall", flush=True)
     _check_batch(torch_gpu, probs, 1)

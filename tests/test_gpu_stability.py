@@ -39,7 +39,9 @@ def _check(r, f, g, C, an, bn, eps, o):
 def test_monitor_and_restart(torch_gpu, path):
     torch = torch_gpu
     from paper_2605_30267_amd import accsk
-    p = W.small_uniform(seed=1, n=256, m=256)
+    # 256 x 256 runs on one workgroup; the cooperative dense solver takes 300 x 300
+    side = 300 if path == "dense" else 256
+    p = W.small_uniform(seed=1, n=side, m=side)
     eps = 1e-3
     C = p["C32"].astype(np.float64)
     an, bn = p["a"], p["b"]
