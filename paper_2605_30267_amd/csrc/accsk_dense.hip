@@ -492,9 +492,34 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
             for (long long cb = j0; cb < j1; cb += CW) {
                 const long long j = cb + coff;
                 double acc = 0.0, pm = -INFINITY;
+                // read-only marginal data of the column, fetched while the partials are in flight
+                double lnbj = 0.0, bnj = 0.0;
+                if (tid < CW && j < j1) {
+                    lnbj = L.lnb[j];
+                    bnj = L.bn[j];
+                }
                 if (pass == 0) {
-                    if (j < j1)
-                        for (int b = grp; b < G; b += NGRP) acc += (double)L.partf[(size_t)b * m + j];
+                    // the partials were written by blocks on other XCDs and miss in L2:
+                    // keep PU loads in flight per thread, summed in block order
+                    if (j < j1) {
+                        constexpr int PU = 8;
+                        // raw buffer over the G x m partials: one offset register per thread,
+                        // the stride between a thread's partials in a scalar register, and
+                        // reads past the last block return 0
+                        const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+                            (void *)L.partf, (short)0, (int)((long long)G * m * 4), 0x00020000);
+                        const int bstride = (int)((long long)NGRP * m * 4);
+                        for (int b0 = grp; b0 < G; b0 += PU * NGRP) {
+                            const int vo = (int)(((long long)b0 * m + j) * 4);
+                            float v[PU];
+#pragma unroll
+                            for (int u = 0; u < PU; u++)
+                                v[u] = __builtin_bit_cast(float,
+                                                          __builtin_amdgcn_raw_buffer_load_b32(prs, vo, u * bstride, 0));
+#pragma unroll
+                            for (int u = 0; u < PU; u++) acc += (double)v[u];
+                        }
+                    }
                 } else {
                     if (j < j1)
                         for (int b = grp; b < G; b += NGRP) pm = fmax(pm, L.partmax[(size_t)b * m + j]);
@@ -526,12 +551,12 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                         lc2 = pm + dlog2(sc) + xj;
                         c = dexp2(lc2);
                     }
-                    const double sh = L.lnb[j] * kLog2e - lc2 + xj;  // (log b_j - ell_j) log2 e
+                    const double sh = lnbj * kLog2e - lc2 + xj;  // (log b_j - ell_j) log2 e
                     L.shat[j] = sh;
                     aS += sh;
-                    aE += fabs(c - L.bn[j]);
+                    aE += fabs(c - bnj);
                     aC += c;
-                    aXB += xj * L.bn[j];
+                    aXB += xj * bnj;
                 }
                 __syncthreads();
             }
@@ -561,7 +586,19 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
             // totals, identical in every block
             for (int sidx = wid; sidx < 6; sidx += NW) {
                 double v = 0.0;
-                for (int b = lane; b < G; b += 64) v += bs[(size_t)b * kNS + sidx];
+                constexpr int TU = 4;  // loads in flight per lane, summed in block order
+                const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)bs, (short)0, (int)((long long)G * kNS * 8), 0x00020000);
+                for (int b0 = lane; b0 < G; b0 += TU * 64) {
+                    const int vo = (int)(((long long)b0 * kNS + sidx) * 8);
+                    double t4[TU];
+#pragma unroll
+                    for (int u = 0; u < TU; u++)
+                        t4[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                               trs, vo, u * 64 * kNS * 8, 0));
+#pragma unroll
+                    for (int u = 0; u < TU; u++) v += t4[u];
+                }
                 v = wave_sum(v);
                 if (lane == 0) tot[sidx] = v;
             }
