@@ -55,11 +55,11 @@ def log(*a):
 def kernel_name(m):
     """Instantiation of the persistent solve kernel the library picks for m columns."""
     if m <= 256:
-        return "dense_solve<64,1,2>"
+        return "dense_solve<256,1,1,WK=1> (wave rows)"
     if m <= 512:
-        return "dense_solve<128,1,2>"
+        return "dense_solve<256,1,1,WK=2> (wave rows)"
     if m <= 1024:
-        return "dense_solve<256,1,4>"
+        return "dense_solve<256,1,1,WK=4> (wave rows)"
     if m <= 2048:
         return "dense_solve<512,1,4>"
     if m <= 4096:

@@ -81,6 +81,17 @@ __device__ __forceinline__ float wave_max_l63(float v) {
     return v;
 }
 
+// Lane 63's value in every lane (wave-uniform).
+__device__ __forceinline__ double wave_bcast63(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float wave_bcast63f(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Combine NW <= 16 per-wave partials stored in LDS: lane l loads v[l % 16]
 // (identity for l % 16 >= NW), a 16-lane DPP reduction leaves the total in
 // lane 15 of every row, and readlane makes it uniform.  Same order everywhere.
