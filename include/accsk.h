@@ -180,6 +180,22 @@ accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t count, const 
                                accsk_result *res, void *stream);
 
 /*
+ * accsk_solve_batch for `batch` problems of one shape stored as strided arrays
+ * (Sec. 2 dual, Sec. 4 algorithms, eq:l1tol per problem; same routing and
+ * kernels).  Problem k: cost C + k*stride_c (device FP32, n x m row-major,
+ * leading dimension ldc >= m, stride_c >= (n-1)*ldc + m), marginals a + k*n and
+ * b + k*m (device FP64, > 0, normalized inside), outputs f_out + k*n and
+ * g_out + k*m (device FP64).  eps: host FP64[batch] of per-problem
+ * regularizations, or NULL for p->eps in every problem.  res: host array of
+ * `batch` results.  The descriptors are built on the host, so a large batch
+ * costs one call.  Returns as accsk_solve_batch.
+ */
+accsk_status accsk_solve_batch_strided(const float *C, int64_t batch, int64_t n, int64_t m, int64_t ldc,
+                                       int64_t stride_c, const double *a, const double *b, const double *eps,
+                                       const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
+                                       void *stream);
+
+/*
  * Cost matrix from point clouds (Sec. 5: squared Euclidean for colour
  * transfer, cosine for word alignment).  X: device FP32 n x d, Y: device FP32
  * m x d (row-major, rows contiguous).  C: device FP32 n x m, leading

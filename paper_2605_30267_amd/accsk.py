@@ -90,6 +90,9 @@ def lib():
         L.accsk_solve_batch.argtypes = [ctypes.POINTER(Problem), _i64, ctypes.POINTER(Params),
                                         ctypes.POINTER(Result), _vp]
         L.accsk_solve_batch.restype = ctypes.c_int
+        L.accsk_solve_batch_strided.argtypes = [_vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp,
+                                                ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(Result), _vp]
+        L.accsk_solve_batch_strided.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -198,6 +201,55 @@ def solve_batch(problems, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=No
     if raise_on_error and st not in (OK, NOT_CONVERGED):
         raise AccskError(st, "accsk_solve_batch")
     return outs, [r.to_dict() for r in res], st
+
+
+def solve_batch_strided(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=None, w_rule=None,
+                        flags=0, raise_on_error=True):
+    """Solve B problems of one shape held in strided tensors (one call, no per-problem work in Python).
+
+    C: float32 [B, n, m] on the device, unit column stride; a: float64 [B, n]; b: float64 [B, m];
+    eps: a float or a sequence of B floats.  Returns (f [B, n], g [B, m], results, status) with
+    results a dict of numpy arrays of length B, one per result field.
+    """
+    import torch
+    _check_dev(C, torch.float32, "C", 3)
+    _check_dev(a, torch.float64, "a", 2)
+    _check_dev(b, torch.float64, "b", 2)
+    if C.stride(2) != 1:
+        raise ValueError("C must have unit column stride")
+    B, n, m = C.shape
+    if tuple(a.shape) != (B, n) or tuple(b.shape) != (B, m):
+        raise ValueError("a must be [B, n] and b [B, m]")
+    a = a.contiguous()
+    b = b.contiguous()
+    f = torch.empty((B, n), dtype=torch.float64, device=C.device)
+    g = torch.empty((B, m), dtype=torch.float64, device=C.device)
+    if isinstance(eps, (int, float)):
+        p = default_params(eps=float(eps), method=method, tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0,
+                           w_rule=w_rule, flags=int(flags))
+        eps_arr = None
+    else:
+        p = default_params(method=method, tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0, w_rule=w_rule,
+                           flags=int(flags))
+        if len(eps) != B:
+            raise ValueError("eps must have one value per problem")
+        eps_arr = (ctypes.c_double * B)(*[float(e) for e in eps])
+    res = (Result * B)()
+    st = lib().accsk_solve_batch_strided(_ptr(C), B, n, m, C.stride(1), C.stride(0), _ptr(a), _ptr(b), eps_arr,
+                                         ctypes.byref(p), _ptr(f), _ptr(g), res, _stream_ptr())
+    if raise_on_error and st not in (OK, NOT_CONVERGED):
+        raise AccskError(st, "accsk_solve_batch_strided")
+    return f, g, results_as_arrays(res), st
+
+
+def results_as_arrays(res):
+    """A ctypes array of Result as a dict of numpy arrays, one per field (no per-problem objects)."""
+    import numpy as np
+    kinds = {ctypes.c_int64: "<i8", ctypes.c_double: "<f8", ctypes.c_int32: "<i4"}
+    dt = np.dtype([(k, kinds[t]) for k, t in Result._fields_], align=True)
+    assert dt.itemsize == ctypes.sizeof(Result)
+    view = np.frombuffer(res, dtype=dt)
+    return {k: view[k].copy() for k, _ in Result._fields_}
 
 
 def plan_dense(C, f, g, eps, row0=0, rows=None, out=None):

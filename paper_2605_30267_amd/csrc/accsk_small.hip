@@ -169,3 +169,17 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
     }
     return worst;
 }
+
+extern "C" accsk_status accsk_solve_batch_strided(const float *C, int64_t batch, int64_t n, int64_t m, int64_t ldc,
+                                                  int64_t stride_c, const double *a, const double *b,
+                                                  const double *eps, const accsk_params *p, double *f_out,
+                                                  double *g_out, accsk_result *res, void *stream) {
+    if (!C || !a || !b || !p || !f_out || !g_out || !res || batch < 0) return ACCSK_INVALID_ARG;
+    if (batch == 0) return ACCSK_OK;
+    if (n < 1 || m < 1 || ldc < m || stride_c < (n - 1) * ldc + m) return ACCSK_SHAPE;
+    std::vector<accsk_problem> probs((size_t)batch);
+    for (int64_t k = 0; k < batch; k++)
+        probs[(size_t)k] = accsk_problem{C + k * stride_c, n, m, ldc, a + k * n, b + k * m, f_out + k * n,
+                                         g_out + k * m, eps ? eps[k] : p->eps};
+    return accsk_solve_batch(probs.data(), batch, p, res, stream);
+}

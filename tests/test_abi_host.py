@@ -90,6 +90,21 @@ def test_host_validation_batch(lib):
     assert lib.accsk_solve_batch(arr, 0, ctypes.byref(p), res, None) == accsk.OK
 
 
+def test_host_validation_batch_strided(lib):
+    p = accsk.default_params()
+    res = (accsk.Result * 2)()
+    fake = 4096  # never dereferenced: every case fails validation on the host
+    f = lib.accsk_solve_batch_strided
+    assert f(None, 2, 4, 4, 4, 16, fake, fake, None, ctypes.byref(p), fake, fake, res, None) == accsk.INVALID_ARG
+    assert f(fake, -1, 4, 4, 4, 16, fake, fake, None, ctypes.byref(p), fake, fake, res, None) == accsk.INVALID_ARG
+    assert f(fake, 0, 4, 4, 4, 16, fake, fake, None, ctypes.byref(p), fake, fake, res, None) == accsk.OK
+    assert f(fake, 2, 4, 4, 3, 16, fake, fake, None, ctypes.byref(p), fake, fake, res, None) == accsk.SHAPE
+    assert f(fake, 2, 4, 4, 4, 15, fake, fake, None, ctypes.byref(p), fake, fake, res, None) == accsk.SHAPE
+    assert f(fake, 2, 0, 4, 4, 16, fake, fake, None, ctypes.byref(p), fake, fake, res, None) == accsk.SHAPE
+    bad_eps = (ctypes.c_double * 2)(1e-2, -1.0)
+    assert f(fake, 2, 4, 4, 4, 16, fake, fake, bad_eps, ctypes.byref(p), fake, fake, res, None) == accsk.INVALID_ARG
+
+
 def test_host_validation_server(lib):
     accsk._register_server(lib)
     h = ctypes.c_void_p()
@@ -105,3 +120,14 @@ def test_host_validation_server(lib):
     assert lib.accsk_server_destroy(None) == accsk.INVALID_ARG
     t0 = lib.accsk_clock_seconds()
     assert lib.accsk_clock_seconds() >= t0 > 0
+
+
+def test_results_as_arrays_layout():
+    """The numpy view of a Result array reads every field at the ctypes offsets."""
+    r = (accsk.Result * 3)()
+    r[1].iters, r[1].eot_value, r[2].status, r[2].converged, r[0].kernel_ms = 7, 1.5, 4, 1, 2.5
+    r[0].restarts, r[2].dual_fval = 3, -0.25
+    d = accsk.results_as_arrays(r)
+    for k in range(3):
+        for name, _ in accsk.Result._fields_:
+            assert d[name][k] == getattr(r[k], name), (k, name)

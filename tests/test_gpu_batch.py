@@ -142,3 +142,32 @@ def test_batch_gaussian_shape(torch_gpu):
         probs.append(dict(C32=C, a=gb["a"][k], b=gb["b"][k], eps=gb["eps"]))
     print("case batch gaussian 16x2048", flush=True)
     _check_batch(torch_gpu, probs[:4], 1)
+
+
+def test_batch_strided_equals_list(torch_gpu):
+    """One strided call (padded rows, per-problem eps) gives the bits of the descriptor-list call."""
+    from paper_2605_30267_amd import accsk
+    torch = torch_gpu
+    B, n, m = 70, 96, 80
+    probs = [W.random_dense(600 + k, n, m, eps=1e-2) for k in range(B)]
+    Cw = torch.zeros((B, n, m + 4), dtype=torch.float32, device="cuda")
+    for k, p in enumerate(probs):
+        Cw[k, :, :m] = _dev(torch, p["C32"], torch.float32)
+    C = Cw[:, :, :m]  # leading dimension m + 4
+    a = torch.stack([_dev(torch, p["a"], torch.float64) for p in probs])
+    b = torch.stack([_dev(torch, p["b"], torch.float64) for p in probs])
+    eps = [1e-2 if k % 2 else 3e-3 for k in range(B)]
+    print("case strided batch", B, n, m, flush=True)
+    f, g, res, st = accsk.solve_batch_strided(C, a, b, eps)
+    outs, res2, st2 = accsk.solve_batch([(C[k], a[k], b[k], eps[k]) for k in range(B)])
+    torch.cuda.synchronize()
+    assert st == st2 == accsk.OK
+    for k in range(B):
+        assert torch.equal(f[k], outs[k][0]) and torch.equal(g[k], outs[k][1])
+        assert res["iters"][k] == res2[k]["iters"] and res["eot_value"][k] == res2[k]["eot_value"]
+    p = dict(probs[5], eps=eps[5])
+    C64 = p["C32"].astype(np.float64)
+    ev = O.evaluate(C64, p["eps"], p["a"], p["b"], f[5].cpu().numpy(), g[5].cpu().numpy())
+    assert res["converged"][5] == 1 and ev["err"] <= 1e-6
+    dp = accsk.default_params()
+    check_stop(C64, p["a"], p["b"], p["eps"], 1e-6, O.ACC, int(res["iters"][5]), dp.mu0, dp.m0, dp.w_rule)
