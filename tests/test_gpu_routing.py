@@ -10,6 +10,8 @@
   (256 problems of 600 x 8192) is split into launches that fit.
 * A single problem whose row blocks cannot fit on chip at one block per CU
   (900000 x 1025, 3.7 GB of cost) goes to the tiled solver.
+* A launch of 16 problems with 1500 to 1911 columns runs the wave-rows kernel
+  with 32 columns per lane.
 
 Bars as in the batch parity tests (FP64 marginal error <= tol, stopping
 iterate against the oracle's trace, dual value); identical problems in one
@@ -126,3 +128,21 @@ def test_tall_single_problem_tiled_fallback(torch_gpu):
     err = float(torch.abs(col - torch.as_tensor(bn, device="cuda")).sum())
     print("  FP64 column error", err, flush=True)
     assert err <= tol
+
+
+def test_wave_rows_wide_batch(torch_gpu):
+    """m in (1024, 2048] in a launch of 16 problems: the wave-rows kernel with 32 columns per lane."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    kinds = [W.random_dense(510 + k, 300, 1500 + 137 * k, eps=1e-2, a_kind="dirichlet") for k in range(4)]
+    dev = [(_dev(torch, p["C32"], torch.float32), _dev(torch, p["a"], torch.float64),
+            _dev(torch, p["b"], torch.float64), p["eps"]) for p in kinds]
+    batch = [dev[k % 4] for k in range(16)]
+    print("case 16-problem batch, m = 1500..1911", flush=True)
+    outs, res, st = accsk.solve_batch(batch)
+    torch.cuda.synchronize()
+    assert st == accsk.OK
+    for k in range(2):
+        _oracle_check(kinds[k], outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy(), res[k])
+    for k in range(4, 16):
+        assert torch.equal(outs[k][0], outs[k % 4][0]) and torch.equal(outs[k][1], outs[k % 4][1])
