@@ -467,8 +467,25 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                 const long long j = cb + coff;
                 double acc = 0.0, pm = -INFINITY;
                 if (pass == 0) {
-                    if (j < j1)
-                        for (int b = grp; b < G; b += NGRP) acc += (double)A.partf[(size_t)b * m + j];
+                    // the partials come from blocks on other XCDs and miss in L2: a raw buffer
+                    // (one offset register, the stride in a scalar register, reads past the
+                    // last block return 0) keeps PU loads in flight, summed in block order
+                    if (j < j1) {
+                        constexpr int PU = 8;
+                        const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+                            (void *)A.partf, (short)0, (int)((long long)G * m * 4), 0x00020000);
+                        const int bstride = (int)((long long)NGRP * m * 4);
+                        for (int b0 = grp; b0 < G; b0 += PU * NGRP) {
+                            const int vo = (int)(((long long)b0 * m + j) * 4);
+                            float v[PU];
+#pragma unroll
+                            for (int u = 0; u < PU; u++)
+                                v[u] = __builtin_bit_cast(float,
+                                                          __builtin_amdgcn_raw_buffer_load_b32(prs, vo, u * bstride, 0));
+#pragma unroll
+                            for (int u = 0; u < PU; u++) acc += (double)v[u];
+                        }
+                    }
                 } else {
                     if (j < j1)
                         for (int b = grp; b < G; b += NGRP) pm = fmax(pm, A.partmax[(size_t)b * m + j]);
