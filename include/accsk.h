@@ -74,6 +74,12 @@ typedef struct {
     int32_t split;      /* point-cloud cross terms X Y^T: 0 = FP64 dot products (default),
                            2 or 3 = BF16 matrix cores on a 2- or 3-piece split of X and Y */
     int32_t flags;      /* ACCSK_FLAG_* bits */
+    double *err_trace;  /* optional device FP64 buffer, NULL for none: err_trace[k] receives the L1
+                           marginal error (eq:l1tol, as the stop test computes it) of the iterate
+                           evaluated by the k-th Sinkhorn step, for k < trace_len.  Calls on one
+                           problem only (accsk_solve_dense, accsk_solve_points, batches of one);
+                           with several problems, or on a server, it is INVALID_ARG */
+    int64_t trace_len;  /* entries of err_trace, >= 0 */
 } accsk_params;
 
 #define ACCSK_FLAG_NO_COST 1       /* skip the final <C,P> pass */

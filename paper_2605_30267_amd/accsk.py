@@ -34,7 +34,8 @@ class AccskError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("w_rule", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("mu0", ctypes.c_double),
-                ("m0", ctypes.c_int64), ("split", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("m0", ctypes.c_int64), ("split", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("err_trace", ctypes.c_void_p), ("trace_len", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
@@ -135,12 +136,24 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _trace_buffer(p, trace, max_iter, device):
+    """Device FP64 buffer for the per-step error trace (one entry per Sinkhorn step), or None."""
+    if not trace:
+        return None
+    import torch
+    buf = torch.full((int(max_iter) + 1,), float("nan"), dtype=torch.float64, device=device)
+    p.err_trace = buf.data_ptr()
+    p.trace_len = buf.numel()
+    return buf
+
+
 def solve_dense(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=None,
-                w_rule=None, flags=0, f_out=None, g_out=None, raise_on_error=True):
+                w_rule=None, flags=0, f_out=None, g_out=None, raise_on_error=True, trace=False):
     """Solve EOT on a dense FP32 cost (device).  Returns (f, g, result dict).
 
     C: float32 [n, m] (row stride used as leading dimension, unit column stride);
     a: float64 [n], b: float64 [m] (positive; normalized inside).
+    trace=True adds result["trace"]: the L1 marginal error of every Sinkhorn step (numpy).
     """
     import torch
     _check_dev(C, torch.float32, "C", 2)
@@ -157,6 +170,7 @@ def solve_dense(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m
         g_out = torch.empty(m, dtype=torch.float64, device=C.device)
     p = default_params(method=method, eps=float(eps), tol=float(tol), max_iter=int(max_iter), mu0=mu0,
                        m0=m0, w_rule=w_rule, flags=int(flags))
+    tbuf = _trace_buffer(p, trace, max_iter, C.device)
     r = Result()
     st = lib().accsk_solve_dense(_ptr(C), n, m, C.stride(0), _ptr(a), _ptr(b), ctypes.byref(p), _ptr(f_out),
                                  _ptr(g_out), ctypes.byref(r), _stream_ptr())
@@ -164,6 +178,8 @@ def solve_dense(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m
         raise AccskError(st, "accsk_solve_dense")
     d = r.to_dict()
     d["status"] = st
+    if tbuf is not None:
+        d["trace"] = tbuf[:max(0, min(r.sinkhorn_steps, tbuf.numel()))].cpu().numpy()
     return f_out, g_out, d
 
 
@@ -419,12 +435,14 @@ def _as_batched(X, Y, a, b):
 
 
 def solve_points(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e-6, method=ACC,
-                 max_iter=100000, mu0=None, m0=None, w_rule=None, flags=0, on_the_fly=False, raise_on_error=True):
+                 max_iter=100000, mu0=None, m0=None, w_rule=None, flags=0, on_the_fly=False, raise_on_error=True,
+                 trace=False):
     """EOT between point clouds.  X [n,d] / [B,n,d] float32, a [n] / [B,n] float64.
 
     on_the_fly: form the cost in every step instead of storing it (d <= 16;
     implied for m > 8192).  Returns (f, g, results): f, g shaped like a, b;
-    results a list of dicts.
+    results a list of dicts.  trace=True (one problem only) adds results[0]["trace"],
+    the L1 marginal error of every Sinkhorn step.
     """
     if on_the_fly:
         flags = int(flags) | FLAG_ON_THE_FLY
@@ -436,6 +454,7 @@ def solve_points(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e
     g = torch.empty((B, m), dtype=torch.float64, device=X.device)
     p = default_params(method=method, eps=float(eps), tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0,
                        w_rule=w_rule, split=int(split), flags=int(flags))
+    tbuf = _trace_buffer(p, trace, max_iter, X.device)
     res = (Result * B)()
     st = _points_lib().accsk_solve_points_batched(_ptr(X), _ptr(Y), B, n, m, d, int(kind), float(cost_scale),
                                                   _ptr(a), _ptr(b), ctypes.byref(p), _ptr(f), _ptr(g), res,
@@ -443,6 +462,8 @@ def solve_points(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e
     if raise_on_error and st not in (OK, NOT_CONVERGED):
         raise AccskError(st, "accsk_solve_points_batched")
     out = [r.to_dict() for r in res]
+    if tbuf is not None:
+        out[0]["trace"] = tbuf[:max(0, min(res[0].sinkhorn_steps, tbuf.numel()))].cpu().numpy()
     if single:
         return f[0], g[0], out
     return f, g, out

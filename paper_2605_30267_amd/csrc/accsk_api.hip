@@ -18,6 +18,8 @@ extern "C" void accsk_default_params(accsk_params *p) {
     p->m0 = kDefaultM0;
     p->split = 0;
     p->flags = 0;
+    p->err_trace = nullptr;
+    p->trace_len = 0;
 }
 
 extern "C" const char *accsk_status_string(int status) {

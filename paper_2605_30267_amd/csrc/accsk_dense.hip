@@ -64,6 +64,8 @@ struct DenseArgs {
     double eps, kappa, tol, tol_stop, mu0;
     long long max_iter, m0;
     int method, w_rule, serpentine, restart;
+    double *trace;  // optional per-step error trace (one problem per launch)
+    long long trace_len;
 };
 
 // ---------------------------------------------------------------------------
@@ -722,6 +724,7 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
         st.mass = tot[3];
         st.xb2 = tot[4];
         st.steps++;
+        if (bid == 0 && tid == 0 && A.trace && st.steps <= A.trace_len) xstore(&A.trace[st.steps - 1], st.err);
         const double fval = 1.0 - (tot[0] + tot[4]) * kLn2;  // f(x) = 1 - <u,a> - <x,b> at this step's x
         bool stop = false;
         if (!isfinite(st.err)) {
@@ -1130,6 +1133,8 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         A.w_rule = p->w_rule;
         A.serpentine = (p->flags & ACCSK_FLAG_NO_SERPENTINE) ? 0 : 1;
         A.restart = (p->flags & ACCSK_FLAG_RESTART) ? 1 : 0;
+        A.trace = p->err_trace;
+        A.trace_len = p->trace_len;
         char *q0 = base + o_prob[q];
         A.an = (double *)q0;
         A.la2 = A.an + n;
@@ -1237,6 +1242,7 @@ accsk_status check_params(const accsk_params *p) {
     if (p->method != ACCSK_SINKHORN && p->method != ACCSK_ACC) return ACCSK_INVALID_ARG;
     if (p->method == ACCSK_ACC && !(p->mu0 > 0.0 && p->mu0 < 1.0 && p->m0 >= 1)) return ACCSK_INVALID_ARG;
     if (p->w_rule != ACCSK_W_LITERAL && p->w_rule != ACCSK_W_Y_CONTINUOUS) return ACCSK_INVALID_ARG;
+    if (p->trace_len < 0 || (p->trace_len > 0 && !p->err_trace)) return ACCSK_INVALID_ARG;
     return ACCSK_OK;
 }
 

@@ -585,6 +585,8 @@ extern "C" accsk_status accsk_solve_points_batched(const float *X, const float *
                                                    double *f_out, double *g_out, accsk_result *res,
                                                    void *stream) {
     if (!p || !a || !b || !f_out || !g_out || !res || batch < 1) return ACCSK_INVALID_ARG;
+    if (p->err_trace && batch > 1) return ACCSK_INVALID_ARG;  // one trace buffer: one problem
+    if (p->trace_len < 0 || (p->trace_len > 0 && !p->err_trace)) return ACCSK_INVALID_ARG;
     accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, p->split);
     if (st != ACCSK_OK) return st;
     if (!finite_pos(p->eps)) return ACCSK_INVALID_ARG;

@@ -527,6 +527,7 @@ extern "C" accsk_status accsk_server_create(size_t hbm_budget, int max_slots, co
                                             accsk_server **out) {
     if (!out || !p) return ACCSK_INVALID_ARG;
     *out = nullptr;
+    if (p->err_trace || p->trace_len != 0) return ACCSK_INVALID_ARG;  // no per-step trace when serving
     SmallCtl ctl;
     accsk_status st = small_ctl_from_params(p, &ctl);
     if (st != ACCSK_OK) return st;

@@ -130,6 +130,7 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
                                           accsk_result *res, void *stream) {
     if (!probs || !res || !p || count < 0) return ACCSK_INVALID_ARG;
     if (count == 0) return ACCSK_OK;
+    if (p->err_trace && count > 1) return ACCSK_INVALID_ARG;  // one trace buffer: one problem
     SmallCtl ctl;
     accsk_status st = small_ctl_from_params(p, &ctl);
     if (st != ACCSK_OK) return st;

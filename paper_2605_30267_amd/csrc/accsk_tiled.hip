@@ -83,6 +83,8 @@ struct TiledArgs {
     double eps, tol, tol_stop, mu0;
     long long max_iter, m0;
     int method, w_rule, flags;
+    double *trace;  // optional per-step error trace
+    long long trace_len;
 };
 
 __device__ double tblock_sum(double v, double *red) {
@@ -560,6 +562,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         if (status != ACCSK_OK) break;
 
         err = tot[2];
+        if (bid == 0 && tid == 0 && A.trace && steps + 1 <= A.trace_len) xstore(&A.trace[steps], err);
         const double mean = tot[1] / (double)m;
         last_mass = tot[3];
         last_xb2 = tot[4];
@@ -736,6 +739,8 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     A.method = p->method;
     A.w_rule = p->w_rule;
     A.flags = p->flags;
+    A.trace = p->trace_len > 0 ? p->err_trace : nullptr;
+    A.trace_len = p->trace_len;
     TiledArgs *d_args = (TiledArgs *)(base + o_args);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;

@@ -38,6 +38,8 @@ struct SmallCtl {
     double tol, tol_stop, mu0;
     long long max_iter, m0;
     int method, w_rule, flags;
+    double *trace;  // optional per-step error trace (launches of one problem)
+    long long trace_len;
 };
 
 // ---- butterfly reductions over the LPR lanes of a row (all lanes get the result)
@@ -341,6 +343,7 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
         const double fval = 1.0 - (wg_sum<NW>(aU, red) + xb2) * kLn2;
         const double mean = sumS / (double)m;
         steps++;
+        if (tid == 0 && ctl.trace && steps <= ctl.trace_len) xstore(&ctl.trace[steps - 1], err);
         if (!isfinite(err)) {
             status = (steps == 1) ? ACCSK_NONFINITE : ACCSK_DIVERGED;
             break;
@@ -445,6 +448,7 @@ inline accsk_status small_ctl_from_params(const accsk_params *p, SmallCtl *c) {
     if (p->method != ACCSK_SINKHORN && p->method != ACCSK_ACC) return ACCSK_INVALID_ARG;
     if (p->method == ACCSK_ACC && !(p->mu0 > 0.0 && p->mu0 < 1.0 && p->m0 >= 1)) return ACCSK_INVALID_ARG;
     if (p->w_rule != ACCSK_W_LITERAL && p->w_rule != ACCSK_W_Y_CONTINUOUS) return ACCSK_INVALID_ARG;
+    if (p->trace_len < 0 || (p->trace_len > 0 && !p->err_trace)) return ACCSK_INVALID_ARG;
     c->tol = p->tol;
     c->tol_stop = p->tol * (1.0 - 1.0 / 16.0);
     c->mu0 = p->mu0;
@@ -453,6 +457,8 @@ inline accsk_status small_ctl_from_params(const accsk_params *p, SmallCtl *c) {
     c->method = p->method;
     c->w_rule = p->w_rule;
     c->flags = p->flags;
+    c->trace = p->trace_len > 0 ? p->err_trace : nullptr;
+    c->trace_len = p->trace_len;
     return ACCSK_OK;
 }
 

@@ -131,3 +131,26 @@ def test_results_as_arrays_layout():
     for k in range(3):
         for name, _ in accsk.Result._fields_:
             assert d[name][k] == getattr(r[k], name), (k, name)
+
+
+def test_host_validation_trace(lib):
+    """The per-step error trace: one problem per call, a buffer for a positive length, not on a server."""
+    fake = 4096  # never dereferenced: every case fails validation on the host
+    r = accsk.Result()
+    p = accsk.default_params(trace_len=-1)
+    assert lib.accsk_solve_dense(fake, 4, 4, 4, fake, fake, ctypes.byref(p), fake, fake, ctypes.byref(r),
+                                 None) == accsk.INVALID_ARG
+    p = accsk.default_params(trace_len=5)  # no buffer
+    assert lib.accsk_solve_dense(fake, 4, 4, 4, fake, fake, ctypes.byref(p), fake, fake, ctypes.byref(r),
+                                 None) == accsk.INVALID_ARG
+    p = accsk.default_params(err_trace=fake, trace_len=5)
+    res = (accsk.Result * 2)()
+    arr = (accsk.Problem * 2)(accsk.Problem(fake, 4, 4, 4, fake, fake, fake, fake, 1e-2),
+                              accsk.Problem(fake, 4, 4, 4, fake, fake, fake, fake, 1e-2))
+    assert lib.accsk_solve_batch(arr, 2, ctypes.byref(p), res, None) == accsk.INVALID_ARG
+    pl = accsk._points_lib()
+    assert pl.accsk_solve_points_batched(fake, fake, 2, 4, 4, 3, 0, 1.0, fake, fake, ctypes.byref(p), fake, fake,
+                                         res, None) == accsk.INVALID_ARG
+    accsk._register_server(lib)
+    h = ctypes.c_void_p()
+    assert lib.accsk_server_create(1 << 20, 0, ctypes.byref(p), ctypes.byref(h)) == accsk.INVALID_ARG
