@@ -118,6 +118,17 @@ void accsk_default_params(accsk_params *p);
 /* Human-readable name of a status code (static storage). */
 const char *accsk_status_string(int status);
 
+/*
+ * Upper bound of the device workspace (bytes) that accsk_solve_dense,
+ * accsk_solve_batch or accsk_solve_batch_strided allocates for `count`
+ * problems of at most n x m.  The library allocates it stream-ordered from the
+ * device's default memory pool (hipMallocAsync / hipFreeAsync on the caller's
+ * stream), so a caller can pre-size that pool with this figure.  Needs the
+ * current device (its CU count).  Errors: INVALID_ARG (bytes NULL, count < 1),
+ * SHAPE (n or m < 1), HIP_ERROR (no device).
+ */
+accsk_status accsk_workspace_bytes(int64_t n, int64_t m, int64_t count, size_t *bytes);
+
 /* Library version string (static storage). */
 const char *accsk_version(void);
 

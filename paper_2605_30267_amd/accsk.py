@@ -94,6 +94,8 @@ def lib():
         L.accsk_solve_batch_strided.argtypes = [_vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp,
                                                 ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(Result), _vp]
         L.accsk_solve_batch_strided.restype = ctypes.c_int
+        L.accsk_workspace_bytes.argtypes = [_i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)]
+        L.accsk_workspace_bytes.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -217,6 +219,15 @@ def solve_batch(problems, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=No
     if raise_on_error and st not in (OK, NOT_CONVERGED):
         raise AccskError(st, "accsk_solve_batch")
     return outs, [r.to_dict() for r in res], st
+
+
+def workspace_bytes(n, m, count=1):
+    """Upper bound of the device workspace of a dense or batched solve (bytes)."""
+    out = ctypes.c_size_t(0)
+    st = lib().accsk_workspace_bytes(int(n), int(m), int(count), ctypes.byref(out))
+    if st != OK:
+        raise AccskError(st, "accsk_workspace_bytes")
+    return out.value
 
 
 def solve_batch_strided(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=None, w_rule=None,

@@ -64,8 +64,6 @@ struct DenseArgs {
     double eps, kappa, tol, tol_stop, mu0;
     long long max_iter, m0;
     int method, w_rule, serpentine, restart;
-    double *trace;  // optional per-step error trace (one problem per launch)
-    long long trace_len;
 };
 
 // ---------------------------------------------------------------------------
@@ -187,8 +185,11 @@ __device__ __forceinline__ float f4get(const float4 &v, int e) {
 // wave owns whole rows, lane l holding columns 4 (l + 64 k) + e for k < WK
 // (m <= 256 WK); row sums stay inside the wave and the waves' column sums are
 // combined once per step.
-template <int TPB, int NG, int RB, bool VEC, int WK = 0>
-__global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__ probs, int gp) {
+// TR: write the per-step error trace (trace / trace_len).  A separate
+// instantiation, so that untraced solves carry no trace code at all.
+template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false>
+__global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__ probs, int gp,
+                                                   double *__restrict__ trace, long long trace_len) {
     // gp workgroups per problem; problem p owns blocks [p*gp, (p+1)*gp)
     const DenseArgs A = probs[blockIdx.x / gp];
     constexpr int NW = TPB / 64;
@@ -724,7 +725,9 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
         st.mass = tot[3];
         st.xb2 = tot[4];
         st.steps++;
-        if (bid == 0 && tid == 0 && A.trace && st.steps <= A.trace_len) xstore(&A.trace[st.steps - 1], st.err);
+        if constexpr (TR) {
+            if (bid == 0 && tid == 0 && st.steps <= trace_len) xstore(&trace[st.steps - 1], st.err);
+        }
         const double fval = 1.0 - (tot[0] + tot[4]) * kLn2;  // f(x) = 1 - <u,a> - <x,b> at this step's x
         bool stop = false;
         if (!isfinite(st.err)) {
@@ -1053,7 +1056,7 @@ struct HostProb {
 
 // Solves problems [k0, k1) of `hp` with one cooperative launch, gp workgroups
 // per problem.  Results go to res[k0..k1).
-template <int TPB, int NG, int RB, bool VEC, int WK = 0>
+template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false>
 accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const accsk_params *p,
                          accsk_result *res, hipStream_t s, int num_cu) {
     const int cnt = k1 - k0;
@@ -1072,7 +1075,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     const long long mextra = WK > 0 ? mmax : 0;  // column sums of the wave-rows pass
     const size_t dyn_probe = (size_t)(2 * mmax + mextra + 5) * sizeof(double);
     ACCSK_HIP_TRY(
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC, WK>, TPB, dyn_probe));
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC, WK, TR>, TPB, dyn_probe));
     if (occ < 1) return ACCSK_SHAPE;
     const long long total = (long long)std::min(occ, 2) * num_cu;
     const long long want = std::max((nmax + 15) / 16, (nmax * mmax + 65535) / 65536);
@@ -1083,7 +1086,8 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     const size_t dyn = (size_t)(2 * mmax + mextra + 5 * rpb_max) * sizeof(double);
     if (dyn > 150 * 1024) return ACCSK_SHAPE;
     int occ2 = 0;
-    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, dense_solve<TPB, NG, RB, VEC, WK>, TPB, dyn));
+    ACCSK_HIP_TRY(
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, dense_solve<TPB, NG, RB, VEC, WK, TR>, TPB, dyn));
     if (occ2 < 1 || (long long)cnt * gp > (long long)occ2 * num_cu) return ACCSK_SHAPE;
 
     // workspace: shared arrays first (args, results, scalars, barriers), then per-problem slices
@@ -1133,8 +1137,6 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         A.w_rule = p->w_rule;
         A.serpentine = (p->flags & ACCSK_FLAG_NO_SERPENTINE) ? 0 : 1;
         A.restart = (p->flags & ACCSK_FLAG_RESTART) ? 1 : 0;
-        A.trace = p->err_trace;
-        A.trace_len = p->trace_len;
         char *q0 = base + o_prob[q];
         A.an = (double *)q0;
         A.la2 = A.an + n;
@@ -1170,8 +1172,10 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
     if (e == hipSuccess) {
         int gpi = (int)gp;
-        void *kargs[] = {&d_args, &gpi};
-        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, RB, VEC, WK>, dim3((unsigned)(cnt * gp)),
+        double *tr = TR ? p->err_trace : nullptr;  // traced launches hold one problem
+        long long tl = TR ? p->trace_len : 0;
+        void *kargs[] = {&d_args, &gpi, &tr, &tl};
+        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, RB, VEC, WK, TR>, dim3((unsigned)(cnt * gp)),
                                        dim3(TPB), kargs, dyn, s);
     }
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
@@ -1215,22 +1219,34 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     return ACCSK_OK;
 }
 
-template <bool VEC>
-accsk_status dense_chunk_cfg(long long mmax, const std::vector<HostProb> &hp, int k0, int k1,
-                             const accsk_params *p, accsk_result *res, hipStream_t s, int cu) {
+template <bool VEC, bool TR>
+accsk_status dense_chunk_cfg_t(long long mmax, const std::vector<HostProb> &hp, int k0, int k1,
+                               const accsk_params *p, accsk_result *res, hipStream_t s, int cu) {
     // Up to 1024 columns each wave owns whole rows (4 to 16 columns per lane):
     // 20-34 % faster per step than rows spread over the workgroup, whose
     // cross-wave row reductions cost more than the row's arithmetic.  With
     // 2048 columns the wave-rows kernel needs 328 registers (one wave per SIMD):
-    // it wins only when a launch holds 16 or more problems.
-    if (mmax <= 256) return dense_chunk<256, 1, 1, VEC, 1>(hp, k0, k1, p, res, s, cu);
-    if (mmax <= 512) return dense_chunk<256, 1, 1, VEC, 2>(hp, k0, k1, p, res, s, cu);
-    if (mmax <= 1024) return dense_chunk<256, 1, 1, VEC, 4>(hp, k0, k1, p, res, s, cu);
-    if (mmax <= 2048)
-        return k1 - k0 >= 16 ? dense_chunk<256, 2, 1, VEC, 8>(hp, k0, k1, p, res, s, cu)
-                             : dense_chunk<512, 1, 4, VEC>(hp, k0, k1, p, res, s, cu);
-    if (mmax <= 4096) return dense_chunk<1024, 1, 2, VEC>(hp, k0, k1, p, res, s, cu);
-    return dense_chunk<1024, 2, 1, VEC>(hp, k0, k1, p, res, s, cu);
+    // it wins only when a launch holds 16 or more problems (never a traced one).
+    if (mmax <= 256) return dense_chunk<256, 1, 1, VEC, 1, TR>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 512) return dense_chunk<256, 1, 1, VEC, 2, TR>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 1024) return dense_chunk<256, 1, 1, VEC, 4, TR>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 2048) {
+        if constexpr (!TR)
+            if (k1 - k0 >= 16) return dense_chunk<256, 2, 1, VEC, 8>(hp, k0, k1, p, res, s, cu);
+        return dense_chunk<512, 1, 4, VEC, 0, TR>(hp, k0, k1, p, res, s, cu);
+    }
+    if (mmax <= 4096) return dense_chunk<1024, 1, 2, VEC, 0, TR>(hp, k0, k1, p, res, s, cu);
+    return dense_chunk<1024, 2, 1, VEC, 0, TR>(hp, k0, k1, p, res, s, cu);
+}
+
+// A launch with the per-step trace holds one problem (the batch entry points
+// refuse a trace for several) and runs the traced instantiation.
+template <bool VEC>
+accsk_status dense_chunk_cfg(long long mmax, const std::vector<HostProb> &hp, int k0, int k1,
+                             const accsk_params *p, accsk_result *res, hipStream_t s, int cu) {
+    if (p->err_trace && p->trace_len > 0 && k1 - k0 == 1)
+        return dense_chunk_cfg_t<VEC, true>(mmax, hp, k0, k1, p, res, s, cu);
+    return dense_chunk_cfg_t<VEC, false>(mmax, hp, k0, k1, p, res, s, cu);
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -1304,6 +1320,36 @@ accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const 
         if (st != ACCSK_OK) return st;
         k0 = k1;
     }
+    return ACCSK_OK;
+}
+
+size_t accsk_tiled_workspace_bound(int64_t n, int64_t m, int cu);
+size_t accsk_small_workspace_bound(int64_t count);
+
+// Upper bound of the workspace of the FP64 evaluation pass (run_eval) on n x m.
+static size_t eval_workspace_bound(long long m) { return (size_t)(64 * m + 3 * 1024 + m) * 8 + 256; }
+
+extern "C" accsk_status accsk_workspace_bytes(int64_t n, int64_t m, int64_t count, size_t *bytes) {
+    using namespace accsk;
+    if (!bytes || count < 1) return ACCSK_INVALID_ARG;
+    if (n < 1 || m < 1) return ACCSK_SHAPE;
+    const int cu = device_cu_count();
+    if (cu <= 0) return ACCSK_HIP_ERROR;
+    // one-workgroup launches (+ the FP64 re-evaluation of a single problem)
+    size_t b = accsk_small_workspace_bound(count) + (size_t)(n + m + 8) * 8 + eval_workspace_bound(m);
+    if (m <= 8192) {
+        // one cooperative launch holds k <= min(count, CUs) problems with k * gp <= 2 CUs
+        const size_t k = (size_t)std::min<int64_t>(count, cu), G = 2 * (size_t)cu;
+        size_t d = align_up(sizeof(DenseArgs) * k) + align_up(sizeof(DevResult) * k) + align_up(64 * k) +
+                   align_up(64 * k) + align_up(256 * k);
+        d += k * (align_up(4 * (size_t)n * 8) + align_up(3 * (size_t)m * 8) + 3 * 256);
+        d += G * (size_t)m * (4 + 16) + (2 * G * kNS + G) * 8 + 2 * k * 256;
+        d += eval_workspace_bound(m);  // allocated while the launch's workspace is still held
+        b = std::max(b, d);
+    }
+    // tiled solver: m > 8192, or a problem whose row blocks do not fit on chip
+    b = std::max(b, accsk_tiled_workspace_bound(n, m, cu));
+    *bytes = b;
     return ACCSK_OK;
 }
 

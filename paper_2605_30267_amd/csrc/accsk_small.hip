@@ -184,3 +184,9 @@ extern "C" accsk_status accsk_solve_batch_strided(const float *C, int64_t batch,
                                          g_out + k * m, eps ? eps[k] : p->eps};
     return accsk_solve_batch(probs.data(), batch, p, res, stream);
 }
+
+// Upper bound of the workspace of one-workgroup launches over `count` problems
+// (descriptors and result records).
+size_t accsk_small_workspace_bound(int64_t count) {
+    return sizeof(SmallProb) * (size_t)count + sizeof(DevResult) * (size_t)count + 512;
+}

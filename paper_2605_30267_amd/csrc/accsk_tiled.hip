@@ -83,8 +83,6 @@ struct TiledArgs {
     double eps, tol, tol_stop, mu0;
     long long max_iter, m0;
     int method, w_rule, flags;
-    double *trace;  // optional per-step error trace
-    long long trace_len;
 };
 
 __device__ double tblock_sum(double v, double *red) {
@@ -179,8 +177,11 @@ __device__ __forceinline__ double readlane63_f64(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int D>
-__global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__ pa) {
+// TR: write the per-step error trace (trace / trace_len).  A separate
+// instantiation, so that untraced solves carry no trace code at all.
+template <int D, bool TR = false>
+__global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__ pa, double *__restrict__ trace,
+                                                   long long trace_len) {
     using Cf = TCfg<D>;
     constexpr int RW = Cf::RW, CH = Cf::CH, CPL = Cf::CPL, RG = Cf::RG, DD = Cf::DD;
     const TiledArgs A = *pa;
@@ -562,7 +563,9 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         if (status != ACCSK_OK) break;
 
         err = tot[2];
-        if (bid == 0 && tid == 0 && A.trace && steps + 1 <= A.trace_len) xstore(&A.trace[steps], err);
+        if constexpr (TR) {
+            if (bid == 0 && tid == 0 && steps < trace_len) xstore(&trace[steps], err);
+        }
         const double mean = tot[1] / (double)m;
         last_mass = tot[3];
         last_xb2 = tot[4];
@@ -686,13 +689,13 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-template <int D>
+template <int D, bool TR>
 accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res, hipStream_t s) {
     int dev = 0, cu = 0, occ = 0;
     ACCSK_HIP_TRY(hipGetDevice(&dev));
     ACCSK_HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
     const size_t lds = tiled_lds_bytes<D>();
-    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tiled_solve<D>, kTT, lds));
+    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tiled_solve<D, TR>, kTT, lds));
     if (occ < 1) return ACCSK_SHAPE;
     const long long G = (long long)std::min(occ, 2) * cu;
     const size_t n = A.n, m = A.m;
@@ -739,8 +742,6 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     A.method = p->method;
     A.w_rule = p->w_rule;
     A.flags = p->flags;
-    A.trace = p->trace_len > 0 ? p->err_trace : nullptr;
-    A.trace_len = p->trace_len;
     TiledArgs *d_args = (TiledArgs *)(base + o_args);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
@@ -753,8 +754,10 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     }
     if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
     if (e == hipSuccess) {
-        void *kargs[] = {&d_args};
-        e = hipLaunchCooperativeKernel((const void *)tiled_solve<D>, dim3((unsigned)G), dim3(kTT), kargs, lds, s);
+        double *tr = TR ? p->err_trace : nullptr;
+        long long tl = TR ? p->trace_len : 0;
+        void *kargs[] = {&d_args, &tr, &tl};
+        e = hipLaunchCooperativeKernel((const void *)tiled_solve<D, TR>, dim3((unsigned)G), dim3(kTT), kargs, lds, s);
     }
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     DevResult hr{};
@@ -808,11 +811,22 @@ accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, cons
     A.g_out = g_out;
     A.eps = eps;
     accsk_status st;
-    if (!X) st = tiled_launch<0>(A, p, res, s);
-    else if (d <= 3) st = tiled_launch<3>(A, p, res, s);
-    else if (d <= 8) st = tiled_launch<8>(A, p, res, s);
-    else if (d <= 16) st = tiled_launch<16>(A, p, res, s);
+    const bool tr = p->err_trace && p->trace_len > 0;
+    if (!X) st = tr ? tiled_launch<0, true>(A, p, res, s) : tiled_launch<0, false>(A, p, res, s);
+    else if (d <= 3) st = tr ? tiled_launch<3, true>(A, p, res, s) : tiled_launch<3, false>(A, p, res, s);
+    else if (d <= 8) st = tr ? tiled_launch<8, true>(A, p, res, s) : tiled_launch<8, false>(A, p, res, s);
+    else if (d <= 16) st = tr ? tiled_launch<16, true>(A, p, res, s) : tiled_launch<16, false>(A, p, res, s);
     else st = ACCSK_SHAPE;
     if (st != ACCSK_OK) return st;
     return (accsk_status)res->status;
+}
+
+// Upper bound of the workspace one tiled solve of an n x m problem allocates
+// (at most two workgroups per CU).
+size_t accsk_tiled_workspace_bound(int64_t n, int64_t m, int cu) {
+    using namespace accsk;
+    const size_t G = 2 * (size_t)cu;
+    return align_up(sizeof(TiledArgs)) + align_up(sizeof(DevResult)) + align_up(64 * 8) + align_up(256) +
+           align_up(5 * (size_t)n * 8) + align_up(7 * (size_t)m * 8) + align_up(G * (size_t)m * 4) +
+           align_up(2 * G * (size_t)m * 8) + align_up((2 * G * kTNS + 2 * G) * 8);
 }

@@ -154,3 +154,11 @@ def test_host_validation_trace(lib):
     accsk._register_server(lib)
     h = ctypes.c_void_p()
     assert lib.accsk_server_create(1 << 20, 0, ctypes.byref(p), ctypes.byref(h)) == accsk.INVALID_ARG
+
+
+def test_host_validation_workspace_bytes(lib):
+    out = ctypes.c_size_t(0)
+    assert lib.accsk_workspace_bytes(4, 4, 1, None) == accsk.INVALID_ARG
+    assert lib.accsk_workspace_bytes(4, 4, 0, ctypes.byref(out)) == accsk.INVALID_ARG
+    assert lib.accsk_workspace_bytes(0, 4, 1, ctypes.byref(out)) == accsk.SHAPE
+    assert lib.accsk_workspace_bytes(4, 0, 1, ctypes.byref(out)) == accsk.SHAPE

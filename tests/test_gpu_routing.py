@@ -146,3 +146,14 @@ def test_wave_rows_wide_batch(torch_gpu):
         _oracle_check(kinds[k], outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy(), res[k])
     for k in range(4, 16):
         assert torch.equal(outs[k][0], outs[k % 4][0]) and torch.equal(outs[k][1], outs[k % 4][1])
+
+
+def test_workspace_bound(torch_gpu):
+    """The workspace bound covers the cooperative launch's column partials and grows with the problem."""
+    from paper_2605_30267_amd import accsk
+    w1 = accsk.workspace_bytes(8192, 8192)
+    # one cooperative launch keeps one FP32 and two FP64 column partials per workgroup and column
+    assert w1 >= 256 * 8192 * (4 + 16)
+    assert accsk.workspace_bytes(16384, 8192) > w1 and accsk.workspace_bytes(8192, 8192, 64) >= w1
+    assert accsk.workspace_bytes(100, 20000) >= 512 * 20000 * (4 + 16)  # tiled: two workgroups per CU
+    assert accsk.workspace_bytes(64, 64, 1024) >= 1024 * 2 * 64
