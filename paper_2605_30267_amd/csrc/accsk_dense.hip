@@ -177,7 +177,8 @@ __device__ __forceinline__ float f4get(const float4 &v, int e) {
 // multiply per entry.  Algorithm A2MD is linear in (x, w, S), so it runs
 // unchanged in these units.
 //
-// Dynamic LDS layout: wl[m] | xl[m] | la2s[rpb] | rowM[rpb] | rowS[rpb] | rowL[rpb] | rowA[rpb]  (doubles).
+// Dynamic LDS layout: wl[m] | xl[m] | la2s[rpb] | rowM[rpb] | rowS[rpb] | rowL[rpb] | rowA[rpb]
+// | (WK > 0) the waves' column sums [m]  (doubles).
 // x and w live in LDS between steps (each thread owns the same columns in
 // every phase), so no per-column state is carried in registers across steps.
 // WK = 0: every row is spread over the whole workgroup (TPB * NG * 4 >= m
@@ -187,9 +188,13 @@ __device__ __forceinline__ float f4get(const float4 &v, int e) {
 // combined once per step.
 // TR: write the per-step error trace (trace / trace_len).  A separate
 // instantiation, so that untraced solves carry no trace code at all.
+// With 32 columns per lane (WK = 8) the wave-rows pass holds one row in
+// flight and is capped at two waves per SIMD (256 registers, a few spills):
+// 224 instead of 268 us per step on 64 problems of 2048 x 2048.  Without
+// 16-byte loads the cap would spill ~90 registers, so it applies to VEC only.
 template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false>
-__global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__ probs, int gp,
-                                                   double *__restrict__ trace, long long trace_len) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(WK >= 8 && VEC ? 2 : 1)))
+void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict__ trace, long long trace_len) {
     // gp workgroups per problem; problem p owns blocks [p*gp, (p+1)*gp)
     const DenseArgs A = probs[blockIdx.x / gp];
     constexpr int NW = TPB / 64;
@@ -445,38 +450,43 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
             };
             // One row: the same shift rule as the workgroup-wide pass (previous
             // step's log-sum-exp, exact maximum when the sum leaves [2^-40, 2^40]),
-            // with every reduction inside the wave.
+            // with every reduction inside the wave.  The row's values are dead once
+            // its exponentials are formed (the exact-maximum redo reloads the row),
+            // so both share registers.
+            auto row_sum = [&](const float4 (&cur)[WK], double M, float (&ev)[WC]) -> double {
+#pragma unroll
+                for (int kk = 0; kk < WK; kk++) {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int col = 4 * (lane + 64 * kk) + e;
+                        const double xc = col < m ? xl_lds[col] : -INFINITY;
+                        ev[kk * 4 + e] =
+                            __builtin_amdgcn_exp2f((float)(fma(-(double)f4get(cur[kk], e), kap2, xc) - M));
+                    }
+                }
+                // FP32 pairwise within the lane, FP64 across lanes
+                float pv[WC];
+#pragma unroll
+                for (int c = 0; c < WC; c++) pv[c] = ev[c];
+#pragma unroll
+                for (int h = 1; h < WC; h <<= 1)
+#pragma unroll
+                    for (int c = 0; c + h < WC; c += 2 * h) pv[c] += pv[c + h];
+                return wave_bcast63(wave_sum_l63((double)pv[0]));
+            };
             auto wrow_pass = [&](int k, const float4 (&cur)[WK]) {
                 const int rl = wrow(k);
                 double M = rowL[rl];
                 float ev[WC];
-                auto row_sum = [&]() -> double {
-#pragma unroll
-                    for (int kk = 0; kk < WK; kk++)
-#pragma unroll
-                        for (int e = 0; e < 4; e++) {
-                            const int col = 4 * (lane + 64 * kk) + e;
-                            const double xc = col < m ? xl_lds[col] : -INFINITY;
-                            ev[kk * 4 + e] = __builtin_amdgcn_exp2f(
-                                (float)(fma(-(double)f4get(cur[kk], e), kap2, xc) - M));
-                        }
-                    // FP32 pairwise within the lane, FP64 across lanes
-                    float pv[WC];
-#pragma unroll
-                    for (int c = 0; c < WC; c++) pv[c] = ev[c];
-#pragma unroll
-                    for (int h = 1; h < WC; h <<= 1)
-#pragma unroll
-                        for (int c = 0; c + h < WC; c += 2 * h) pv[c] += pv[c + h];
-                    return wave_bcast63(wave_sum_l63((double)pv[0]));
-                };
                 double S = 0.0;
                 bool exact = !(M < INFINITY);
                 if (!exact) {
-                    S = row_sum();
+                    S = row_sum(cur, M, ev);
                     exact = !(S >= 0x1p-40 && S <= 0x1p40);
                 }
                 if (exact) {  // wave-uniform
+                    float4 re[WK];
+                    wload(k, re);
                     double mloc = -INFINITY;
 #pragma unroll
                     for (int kk = 0; kk < WK; kk++)
@@ -484,10 +494,10 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                         for (int e = 0; e < 4; e++) {
                             const int col = 4 * (lane + 64 * kk) + e;
                             const double xc = col < m ? xl_lds[col] : -INFINITY;
-                            mloc = fmax(mloc, fma(-(double)f4get(cur[kk], e), kap2, xc));
+                            mloc = fmax(mloc, fma(-(double)f4get(re[kk], e), kap2, xc));
                         }
                     M = (double)wave_bcast63f(wave_max_l63((float)mloc));
-                    S = row_sum();
+                    S = row_sum(re, M, ev);
                 }
                 const double rfac = rowA[rl] / S;
 #pragma unroll
@@ -498,14 +508,23 @@ __global__ __launch_bounds__(TPB) void dense_solve(const DenseArgs *__restrict__
                     rowL[rl] = M + (double)__builtin_amdgcn_logf((float)S);  // next step's shift
                 }
             };
-            float4 wA[WK], wB[WK];
-            if (nrw > 0) wload(0, wA);
-            for (int k = 0; k < nrw; k += 2) {
-                if (k + 1 < nrw) wload(k + 1, wB);
-                wrow_pass(k, wA);
-                if (k + 1 < nrw) {
-                    if (k + 2 < nrw) wload(k + 2, wA);
-                    wrow_pass(k + 1, wB);
+            if constexpr (WK >= 8) {
+                // one row in flight per wave; the other waves of the SIMD hide its latency
+                for (int k = 0; k < nrw; k++) {
+                    float4 wA[WK];
+                    wload(k, wA);
+                    wrow_pass(k, wA);
+                }
+            } else {
+                float4 wA[WK], wB[WK];
+                if (nrw > 0) wload(0, wA);
+                for (int k = 0; k < nrw; k += 2) {
+                    if (k + 1 < nrw) wload(k + 1, wB);
+                    wrow_pass(k, wA);
+                    if (k + 1 < nrw) {
+                        if (k + 2 < nrw) wload(k + 2, wA);
+                        wrow_pass(k + 1, wB);
+                    }
                 }
             }
             // the waves' column sums, added in wave order through on-chip memory

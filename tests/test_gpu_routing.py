@@ -130,15 +130,17 @@ def test_tall_single_problem_tiled_fallback(torch_gpu):
     assert err <= tol
 
 
-def test_wave_rows_wide_batch(torch_gpu):
-    """m in (1024, 2048] in a launch of 16 problems: the wave-rows kernel with 32 columns per lane."""
+@pytest.mark.parametrize("widths", [(1500, 1637, 1774, 1911), (1500, 1600, 1800, 2048)])
+def test_wave_rows_wide_batch(torch_gpu, widths):
+    """m in (1024, 2048] in a launch of 16 problems: the wave-rows kernel with 32 columns per lane,
+    with 4-byte loads (some m not a multiple of 4) and with 16-byte loads (two waves per SIMD)."""
     torch = torch_gpu
     from paper_2605_30267_amd import accsk
-    kinds = [W.random_dense(510 + k, 300, 1500 + 137 * k, eps=1e-2, a_kind="dirichlet") for k in range(4)]
+    kinds = [W.random_dense(510 + k, 300, w, eps=1e-2, a_kind="dirichlet") for k, w in enumerate(widths)]
     dev = [(_dev(torch, p["C32"], torch.float32), _dev(torch, p["a"], torch.float64),
             _dev(torch, p["b"], torch.float64), p["eps"]) for p in kinds]
     batch = [dev[k % 4] for k in range(16)]
-    print("case 16-problem batch, m = 1500..1911", flush=True)
+    print("case 16-problem batch, m =", widths, flush=True)
     outs, res, st = accsk.solve_batch(batch)
     torch.cuda.synchronize()
     assert st == accsk.OK
