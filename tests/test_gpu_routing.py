@@ -159,3 +159,17 @@ def test_workspace_bound(torch_gpu):
     assert accsk.workspace_bytes(16384, 8192) > w1 and accsk.workspace_bytes(8192, 8192, 64) >= w1
     assert accsk.workspace_bytes(100, 20000) >= 512 * 20000 * (4 + 16)  # tiled: two workgroups per CU
     assert accsk.workspace_bytes(64, 64, 1024) >= 1024 * 2 * 64
+
+
+@pytest.mark.parametrize("n,m", [(100000, 1), (40000, 3), (1, 8192), (2, 5000), (70000, 200)])
+def test_extreme_aspect_ratios(torch_gpu, n, m):
+    """Very tall and very wide problems on the cooperative solver (most lanes' columns masked, or a
+    single row for the whole launch)."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    p = W.random_dense(520 + m, n, m, eps=1e-2, a_kind="dirichlet")
+    print("case aspect", n, m, flush=True)
+    f, g, r = accsk.solve_dense(_dev(torch, p["C32"], torch.float32), _dev(torch, p["a"], torch.float64),
+                                _dev(torch, p["b"], torch.float64), 1e-2)
+    torch.cuda.synchronize()
+    _oracle_check(p, f.cpu().numpy(), g.cpu().numpy(), r)
