@@ -171,3 +171,35 @@ def test_batch_strided_equals_list(torch_gpu):
     assert res["converged"][5] == 1 and ev["err"] <= 1e-6
     dp = accsk.default_params()
     check_stop(C64, p["a"], p["b"], p["eps"], 1e-6, O.ACC, int(res["iters"][5]), dp.mu0, dp.m0, dp.w_rule)
+
+
+def test_gaussian_batch_full_size(torch_gpu):
+    """The differentiable-loss workload at full size: 64 problems of 2048 x 2048 (N(0, I_64) points,
+    squared Euclidean cost / 128, uniform marginals, eps = 5e-3) in one launch, which runs the
+    wave-rows solver with 32 columns per lane.  Every problem: FP64 marginal error <= tol and the
+    dual value at its returned potentials; one problem: the stopping iterate against the oracle."""
+    from paper_2605_30267_amd import accsk
+    torch = torch_gpu
+    gb = W.gaussian_batch(seed=5, batch=64, n=2048, m=2048, d=64, eps=5e-3)
+    Cs = []
+    for k in range(64):
+        X, Y = gb["X"][k].astype(np.float64), gb["Y"][k].astype(np.float64)
+        D = (X * X).sum(1)[:, None] + (Y * Y).sum(1)[None, :] - 2.0 * X @ Y.T
+        Cs.append((np.maximum(D, 0.0) / gb["scale"]).astype(np.float32))
+    dev = [(_dev(torch, Cs[k], torch.float32), _dev(torch, gb["a"][k], torch.float64),
+            _dev(torch, gb["b"][k], torch.float64), gb["eps"]) for k in range(64)]
+    print("case gaussian batch 64 x 2048^2", flush=True)
+    outs, res, st = accsk.solve_batch(dev)
+    torch.cuda.synchronize()
+    assert st == accsk.OK
+    dp = accsk.default_params()
+    for k in range(64):
+        C = Cs[k].astype(np.float64)
+        f, g = outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy()
+        ev = O.evaluate(C, gb["eps"], gb["a"][k], gb["b"][k], f, g)
+        assert res[k]["converged"] == 1 and ev["err"] <= 1e-6, (k, ev["err"])
+        assert abs(res[k]["eot_value"] - ev["dual"]) <= 1e-12 * max(1.0, abs(ev["dual"]))
+        if k == 37:
+            print("  problem", k, "It", res[k]["iters"], "err", ev["err"], flush=True)
+            check_stop(C, gb["a"][k], gb["b"][k], gb["eps"], 1e-6, O.ACC, res[k]["iters"], dp.mu0, dp.m0,
+                       dp.w_rule)
