@@ -471,6 +471,18 @@ def main():
     log("timed: %d solves in %.3f s, It %d, kernel avg %.3f ms, %.1f GB/s algorithmic, %.1f GB/s of C read"
         % (args.steps, dt, rs[0]["iters"], kms_tot / args.steps, achieved, physical))
 
+    # Measured read-stream bandwidth, outside the timed region: the references
+    # the read rate of C is compared with beside the published peak.  Over
+    # 1 GiB (four times the last-level cache) it is HBM's; re-reading C itself
+    # (the solve's footprint, about the cache's size) it includes what the
+    # cache keeps between passes.
+    sbuf = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    stream_gbps = accsk.read_bandwidth(sbuf, reps=10)
+    del sbuf
+    stream_c_gbps = accsk.read_bandwidth(C, reps=20)
+    log("read stream: %.1f GB/s over 1 GiB, %.1f GB/s re-reading C; C read by the solve at %.3f / %.3f of them"
+        % (stream_gbps, stream_c_gbps, physical / stream_gbps, physical / stream_c_gbps))
+
     context = {}
     if args.context:
         for eps in (1e-2, 1e-3, 1e-4):
@@ -541,7 +553,11 @@ def main():
                      "algorithmic_bytes_per_step": alg_per_step, "steps_per_launch": steps_tot / args.steps,
                      "avg_launch_ms": kms_tot / args.steps,
                      "reads_of_C_per_step": 1, "read_rate_GBps": physical,
-                     "read_frac": physical / HBM_PEAK_GBPS},
+                     "read_frac": physical / HBM_PEAK_GBPS,
+                     "measured_read_stream_GBps": stream_gbps,
+                     "read_frac_of_measured_stream": physical / stream_gbps,
+                     "measured_reread_of_C_GBps": stream_c_gbps,
+                     "read_frac_of_measured_reread": physical / stream_c_gbps},
         "cpu_baseline": cpu,
         "context": context,
         "colour_transfer": color,

@@ -129,6 +129,18 @@ const char *accsk_status_string(int status);
  */
 accsk_status accsk_workspace_bytes(int64_t n, int64_t m, int64_t count, size_t *bytes);
 
+/*
+ * Measured HBM read bandwidth (GB/s), the reference beside the published peak
+ * for kernels bound by reading HBM: a read-only stream kernel (grid-stride
+ * float4 loads, 4 to 16 in flight per thread) over the first `bytes` (rounded
+ * down to 16) of the device buffer buf (16-byte aligned), timed with HIP
+ * events over `reps` launches after one warm-up, in three launch shapes; the
+ * best rate is returned.  A buffer larger than the 256 MB last-level cache
+ * measures HBM; a smaller one re-read measures what the cache adds.  Not part
+ * of the solve.  Errors: INVALID_ARG, OOM, HIP_ERROR.
+ */
+accsk_status accsk_read_bandwidth(const void *buf, int64_t bytes, int32_t reps, double *gbps, void *stream);
+
 /* Library version string (static storage). */
 const char *accsk_version(void);
 

@@ -96,6 +96,8 @@ def lib():
         L.accsk_solve_batch_strided.restype = ctypes.c_int
         L.accsk_workspace_bytes.argtypes = [_i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)]
         L.accsk_workspace_bytes.restype = ctypes.c_int
+        L.accsk_read_bandwidth.argtypes = [_vp, _i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _vp]
+        L.accsk_read_bandwidth.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -227,6 +229,16 @@ def workspace_bytes(n, m, count=1):
     st = lib().accsk_workspace_bytes(int(n), int(m), int(count), ctypes.byref(out))
     if st != OK:
         raise AccskError(st, "accsk_workspace_bytes")
+    return out.value
+
+
+def read_bandwidth(buf, reps=10):
+    """Measured HBM read bandwidth (GB/s) of a read-only stream over the device tensor buf."""
+    out = ctypes.c_double(0.0)
+    st = lib().accsk_read_bandwidth(_ptr(buf), buf.numel() * buf.element_size(), int(reps), ctypes.byref(out),
+                                    _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_read_bandwidth")
     return out.value
 
 

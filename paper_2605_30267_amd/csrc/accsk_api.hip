@@ -38,3 +38,78 @@ extern "C" const char *accsk_status_string(int status) {
 }
 
 extern "C" const char *accsk_version(void) { return "accsk 0.1 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// Read-only stream: the measured HBM read bandwidth that kernels bound by
+// reading HBM are compared with.  Each thread sums float4 groups with a grid
+// stride, U loads in flight; one FP32 value per wave keeps the loads live.
+// The rate depends on the launch shape by up to 15 %, so the entry point
+// reports the best of three shapes.
+// ---------------------------------------------------------------------------
+namespace {
+template <int U, int TPB>
+__global__ __launch_bounds__(TPB) void read_stream(const float4 *__restrict__ p, long long n4,
+                                                   float *__restrict__ out) {
+    float acc = 0.f;
+    const long long stride = (long long)gridDim.x * TPB;
+    long long i = (long long)blockIdx.x * TPB + threadIdx.x;
+    for (; i + (U - 1) * stride < n4; i += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = p[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; u++) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    }
+    for (; i < n4; i += stride) {
+        const float4 v = p[i];
+        acc += (v.x + v.y) + (v.z + v.w);
+    }
+    acc = accsk::wave_sumf(acc);
+    if ((threadIdx.x & 63) == 0) out[blockIdx.x * (TPB / 64) + (threadIdx.x >> 6)] = acc;
+}
+
+// GB/s of `reps` launches of one shape after a warm-up launch; 0 on a HIP error.
+template <int U, int TPB>
+double time_read_stream(const float4 *p, long long n4, float *out, unsigned grid, int reps, hipStream_t s,
+                        hipEvent_t e0, hipEvent_t e1) {
+    hipLaunchKernelGGL((read_stream<U, TPB>), dim3(grid), dim3(TPB), 0, s, p, n4, out);
+    if (hipEventRecord(e0, s) != hipSuccess) return 0.0;
+    for (int r = 0; r < reps; r++) hipLaunchKernelGGL((read_stream<U, TPB>), dim3(grid), dim3(TPB), 0, s, p, n4, out);
+    float ms = 0.f;
+    if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess || !(ms > 0.f))
+        return 0.0;
+    return (double)(n4 * 16) * reps / (ms * 1e-3) / 1e9;
+}
+}  // namespace
+
+extern "C" accsk_status accsk_read_bandwidth(const void *buf, int64_t bytes, int32_t reps, double *gbps,
+                                             void *stream) {
+    if (!buf || !gbps || reps < 1 || bytes < 16 || (((uintptr_t)buf) & 15)) return ACCSK_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cu = 0;
+    ACCSK_HIP_TRY(hipGetDevice(&dev));
+    ACCSK_HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const long long n4 = bytes / 16;
+    const float4 *p = (const float4 *)buf;
+    // one FP32 value per wave of the largest grid: 32 cu blocks of 4 waves
+    const unsigned g1 = (unsigned)cu, g32 = (unsigned)(32 * cu);
+    float *out = nullptr;
+    if (hipMallocAsync((void **)&out, (size_t)g32 * 4 * sizeof(float), s) != hipSuccess) return ACCSK_OOM;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best = 0.0;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    if (ok) {
+        const double r0 = time_read_stream<4, 1024>(p, n4, out, g1, reps, s, e0, e1);
+        const double r1 = r0 > 0 ? time_read_stream<8, 256>(p, n4, out, g32, reps, s, e0, e1) : 0.0;
+        const double r2 = r1 > 0 ? time_read_stream<16, 256>(p, n4, out, g32, reps, s, e0, e1) : 0.0;
+        ok = r2 > 0;
+        best = r0 > r1 ? (r0 > r2 ? r0 : r2) : (r1 > r2 ? r1 : r2);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFreeAsync(out, s);
+    if (!ok) return ACCSK_HIP_ERROR;
+    *gbps = best;
+    return ACCSK_OK;
+}

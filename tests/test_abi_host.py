@@ -162,3 +162,13 @@ def test_host_validation_workspace_bytes(lib):
     assert lib.accsk_workspace_bytes(4, 4, 0, ctypes.byref(out)) == accsk.INVALID_ARG
     assert lib.accsk_workspace_bytes(0, 4, 1, ctypes.byref(out)) == accsk.SHAPE
     assert lib.accsk_workspace_bytes(4, 0, 1, ctypes.byref(out)) == accsk.SHAPE
+
+
+def test_host_validation_read_bandwidth(lib):
+    out = ctypes.c_double(0.0)
+    f = lib.accsk_read_bandwidth
+    assert f(None, 1 << 20, 1, ctypes.byref(out), None) == accsk.INVALID_ARG
+    assert f(4096, 1 << 20, 0, ctypes.byref(out), None) == accsk.INVALID_ARG
+    assert f(4096, 8, 1, ctypes.byref(out), None) == accsk.INVALID_ARG
+    assert f(4097, 1 << 20, 1, ctypes.byref(out), None) == accsk.INVALID_ARG
+    assert f(4096, 1 << 20, 1, None, None) == accsk.INVALID_ARG
