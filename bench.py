@@ -555,6 +555,7 @@ def main():
                      "reads_of_C_per_step": 1, "read_rate_GBps": physical,
                      "read_frac": physical / HBM_PEAK_GBPS,
                      "measured_read_stream_GBps": stream_gbps,
+                     "frac_of_measured_stream": achieved / stream_gbps,
                      "read_frac_of_measured_stream": physical / stream_gbps,
                      "measured_reread_of_C_GBps": stream_c_gbps,
                      "read_frac_of_measured_reread": physical / stream_c_gbps},

@@ -172,6 +172,15 @@ __device__ __forceinline__ void xstore(float *p, float v) {
 __device__ __forceinline__ void xstore(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Four floats to bytes [off, off + 16) of a raw buffer, with SC1 set: the
+// line is written through the XCD's L2 like xstore's, for per-block results
+// too large for single-word stores (column partials: with plain stores, the
+// barrier's write-back of 8 MB of dirty partials cost ~6 us per step).
+__device__ __forceinline__ void xstore4(__amdgpu_buffer_rsrc_t r, int off, float4 v) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    constexpr int kSC1 = 16;  // cache-policy operand of a raw buffer access: SC1
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, kSC1);
+}
 __device__ __forceinline__ float xload(const float *p) {
     return __hip_atomic_load(const_cast<float *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -549,8 +549,8 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                     colacc[k * 4 + e] = col < m ? cl[col] : 0.0;
                 }
         }
-        // per-block column sums: FP64-accumulated, rounded once to FP32, stored as
-        // full float4 groups (the barrier's L2 write-back flushes whole lines)
+        // per-block column sums: FP64-accumulated, rounded once to FP32, written
+        // through L2 (other XCDs read them after the barrier)
 #pragma unroll
         for (int k = 0; k < NG; k++) {
             const int c0 = 4 * (ctid + k * TPB);
@@ -558,12 +558,15 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
             const float4 v = make_float4((float)colacc[k * 4 + 0], (float)colacc[k * 4 + 1],
                                          (float)colacc[k * 4 + 2], (float)colacc[k * 4 + 3]);
             if (VEC && c0 + 3 < m) {
-                *reinterpret_cast<float4 *>(dst) = v;
+                // raw buffer over this block's partial row: stores past its end are dropped
+                const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(L.partf + (size_t)bid * m), (short)0, (int)(m * 4), 0x00020000);
+                xstore4(wrs, c0 * 4, v);
             } else {
-                if (c0 + 0 < m) dst[0] = v.x;
-                if (c0 + 1 < m) dst[1] = v.y;
-                if (c0 + 2 < m) dst[2] = v.z;
-                if (c0 + 3 < m) dst[3] = v.w;
+                if (c0 + 0 < m) xstore(dst + 0, v.x);
+                if (c0 + 1 < m) xstore(dst + 1, v.y);
+                if (c0 + 2 < m) xstore(dst + 2, v.z);
+                if (c0 + 3 < m) xstore(dst + 3, v.w);
             }
         }
         if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
@@ -681,7 +684,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                         c = dexp2(lc2);
                     }
                     const double sh = lnbj * kLog2e - lc2 + xj;  // (log b_j - ell_j) log2 e
-                    L.shat[j] = sh;
+                    xstore(&L.shat[j], sh);
                     aS += sh;
                     aE += fabs(c - bnj);
                     aC += c;

@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                     A.part[(size_t)bid * m + jc[p]] = acc[p];
                     A.partmax[(size_t)bid * m + jc[p]] = cmx[p];
                 } else {
-                    A.partf[(size_t)bid * m + jc[p]] = (float)acc[p];
+                    xstore(&A.partf[(size_t)bid * m + jc[p]], (float)acc[p]);
                 }
             }
         }
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
             if (steps > 1 && fval_rose(fval, fp)) incr++;
             if (err < A.tol_stop || it >= A.max_iter) stop = true;
             else {
-                for (long long j = j0 + tid; j < j1; j += kTT) A.xg[j] = A.shat[j] - mean;
+                for (long long j = j0 + tid; j < j1; j += kTT) xstore(&A.xg[j], A.shat[j] - mean);
                 it++;
             }
         } else {
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                 }
                 first = false;
                 const double inv = 1.0 / (1.0 + alpha);
-                for (long long j = j0 + tid; j < j1; j += kTT) A.xg[j] = (A.wg[j] + (A.shat[j] - mean)) * inv;
+                for (long long j = j0 + tid; j < j1; j += kTT) xstore(&A.xg[j], (A.wg[j] + (A.shat[j] - mean)) * inv);
             }
         }
         if (stop) break;
