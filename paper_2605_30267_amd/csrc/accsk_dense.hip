@@ -179,8 +179,9 @@ __device__ __forceinline__ float f4get(const float4 &v, int e) {
 //
 // Dynamic LDS layout: wl[m] | xl[m] | la2s[rpb] | rowM[rpb] | rowS[rpb] | rowL[rpb] | rowA[rpb]
 // | (WK > 0) the waves' column sums [m]  (doubles).
-// x and w live in LDS between steps (each thread owns the same columns in
-// every phase), so no per-column state is carried in registers across steps.
+// x and w live in LDS between steps (the strip pass and the update walk them
+// in different thread orders, with workgroup barriers between the phases), so
+// no per-column state is carried in registers across steps.
 // WK = 0: every row is spread over the whole workgroup (TPB * NG * 4 >= m
 // columns, RB rows per batch, row sums reduced across waves).  WK > 0: each
 // wave owns whole rows, lane l holding columns 4 (l + 64 k) + e for k < WK
@@ -741,6 +742,11 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
         if (status != ACCSK_OK) break;
 
         // ---------------- update (every block, identical) ----------------
+        // Elementwise over the m columns of x and w (on chip) and S(x): thread t
+        // takes columns t + TPB q, so a wave's LDS accesses are consecutive
+        // doubles.  (The strip layout, four adjacent columns per thread, puts
+        // lanes 32 bytes apart: an 8-way bank conflict on every access.)
+        auto ucol = [&](int q) -> long long { return (long long)ctid + (long long)TPB * q; };
         LoopState st = ls;  // uniform copy, live only in this phase
         st.err = tot[2];
         const double mean = tot[1] / (double)m;
@@ -765,7 +771,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                 for (int k = 0; k < NG; k++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        const long long col = 4ll * (ctid + k * TPB) + e;
+                        const long long col = ucol(k * 4 + e);
                         if (col < m) xl_lds[col] = L.shat[col] - mean;
                     }
                 st.it++;
@@ -778,7 +784,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
             for (int k = 0; k < NG; k++)
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    const long long col = 4ll * (ctid + k * TPB) + e;
+                    const long long col = ucol(k * 4 + e);
                     S[k * 4 + e] = (col < m) ? L.shat[col] - mean : 0.0;
                 }
             if (!st.first) {
@@ -787,7 +793,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                 for (int k = 0; k < NG; k++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        const long long col = 4ll * (ctid + k * TPB) + e;
+                        const long long col = ucol(k * 4 + e);
                         if (col < m) wl_lds[col] = (wl_lds[col] + c2 * xl_lds[col] + 2.0 * S[k * 4 + e]) * inv;
                     }
                 st.it++;
@@ -799,7 +805,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                         for (int k = 0; k < NG; k++)
 #pragma unroll
                             for (int e = 0; e < 4; e++) {
-                                const long long col = 4ll * (ctid + k * TPB) + e;
+                                const long long col = ucol(k * 4 + e);
                                 if (col < m) wl_lds[col] = st.alpha * xl_lds[col];
                             }
                         st.restarts++;
@@ -818,7 +824,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                         for (int k = 0; k < NG; k++)
 #pragma unroll
                             for (int e = 0; e < 4; e++) {
-                                const long long col = 4ll * (ctid + k * TPB) + e;
+                                const long long col = ucol(k * 4 + e);
                                 if (col < m) wl_lds[col] *= ratio;
                             }
                     }
@@ -833,7 +839,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                 for (int k = 0; k < NG; k++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        const long long col = 4ll * (ctid + k * TPB) + e;
+                        const long long col = ucol(k * 4 + e);
                         if (col < m) xl_lds[col] = (wl_lds[col] + S[k * 4 + e]) * inv;
                     }
             }
