@@ -746,7 +746,8 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
         // takes columns t + TPB q, so a wave's LDS accesses are consecutive
         // doubles.  (The strip layout, four adjacent columns per thread, puts
         // lanes 32 bytes apart: an 8-way bank conflict on every access.)
-        auto ucol = [&](int q) -> long long { return (long long)ctid + (long long)TPB * q; };
+        auto ucol = [&](int q) -> int { return ctid + TPB * q; };  // m <= TPB * NC <= 8192
+        const int mi = (int)m;
         LoopState st = ls;  // uniform copy, live only in this phase
         st.err = tot[2];
         const double mean = tot[1] / (double)m;
@@ -768,80 +769,62 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                 stop = true;
             } else {
 #pragma unroll
-                for (int k = 0; k < NG; k++)
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const long long col = ucol(k * 4 + e);
-                        if (col < m) xl_lds[col] = L.shat[col] - mean;
-                    }
+                for (int q = 0; q < NC; q++) {
+                    const int col = ucol(q);
+                    if (col < mi) xl_lds[col] = L.shat[col] - mean;
+                }
                 st.it++;
             }
         } else {
             // Algorithm A2MD: S is Sinkhorn(x) at the current x; the w update
             // below uses it as Sinkhorn(x_{k+1}) and the next x update reuses it.
-            double S[NC];
-#pragma unroll
-            for (int k = 0; k < NG; k++)
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const long long col = ucol(k * 4 + e);
-                    S[k * 4 + e] = (col < m) ? L.shat[col] - mean : 0.0;
-                }
-            if (!st.first) {
-                const double c2 = st.alpha * st.alpha - 2.0, inv = 1.0 / (1.0 + st.alpha);
-#pragma unroll
-                for (int k = 0; k < NG; k++)
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const long long col = ucol(k * 4 + e);
-                        if (col < m) wl_lds[col] = (wl_lds[col] + c2 * xl_lds[col] + 2.0 * S[k * 4 + e]) * inv;
-                    }
+            // The step's decisions are uniform, so they are taken first; then
+            // one pass over the thread's columns reads S, w and x once each.
+            const bool upd_w = !st.first;
+            const double alpha0 = st.alpha;
+            const double c2 = alpha0 * alpha0 - 2.0, inv_w = 1.0 / (1.0 + alpha0);
+            bool reset = false;  // safeguard: reset the extrapolation, w <- alpha x
+            if (upd_w) {
                 st.it++;
                 st.kin++;
                 if (fval_rose(fval, st.fprev)) {
                     st.incr++;
-                    if (A.restart) {  // safeguard: reset the extrapolation, w <- alpha x
-#pragma unroll
-                        for (int k = 0; k < NG; k++)
-#pragma unroll
-                            for (int e = 0; e < 4; e++) {
-                                const long long col = ucol(k * 4 + e);
-                                if (col < m) wl_lds[col] = st.alpha * xl_lds[col];
-                            }
+                    if (A.restart) {
+                        reset = true;
                         st.restarts++;
                     }
                 }
             }
+            double ratio = 1.0;  // w scale at a stage change (exact no-op otherwise)
             if (st.err < A.tol_stop || st.it >= A.max_iter) {
                 stop = true;
             } else {
                 if (!st.first && st.kin == st.mstage) {
                     // Algorithm A2MD-homotopy: mu <- mu/2, m <- floor(sqrt(2) m) + 1
                     const double mu_new = st.mu / 2.0;
-                    if (A.w_rule == ACCSK_W_Y_CONTINUOUS) {
-                        const double ratio = dsqrt(2.0 * mu_new) / st.alpha;
-#pragma unroll
-                        for (int k = 0; k < NG; k++)
-#pragma unroll
-                            for (int e = 0; e < 4; e++) {
-                                const long long col = ucol(k * 4 + e);
-                                if (col < m) wl_lds[col] *= ratio;
-                            }
-                    }
+                    if (A.w_rule == ACCSK_W_Y_CONTINUOUS) ratio = dsqrt(2.0 * mu_new) / st.alpha;
                     st.mu = mu_new;
                     st.alpha = dsqrt(2.0 * st.mu);
                     st.mstage = (long long)floor(1.4142135623730951 * (double)st.mstage) + 1;
                     st.kin = 0;
                 }
                 st.first = 0;
-                const double inv = 1.0 / (1.0 + st.alpha);
+            }
+            const double inv_x = 1.0 / (1.0 + st.alpha);
 #pragma unroll
-                for (int k = 0; k < NG; k++)
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const long long col = ucol(k * 4 + e);
-                        if (col < m) xl_lds[col] = (wl_lds[col] + S[k * 4 + e]) * inv;
+            for (int q = 0; q < NC; q++) {
+                const int col = ucol(q);
+                if (col < mi) {
+                    const double S = L.shat[col] - mean;
+                    double w = wl_lds[col];
+                    if (upd_w) {
+                        const double xv = xl_lds[col];
+                        w = reset ? alpha0 * xv : (w + c2 * xv + 2.0 * S) * inv_w;
                     }
+                    w *= ratio;
+                    wl_lds[col] = w;
+                    if (!stop) xl_lds[col] = (w + S) * inv_x;
+                }
             }
         }
         st.fprev = fval;
