@@ -257,6 +257,10 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
         rowL[r] = INFINITY;  // unknown: the first step takes the exact row maximum
         rowA[r] = dexp2(la2s[r] - A.gscal[0]);
     }
+    // max a, read after every combine: kept on chip (a load from global memory
+    // there would follow the barrier's cache invalidation and wait a full round trip)
+    __shared__ double maxa_lds;
+    if (tid == 0) maxa_lds = A.gscal[1];
     __syncthreads();
 
     // Loop-carried scalars (the same in every thread) stay in LDS between update
@@ -678,7 +682,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                     double lc2, c;  // log2 c_j and c_j, c_j = column sum of P at (u(x), x)
                     if (pass == 0) {
                         lc2 = La2 + dlog2(sc);
-                        c = sc * A.gscal[1];
+                        c = sc * maxa_lds;
                         if (sc < 0x1p-64) aFB += 1.0;
                     } else {
                         lc2 = pm + dlog2(sc) + xj;
@@ -699,7 +703,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                 // sum near 1 (the shift is the previous step's log-sum-exp)
                 double aU = 0.0;  // a_i = rowA_i max a: on-chip, no load after the barrier
                 for (int r = lane; r < nr; r += 64) aU += rowA[r] * (la2s[r] - rowL[r]);
-                aU = wave_sum(aU) * A.gscal[1];
+                aU = wave_sum(aU) * maxa_lds;
                 aS = wave_sum(aS);
                 aE = wave_sum(aE);
                 aC = wave_sum(aC);
