@@ -313,6 +313,77 @@ void oracle_eval(const double *C, int64_t n, int64_t m, double eps,
     free(col); free(rowsum); free(rowcost);
 }
 
+/*
+ * The cost entry of two points, formed in FP64 from its definition (Sec. 5):
+ * kind 0: ||x - y||^2 / scale (colour transfer), kind 1: (1 - <x, y>) / scale
+ * (word alignment, unit rows).
+ */
+static double point_cost(int kind, const double *x, const double *y, int64_t d, double scale)
+{
+    double s = 0.0;
+    if (kind == 0) {
+        for (int64_t k = 0; k < d; k++) {
+            double t = x[k] - y[k];
+            s += t * t;
+        }
+        return s / scale;
+    }
+    for (int64_t k = 0; k < d; k++) s += x[k] * y[k];
+    return (1.0 - s) / scale;
+}
+
+/*
+ * oracle_eval on a point-cloud cost that is never stored: every C_ij is
+ * formed from x_i and y_j when it is needed (once in the row pass, once in the
+ * column pass), so problems far larger than an n x m array fit.  Same outputs
+ * and definitions as oracle_eval (eq:P-from-dual, eq:l1tol, eq:dual-obj).
+ */
+void oracle_eval_points(int kind, const double *X, const double *Y, int64_t n, int64_t m, int64_t d,
+                        double scale, double eps, const double *a, const double *b, const double *f,
+                        const double *g, double *row_err, double *col_err, double *dual, double *cost,
+                        double *mass)
+{
+    double *col = (double *)malloc(sizeof(double) * (size_t)m);
+    double *rowsum = (double *)malloc(sizeof(double) * (size_t)n);
+    double *rowcost = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double rs = 0.0, rc = 0.0;
+        for (int64_t j = 0; j < m; j++) {
+            double c = point_cost(kind, X + i * d, Y + j * d, d, scale);
+            double p = exp((f[i] + g[j] - c) / eps);
+            rs += p;
+            rc += c * p;
+        }
+        rowsum[i] = rs;
+        rowcost[i] = rc;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < m; j++) {
+        double cs = 0.0;
+        for (int64_t i = 0; i < n; i++)
+            cs += exp((f[i] + g[j] - point_cost(kind, X + i * d, Y + j * d, d, scale)) / eps);
+        col[j] = cs;
+    }
+    double re = 0.0, ce = 0.0, fa = 0.0, gb = 0.0, tot = 0.0, cst = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        re += fabs(rowsum[i] - a[i]);
+        fa += f[i] * a[i];
+        tot += rowsum[i];
+        cst += rowcost[i];
+    }
+    for (int64_t j = 0; j < m; j++) {
+        ce += fabs(col[j] - b[j]);
+        gb += g[j] * b[j];
+    }
+    *row_err = re;
+    *col_err = ce;
+    *dual = fa + gb - eps * tot;
+    *cost = cst;
+    *mass = tot;
+    free(col); free(rowsum); free(rowcost);
+}
+
 /* Transport plan rows [row0, row0+rows): P_ij = exp((f_i + g_j - C_ij)/eps). */
 void oracle_plan(const double *C, int64_t n, int64_t m, double eps,
                  const double *f, const double *g, int64_t row0, int64_t rows, double *P)

@@ -6,8 +6,9 @@ the CPU-baseline leg of the benchmark do.
 
 Contents
 --------
-* ``solve`` / ``sstep`` / ``evaluate`` / ``plan`` / cost builders / point-cloud
-  gradients: thin wrappers around the plain C oracle (FP64 throughout).
+* ``solve`` / ``sstep`` / ``evaluate`` / ``evaluate_points`` / ``plan`` / cost
+  builders / point-cloud gradients: thin wrappers around the plain C oracle
+  (FP64 throughout).
 * ``scheme_xy``: a second, independent form of the accelerated iteration written
   with the explicit auxiliary sequence y of eq:scheme (Sec. 4) and the mirror
   map grad phi*(xi) = log(1 + xi./b) of Sec. 3, in numpy, for small problems.
@@ -76,6 +77,9 @@ def _load():
         lib.oracle_solve_ex.restype = ctypes.c_int
         lib.oracle_eval.argtypes = [_d, _i64, _i64, ctypes.c_double, _d, _d, _d, _d, _d, _d, _d, _d, _d]
         lib.oracle_eval.restype = None
+        lib.oracle_eval_points.argtypes = [ctypes.c_int, _d, _d, _i64, _i64, _i64, ctypes.c_double,
+                                           ctypes.c_double, _d, _d, _d, _d, _d, _d, _d, _d, _d]
+        lib.oracle_eval_points.restype = None
         lib.oracle_plan.argtypes = [_d, _i64, _i64, ctypes.c_double, _d, _d, _i64, _i64, _d]
         lib.oracle_plan.restype = None
         lib.oracle_cost_sqeuclid.argtypes = [_d, _d, _i64, _i64, _i64, ctypes.c_double, _d]
@@ -176,6 +180,20 @@ def evaluate(C, eps, a, b, f, g):
     vals = [ctypes.c_double() for _ in range(5)]
     _load().oracle_eval(_p(C), n, m, float(eps), _p(a), _p(b), _p(f), _p(g),
                         *[ctypes.byref(v) for v in vals])
+    re, ce, dual, cost, mass = (v.value for v in vals)
+    return dict(row_err=re, col_err=ce, err=re + ce, dual=dual, cost=cost, mass=mass)
+
+
+def evaluate_points(kind, X, Y, scale, eps, a, b, f, g):
+    """``evaluate`` on the point-cloud cost (kind 0 squared Euclidean, 1 cosine,
+    divided by ``scale``), each entry formed in FP64 when used, nothing n x m stored."""
+    X, Y = _f64(X), _f64(Y)
+    n, d = X.shape
+    m = Y.shape[0]
+    a, b, f, g = _f64(a), _f64(b), _f64(f), _f64(g)
+    vals = [ctypes.c_double() for _ in range(5)]
+    _load().oracle_eval_points(int(kind), _p(X), _p(Y), n, m, d, float(scale), float(eps), _p(a), _p(b), _p(f),
+                               _p(g), *[ctypes.byref(v) for v in vals])
     re, ce, dual, cost, mass = (v.value for v in vals)
     return dict(row_err=re, col_err=ce, err=re + ce, dual=dual, cost=cost, mass=mass)
 

@@ -486,3 +486,104 @@ def test_stability_monitor_pins():
             # same optimum (gauge: g centred on both sides), as Sinkhorn's
             assert np.allclose(rst["g"], sk["g"], rtol=0, atol=1e-8 * eps * 1e3)
             assert np.allclose(rst["f"], sk["f"], rtol=0, atol=1e-8 * eps * 1e3)
+
+
+# ---------------------------------------------------------------------------
+# The checker itself: evaluate, plan, evaluate_points and the cost builders
+# ---------------------------------------------------------------------------
+
+def _constructed(seed, n, m, eps):
+    """A cost whose plan at chosen, non-optimal potentials (f, g) is a known matrix P0.
+
+    eq:P-from-dual gives P_ij = exp((f_i + g_j - C_ij)/eps); choosing
+    C_ij = f_i + g_j - eps log P0_ij makes the plan at (f, g) equal P0, so its
+    marginals, mass and <C,P> follow from P0 by plain sums, with no exponential.
+    P0's row and column sums straddle a and b (mixed-sign residuals) and its
+    mass is not 1, so a dropped absolute value, a swapped marginal or a wrong
+    exponent sign changes the result.
+    """
+    r = _rng(seed)
+    P0 = r.uniform(0.2, 1.8, size=(n, m)) / (n * m) * 1.3
+    a = r.dirichlet(np.ones(n))
+    b = r.dirichlet(np.ones(m))
+    f = r.normal(0.0, 0.3, n)
+    g = r.normal(0.0, 0.3, m)
+    C = f[:, None] + g[None, :] - eps * np.log(P0)
+    return C, a, b, f, g, P0
+
+
+@pytest.mark.parametrize("seed,n,m,eps", [(201, 9, 6, 0.7), (202, 5, 13, 0.05), (203, 31, 17, 2.0)])
+def test_evaluate_on_constructed_plan(seed, n, m, eps):
+    """oracle evaluate/plan at potentials that are not optimal, against P0's own sums."""
+    C, a, b, f, g, P0 = _constructed(seed, n, m, eps)
+    rs, cs = P0.sum(1), P0.sum(0)
+    assert np.any(rs > a) and np.any(rs < a) and np.any(cs > b) and np.any(cs < b)
+    ev = O.evaluate(C, eps, a, b, f, g)
+    assert ev["row_err"] == pytest.approx(np.abs(rs - a).sum(), rel=1e-12)
+    assert ev["col_err"] == pytest.approx(np.abs(cs - b).sum(), rel=1e-12)
+    assert ev["err"] == pytest.approx(ev["row_err"] + ev["col_err"], rel=1e-15)
+    assert ev["mass"] == pytest.approx(P0.sum(), rel=1e-12)
+    assert abs(ev["mass"] - 1.0) > 0.05
+    assert ev["cost"] == pytest.approx((C * P0).sum(), rel=1e-11, abs=1e-13)
+    assert ev["dual"] == pytest.approx(f @ a + g @ b - eps * P0.sum(), rel=1e-11, abs=1e-13)
+    np.testing.assert_allclose(O.plan(C, eps, f, g), P0, rtol=1e-12)
+    np.testing.assert_allclose(O.plan(C, eps, f, g, row0=2, rows=3), P0[2:5], rtol=1e-12)
+
+
+def test_evaluate_at_the_optimum_of_a_separable_cost():
+    """Separable cost C_ij = alpha_i + beta_j: the optimal potentials are known in
+    closed form, f_i = alpha_i + eps log a_i + c and g_j = beta_j + eps log b_j - c
+    (eq:P-from-dual with P = a b^T), so both marginal errors are 0 and the mass is 1."""
+    r = _rng(204)
+    n, m, eps = 8, 11, 0.3
+    al, be = r.uniform(0, 1, n), r.uniform(0, 1, m)
+    a, b = r.dirichlet(np.ones(n)), r.dirichlet(np.ones(m))
+    C = al[:, None] + be[None, :]
+    f = al + eps * np.log(a) + 0.37
+    g = be + eps * np.log(b) - 0.37
+    ev = O.evaluate(C, eps, a, b, f, g)
+    assert ev["row_err"] < 1e-14 and ev["col_err"] < 1e-14
+    assert ev["mass"] == pytest.approx(1.0, abs=1e-14)
+    ab = np.outer(a, b)
+    assert ev["dual"] == pytest.approx(al @ a + be @ b + eps * np.sum(ab * (np.log(ab) - 1.0)), abs=1e-13)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_cost_points_against_scipy(kind):
+    """Sec. 5 costs against scipy's pairwise distances (a separate library routine)."""
+    from scipy.spatial.distance import cdist
+    r = _rng(205 + kind)
+    X, Y = r.normal(size=(23, 7)), r.normal(size=(19, 7))
+    if kind == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+        ref = cdist(X, Y, "cosine") / 3.0  # 1 - x.y/(|x||y|) with unit rows
+    else:
+        ref = cdist(X, Y, "sqeuclidean") / 3.0
+    np.testing.assert_allclose(O.cost_points(kind, X, Y, 3.0), ref, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_evaluate_points_against_stored_cost(kind):
+    """evaluate_points forms each entry itself; on scipy's stored cost, evaluate
+    (pinned above by construction) must give the same five values."""
+    from scipy.spatial.distance import cdist
+    r = _rng(207 + kind)
+    n, m, d, s, eps = 37, 29, 5, 2.5, 0.08
+    X, Y = r.uniform(size=(n, d)), r.uniform(size=(m, d))
+    if kind == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+        C = cdist(X, Y, "cosine") / s
+    else:
+        C = cdist(X, Y, "sqeuclidean") / s
+    a, b = r.dirichlet(np.ones(n)), r.dirichlet(np.ones(m))
+    f, g = r.normal(0, 0.02, n), r.normal(0, 0.02, m)
+    ep = O.evaluate_points(kind, X, Y, s, eps, a, b, f, g)
+    ev = O.evaluate(C, eps, a, b, f, g)
+    for k in ("row_err", "col_err", "dual", "cost", "mass"):
+        assert ep[k] == pytest.approx(ev[k], rel=1e-11, abs=1e-14), k
+    # and at an optimum: both errors vanish on the solved problem
+    out = O.solve(C, a, b, eps, tol=1e-12, method=O.SINKHORN, max_iter=100000)
+    ep = O.evaluate_points(kind, X, Y, s, eps, a, b, out["f"], out["g"])
+    assert ep["err"] < 1e-11
