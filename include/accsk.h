@@ -378,6 +378,16 @@ accsk_status accsk_server_poll(accsk_server *srv, uint64_t ticket, accsk_result 
 /* info[5]: worker workgroups, waiting requests, requests in flight, kernel launches, free arena bytes. */
 accsk_status accsk_server_info(accsk_server *srv, int64_t *info);
 
+/*
+ * Admission by HBM footprint, counted since the server was created.
+ * stats[6]: requests that waited for arena space (a first-fit search over the
+ * free blocks found none large enough for their n x ceil4(m) FP32 cost), failed
+ * first-fit searches in total, requests admitted ahead of an earlier waiting
+ * request that did not fit, peak arena bytes in use, peak requests in flight,
+ * arena size (hbm_budget).  INVALID_ARG for NULL arguments.
+ */
+accsk_status accsk_server_admission(accsk_server *srv, int64_t *stats);
+
 /* Stops the persistent kernel once the requests in flight have finished, and frees the server. */
 accsk_status accsk_server_destroy(accsk_server *srv);
 

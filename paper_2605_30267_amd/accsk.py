@@ -590,6 +590,8 @@ def _register_server(L):
     L.accsk_server_poll.restype = ctypes.c_int
     L.accsk_server_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
     L.accsk_server_info.restype = ctypes.c_int
+    L.accsk_server_admission.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+    L.accsk_server_admission.restype = ctypes.c_int
     L.accsk_server_destroy.argtypes = [_vp]
     L.accsk_server_destroy.restype = ctypes.c_int
     L.accsk_clock_seconds.argtypes = []
@@ -680,6 +682,15 @@ class Server:
         if st != OK:
             raise AccskError(st, "accsk_server_info")
         return dict(workers=v[0], waiting=v[1], in_flight=v[2], launches=v[3], free_bytes=v[4])
+
+    def admission(self):
+        """Admission-by-footprint counters (see accsk_server_admission)."""
+        v = (ctypes.c_int64 * 6)()
+        st = self._L.accsk_server_admission(self._h, v)
+        if st != OK:
+            raise AccskError(st, "accsk_server_admission")
+        return dict(space_waited=v[0], fit_failures=v[1], overtakes=v[2], peak_bytes_in_use=v[3],
+                    peak_in_flight=v[4], budget=v[5])
 
     def close(self):
         if getattr(self, "_h", None):

@@ -348,6 +348,7 @@ struct accsk_server {
         long long ring_idx = -1;
         accsk_result res{};
         double t_submit = 0, t_admit = 0, t_done = 0;
+        bool space_waited = false;  // a first-fit search found no arena block for it
     };
     std::mutex mu;
     std::condition_variable cv;
@@ -361,6 +362,11 @@ struct accsk_server {
     std::atomic<bool> quit{false};
     accsk_status fault = ACCSK_OK;
     long long launches = 0;
+    // admission by footprint: requests that waited for arena space, first-fit
+    // searches that failed, requests admitted ahead of an earlier one that did
+    // not fit, peak arena bytes in use and peak requests in flight
+    long long space_waited = 0, fit_failures = 0, overtakes = 0, peak_inflight = 0;
+    size_t in_use = 0, peak_in_use = 0;
 
     bool alloc(size_t bytes, size_t *off) {
         for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
@@ -422,6 +428,7 @@ struct accsk_server {
             r.state = 2;
             r.t_done = now_seconds();
             release(r.off, r.bytes);
+            in_use -= r.bytes;
             slot_ticket[slot] = 0;
             inflight_idx[k] = inflight_idx.back();
             inflight_idx.pop_back();
@@ -437,9 +444,17 @@ struct accsk_server {
             Rec &r = recs[*it];
             size_t off;
             if (!alloc(r.bytes, &off)) {
+                fit_failures++;
+                if (!r.space_waited) {
+                    r.space_waited = true;
+                    space_waited++;
+                }
                 ++it;
                 continue;
             }
+            if (it != waiting.begin()) overtakes++;  // an earlier request is still waiting for space
+            in_use += r.bytes;
+            peak_in_use = std::max(peak_in_use, in_use);
             r.off = off;
             r.state = 1;
             r.ring_idx = (long long)published;
@@ -466,6 +481,7 @@ struct accsk_server {
             memcpy(&ring->desc[slot], &D, sizeof(D));
             slot_ticket[slot] = *it;
             inflight_idx.push_back((long long)published);
+            peak_inflight = std::max(peak_inflight, (long long)inflight_idx.size());
             published++;
             any = true;
             it = waiting.erase(it);
@@ -635,6 +651,18 @@ extern "C" accsk_status accsk_server_info(accsk_server *s, int64_t *info) {
     size_t fr = 0;
     for (auto &kv : s->free_blocks) fr += kv.second;
     info[4] = (int64_t)fr;
+    return ACCSK_OK;
+}
+
+extern "C" accsk_status accsk_server_admission(accsk_server *s, int64_t *stats) {
+    if (!s || !stats) return ACCSK_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    stats[0] = s->space_waited;
+    stats[1] = s->fit_failures;
+    stats[2] = s->overtakes;
+    stats[3] = (int64_t)s->peak_in_use;
+    stats[4] = s->peak_inflight;
+    stats[5] = (int64_t)s->budget;
     return ACCSK_OK;
 }
 

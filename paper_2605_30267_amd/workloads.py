@@ -34,6 +34,9 @@ MUSE dictionary of Sec. 5 -- are not available, so these stand in for them):
                         marginals, cosine cost: the size of Sec. 5's
                         word-alignment table, with a known ground truth for the
                         top-1 / top-5 readout.
+* ``outlier_columns``   tests only: U[0, 0.5] costs with a few columns raised
+                        by 0.5, so that at small eps they get almost no mass at
+                        the start.
 """
 from __future__ import annotations
 
@@ -206,3 +209,18 @@ def random_dense(seed, n, m, eps=1e-2, a_kind="uniform"):
         b = rng.uniform(0.5, 1.5, size=m)
         a, b = a / a.sum(), b / b.sum()
     return dict(C32=C, a=a, b=b, eps=eps)
+
+
+def outlier_columns(seed, n, m, eps=1e-4, frac=0.02, lift=0.5):
+    """Test problem with columns no row reaches at the start: C ~ U[0, 0.5] as
+    float32, then a random `frac` of the columns raised by `lift`; marginals
+    U(0.5, 1.5) normalized.  Draw order: C, the raised columns, a, b.  At small
+    eps those columns receive almost no mass in the first steps (the degenerate
+    start the solvers' exact column pass handles)."""
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0.0, 0.5, size=(n, m))
+    cols = rng.choice(m, max(1, int(frac * m)), replace=False)
+    C[:, cols] += lift
+    a = rng.uniform(0.5, 1.5, size=n)
+    b = rng.uniform(0.5, 1.5, size=m)
+    return dict(C32=C.astype(np.float32), a=a / a.sum(), b=b / b.sum(), eps=eps, cols=np.sort(cols))

@@ -203,3 +203,57 @@ def test_gaussian_batch_full_size(torch_gpu):
             print("  problem", k, "It", res[k]["iters"], "err", ev["err"], flush=True)
             check_stop(C, gb["a"][k], gb["b"][k], gb["eps"], 1e-6, O.ACC, res[k]["iters"], dp.mu0, dp.m0,
                        dp.w_rule)
+
+
+def test_gaussian_batch_backward_full_size(torch_gpu):
+    """The differentiable-loss workload as the benchmark runs it: 64 problems of
+    2048 x 2048, d = 64, BF16x3 split cost, forward Acc-Sinkhorn, then the
+    envelope-theorem backward of all 64 in one call.
+
+    * At the GPU's potentials, dX and dY of problems 0 and 37 against the oracle's
+      envelope gradient on the exact FP64 cost: relative L2 error <= 1e-5 (FP32
+      exponentials of FP64 arguments, FP64 sums, FP32 output).
+    * The forward solved the split cost, whose entries differ from the exact ones
+      by |dC| <= 2^-20 (|x|^2 + |y|^2)/s; the FP64 marginal error of its
+      potentials on the exact cost is bounded by 2 max|dC|/eps.
+    * End to end on problem 0: GPU gradients against the oracle's gradients at
+      the oracle's own solution of the exact cost (same stop rule), relative L2
+      error <= 1e-3 (the precision target of the split cost)."""
+    from paper_2605_30267_amd import accsk
+    torch = torch_gpu
+    gb = W.gaussian_batch(seed=5, batch=64, n=2048, m=2048, d=64, eps=5e-3)
+    X, Y = _dev(torch, gb["X"], torch.float32), _dev(torch, gb["Y"], torch.float32)
+    a, b = _dev(torch, gb["a"], torch.float64), _dev(torch, gb["b"], torch.float64)
+    print("case gaussian batch backward 64 x 2048^2, split 3", flush=True)
+    f, g, res = accsk.solve_points(X, Y, a, b, gb["eps"], cost_scale=gb["scale"], split=3)
+    dX, dY, _, _ = accsk.backward_points(X, Y, a, b, f, g, gb["eps"], cost_scale=gb["scale"], marginals=False)
+    torch.cuda.synchronize()
+    assert all(r["converged"] == 1 for r in res)
+    s, eps = gb["scale"], gb["eps"]
+    for k in (0, 37):
+        Xk, Yk = gb["X"][k].astype(np.float64), gb["Y"][k].astype(np.float64)
+        fk, gk = f[k].cpu().numpy(), g[k].cpu().numpy()
+        ox, oy = O.grad_points(0, Xk, Yk, s, eps, fk, gk)
+        gx, gy = dX[k].cpu().numpy().astype(np.float64), dY[k].cpu().numpy().astype(np.float64)
+        ex = np.linalg.norm(gx - ox) / np.linalg.norm(ox)
+        ey = np.linalg.norm(gy - oy) / np.linalg.norm(oy)
+        ev = O.evaluate_points(0, Xk, Yk, s, eps, gb["a"][k] / gb["a"][k].sum(), gb["b"][k] / gb["b"][k].sum(),
+                               fk, gk)
+        B = ((Xk ** 2).sum(1)[:, None] + (Yk ** 2).sum(1)[None, :]).max() / s
+        bound = 2.0 * (2.0 ** -20) * B / eps
+        print("  problem", k, "grad rel err X %.3e Y %.3e" % (ex, ey), "FP64 err on the exact cost %.3e" % ev["err"],
+              "bound %.3e" % bound, flush=True)
+        assert ex <= 1e-5 and ey <= 1e-5
+        assert ev["err"] <= bound
+    # end to end: the oracle's own solution of problem 0 on the exact cost
+    dp = accsk.default_params()
+    X0, Y0 = gb["X"][0].astype(np.float64), gb["Y"][0].astype(np.float64)
+    C0 = O.cost_points(0, X0, Y0, s)
+    o = O.solve(C0, gb["a"][0], gb["b"][0], eps, tol=1e-6 * STOP, method=O.ACC, mu0=dp.mu0, m0=dp.m0,
+                w_rule=dp.w_rule)
+    ox, oy = O.grad_points(0, X0, Y0, s, eps, o["f"], o["g"])
+    ex = np.linalg.norm(dX[0].cpu().numpy() - ox) / np.linalg.norm(ox)
+    ey = np.linalg.norm(dY[0].cpu().numpy() - oy) / np.linalg.norm(oy)
+    print("  end to end, problem 0: oracle It", o["iters"], "GPU It", res[0]["iters"],
+          "grad rel err X %.3e Y %.3e" % (ex, ey), flush=True)
+    assert ex <= 1e-3 and ey <= 1e-3

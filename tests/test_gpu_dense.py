@@ -184,7 +184,23 @@ def test_plan_and_eval(torch_gpu):
         assert abs(ev[k] - evo[k]) <= 1e-12 * max(1.0, abs(evo[k]))
 
 
-@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+@pytest.mark.parametrize("m", [2048, 3000, 4097, 8192])
+def test_exact_column_pass_wide(torch_gpu, m):
+    """eps = 1e-4 with 2 % of the columns out of every row's reach at the start
+    (column sums near 2^-7000): the exact column pass runs in each workgroup-rows
+    instantiation of the cooperative solver (m = 2048: 512 threads, four rows per
+    batch; 3000: 1024 threads, two rows; 4097 and 8192: 1024 threads, two column
+    groups per thread, with and without 16-byte loads).  FP64 two-sided error of
+    the result <= tol, dual value, stopping iterate against the oracle."""
+    p = W.outlier_columns(51, 600, m, eps=1e-4)
+    print("case outlier columns 600 x", m, flush=True)
+    f, g, r, o = _solve_both(torch_gpu, p["C32"], p["a"], p["b"], 1e-4, 1e-6, 1)
+    print("  It", r["iters"], "fallback", r["fallback_steps"], "oracle It", o["iters"], flush=True)
+    _check(p["C32"], p["a"], p["b"], 1e-4, 1e-6, (f, g), r, o, "outlier%d" % m)
+    assert r["fallback_steps"] >= 1
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3, 1e-4])
 def test_gmm_full_size(torch_gpu, eps):
     """n = m = 8192: KKT in FP64, sampled exact row solves, dual value, both methods."""
     from paper_2605_30267_amd import accsk

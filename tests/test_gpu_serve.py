@@ -90,6 +90,48 @@ def test_serve_alone_vs_mixed(torch_gpu, budget):
     print("budget", budget, "saw waiting requests:", seen_wait, info, flush=True)
 
 
+def test_serve_admission_binds(torch_gpu):
+    """Admission by HBM footprint: an arena that holds one 256 x 256 cost
+    (256 KiB) plus one 96 x 160 cost (60 KiB), and five requests submitted at
+    once: big A, big B, small c, big D, small e (B and D sized like A).
+    A is admitted at once; B waits for A's block (its first-fit search fails),
+    the small c goes first into the remaining space; B is admitted only after A
+    completed and D only after B.  Each result is bitwise the one the request
+    gives alone, and the server's admission counters record the waits."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    rng = np.random.default_rng(26)
+
+    def req(n, m, eps):
+        X = W.unit_rows(rng, n, 300).astype(np.float32)
+        Y = W.unit_rows(rng, m, 300).astype(np.float32)
+        return dict(X=X, Y=Y, a=np.full(n, 1.0 / n), b=np.full(m, 1.0 / m), eps=eps)
+
+    big = [req(256, 256, 1e-3), req(256, 256, 3e-3), req(256, 256, 1e-3)]
+    small = [req(96, 160, 1e-2), req(96, 160, 3e-3)]
+    order = [big[0], big[1], small[0], big[2], small[1]]
+    budget = 256 * 256 * 4 + 96 * 160 * 4
+    with accsk.Server(hbm_budget=budget) as srv:
+        alone = [_run_all(torch, srv, [r])[0] for r in order]
+        st0 = srv.admission()
+        assert st0["space_waited"] == 0
+        tickets = [_submit(torch, srv, r) for r in order]
+        torch.cuda.synchronize()
+        outs = [srv.wait(t, timeout=120.0) for t in tickets]
+        st = srv.admission()
+    tA, tB, tc, tD, te = [o[3] for o in outs]  # (submit, admit, done) on the host clock
+    print("admission", st, flush=True)
+    print("  A admit %.6f done %.6f | B admit %.6f done %.6f | c admit %.6f | D admit %.6f"
+          % (tA[1], tA[2], tB[1], tB[2], tc[1], tD[1]), flush=True)
+    assert tB[1] >= tA[2] and tD[1] >= tB[2]  # each big one admitted after the previous big one completed
+    assert tc[1] < tB[1]  # the small request went ahead of the waiting big one
+    assert st["space_waited"] >= 2 and st["fit_failures"] >= 2 and st["overtakes"] >= 1
+    assert st["peak_bytes_in_use"] <= budget
+    for (f, g, res, _), (fa, ga, ra) in zip(outs, alone):
+        assert res["converged"] == 1 and res["iters"] == ra["iters"]
+        assert np.array_equal(f.cpu().numpy(), fa) and np.array_equal(g.cpu().numpy(), ga)
+
+
 @pytest.mark.parametrize("split", [0, 3])
 def test_serve_equals_batched_points(torch_gpu, split):
     torch = torch_gpu

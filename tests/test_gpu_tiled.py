@@ -90,8 +90,12 @@ def test_cost_max_points(torch_gpu, kind, n, m, d):
     assert abs(got - ref) <= 1e-15 * max(1.0, abs(ref))
 
 
-def test_color_transfer_full_size_sampled(torch_gpu):
-    """n = m = 32768 RGB points, eps = 1e-3, cost / exact max, formed on the fly."""
+def test_color_transfer_full_size(torch_gpu):
+    """n = m = 32768 RGB points, eps = 1e-3, cost / exact max, formed on the fly.
+
+    The FP64 oracle evaluates the returned potentials on the exact cost over all
+    2^30 entries (each formed from the points when used, nothing n x m stored):
+    two-sided L1 marginal error <= tol, and the dual value."""
     torch = torch_gpu
     from paper_2605_30267_amd import accsk
     p = W.color_points(seed=3, n=32768, m=32768, eps=1e-3)
@@ -107,21 +111,17 @@ def test_color_transfer_full_size_sampled(torch_gpu):
     f, g = f.cpu().numpy(), g.cpu().numpy()
     X, Y = p["X"].astype(np.float64), p["Y"].astype(np.float64)
     an, bn = p["a"] / p["a"].sum(), p["b"] / p["b"].sum()
+    ev = O.evaluate_points(0, X, Y, s, p["eps"], an, bn, f, g)
+    print("  FP64 on the exact cost: row err", ev["row_err"], "col err", ev["col_err"], "dual", ev["dual"],
+          flush=True)
+    assert ev["err"] <= 1e-6
+    assert abs(r["eot_value"] - ev["dual"]) <= 2e-7 * p["eps"] + 1e-12 * abs(ev["dual"])
     rng = np.random.default_rng(0)
     # sampled rows: the row solve is exact, so each row marginal matches a_i to FP32-exponential accuracy
-    for i in rng.choice(32768, 48, replace=False):
+    for i in rng.choice(32768, 16, replace=False):
         Ci = ((X[i] - Y) ** 2).sum(axis=1) / s
         ri = np.exp((f[i] + g - Ci) / p["eps"]).sum()
         assert abs(ri - an[i]) <= 1e-6 * an[i] + 1e-300
-    # sampled columns: sum_j |c_j - b_j| <= tol overall; each sampled column within tol
-    tot = 0.0
-    for j in rng.choice(32768, 48, replace=False):
-        Cj = ((X - Y[j]) ** 2).sum(axis=1) / s
-        cj = np.exp((f + g[j] - Cj) / p["eps"]).sum()
-        tot += abs(cj - bn[j])
-    assert tot <= 1e-6
-    # the dual value at the returned potentials is the EOT value: <f, a> + <g, b> - eps * mass, mass ~ 1
-    assert abs(r["eot_value"] - (f @ an + g @ bn - p["eps"])) <= 2e-6 * p["eps"]
 
 
 def test_tiled_errors_and_limits(torch_gpu):
