@@ -161,6 +161,28 @@ accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc
                                double *f_out, double *g_out, accsk_result *res, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops or harnesses that forbid hipMalloc): accsk_solve_dense with
+ * the same arguments, routing, kernels and results, but no device allocation
+ * by the library (no hipMalloc, hipMallocAsync or HIP events).  Its workspace
+ * is one fixed device array of ACCSK_NOALLOC_SCRATCH_BYTES per GPU, held from
+ * the library's load until the process ends; kernel_ms is then measured on the
+ * device clock.  Every call on one GPU uses that GPU's array, so calls whose
+ * work overlaps on one GPU (other streams, other host threads) race and must
+ * be serialized by the caller; work enqueued on one stream is ordered.
+ * Limits: m <= 8192, and a workspace (one workgroup or one cooperative launch
+ * of up to one workgroup per compute unit, plus the FP64 evaluation) within
+ * ACCSK_NOALLOC_SCRATCH_BYTES, e.g. n = m = 8192 or n up to about 100000 at
+ * m = 8192; larger problems, and problems whose row blocks do not fit on chip
+ * (which accsk_solve_dense hands to the tiled solver), return ACCSK_SHAPE
+ * before any work is enqueued.  The call blocks like accsk_solve_dense.
+ */
+#define ACCSK_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+accsk_status accsk_solve_dense_noalloc(const float *C, int64_t n, int64_t m, int64_t ldc,
+                                       const double *a, const double *b, const accsk_params *p,
+                                       double *f_out, double *g_out, accsk_result *res, void *stream);
+
+/*
  * Transport plan rows [row0, row0+rows) from potentials (eq:P-from-dual):
  * P_ij = exp((f_i + g_j - C_ij)/eps), written as FP32 to P (device,
  * rows x m, leading dimension ldp >= m).  f, g: device FP64 (full length).

@@ -83,6 +83,8 @@ def lib():
         L.accsk_solve_dense.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, ctypes.POINTER(Params), _vp, _vp,
                                         ctypes.POINTER(Result), _vp]
         L.accsk_solve_dense.restype = ctypes.c_int
+        L.accsk_solve_dense_noalloc.argtypes = L.accsk_solve_dense.argtypes
+        L.accsk_solve_dense_noalloc.restype = ctypes.c_int
         L.accsk_plan_dense.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _i64, _vp, _i64, _vp]
         L.accsk_plan_dense.restype = ctypes.c_int
         L.accsk_eval_dense.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _vp, _vp,
@@ -159,6 +161,20 @@ def solve_dense(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m
     a: float64 [n], b: float64 [m] (positive; normalized inside).
     trace=True adds result["trace"]: the L1 marginal error of every Sinkhorn step (numpy).
     """
+    return _solve_dense_call("accsk_solve_dense", C, a, b, eps, tol, method, max_iter, mu0, m0, w_rule, flags,
+                             f_out, g_out, raise_on_error, trace)
+
+
+def solve_dense_noalloc(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=None,
+                        w_rule=None, flags=0, f_out=None, g_out=None, raise_on_error=True, trace=False):
+    """solve_dense through accsk_solve_dense_noalloc: the library allocates no device memory (its
+    workspace is a fixed per-device array).  Pass f_out / g_out to avoid torch allocations too."""
+    return _solve_dense_call("accsk_solve_dense_noalloc", C, a, b, eps, tol, method, max_iter, mu0, m0, w_rule,
+                             flags, f_out, g_out, raise_on_error, trace)
+
+
+def _solve_dense_call(entry, C, a, b, eps, tol, method, max_iter, mu0, m0, w_rule, flags, f_out, g_out,
+                      raise_on_error, trace):
     import torch
     _check_dev(C, torch.float32, "C", 2)
     _check_dev(a, torch.float64, "a", 1)
@@ -176,10 +192,10 @@ def solve_dense(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m
                        m0=m0, w_rule=w_rule, flags=int(flags))
     tbuf = _trace_buffer(p, trace, max_iter, C.device)
     r = Result()
-    st = lib().accsk_solve_dense(_ptr(C), n, m, C.stride(0), _ptr(a), _ptr(b), ctypes.byref(p), _ptr(f_out),
-                                 _ptr(g_out), ctypes.byref(r), _stream_ptr())
+    st = getattr(lib(), entry)(_ptr(C), n, m, C.stride(0), _ptr(a), _ptr(b), ctypes.byref(p), _ptr(f_out),
+                               _ptr(g_out), ctypes.byref(r), _stream_ptr())
     if raise_on_error and st not in (OK, NOT_CONVERGED):
-        raise AccskError(st, "accsk_solve_dense")
+        raise AccskError(st, entry)
     d = r.to_dict()
     d["status"] = st
     if tbuf is not None:

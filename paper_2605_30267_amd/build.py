@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaccsk.so")
 ARCH = "gfx950"
 
-SOURCES = ["accsk_api.hip", "accsk_dense.hip", "accsk_small.hip", "accsk_points.hip", "accsk_serve.hip", "accsk_tiled.hip"]
+SOURCES = ["accsk_api.hip", "accsk_dense.hip", "accsk_small.hip", "accsk_points.hip", "accsk_serve.hip", "accsk_tiled.hip",
+           "accsk_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

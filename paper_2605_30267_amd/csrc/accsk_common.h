@@ -207,8 +207,69 @@ struct DevResult {
     double eot;
     double fval;
     double cost;
+    long long t0, t1;    // device wall clock (wall_clock64 ticks) at the start and end of the solve
     int converged;
     int status;
+};
+
+// Device wall clock (constant rate, hipDeviceAttributeWallClockRate kHz).
+__device__ __forceinline__ long long dev_clock() { return (long long)wall_clock64(); }
+
+// Milliseconds per wall_clock64 tick of the current device (0 if unknown).
+inline double wall_tick_ms() {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0.0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) return 0.0;
+    return 1.0 / (double)khz;
+}
+
+// Copies a device result record into the public one.  kms < 0: the solve's
+// duration is taken from the record's device clock stamps instead of events.
+inline void fill_result(accsk_result &o, const DevResult &r, double kms) {
+    o.iters = r.iters;
+    o.sinkhorn_steps = r.steps;
+    o.fallback_steps = r.fallback;
+    o.fval_increases = r.incr;
+    o.restarts = r.restarts;
+    o.marginal_err = r.err;
+    o.eot_value = r.eot;
+    o.transport_cost = r.cost;
+    o.dual_fval = r.fval;
+    if (kms < 0.0) {
+        const double tick = wall_tick_ms();
+        kms = (tick > 0.0 && r.t1 >= r.t0) ? (double)(r.t1 - r.t0) * tick : -1.0;
+    }
+    o.kernel_ms = kms;
+    o.converged = r.converged;
+    o.status = r.status;
+    if (r.status == ACCSK_OK && !r.converged) o.status = ACCSK_NOT_CONVERGED;
+}
+
+// Device workspace of one library call.  By default it is stream-ordered
+// (hipMallocAsync / hipFreeAsync on the call's stream).  Over a fixed region
+// (base != nullptr) it hands out 256-byte aligned slices in stack order and
+// allocates nothing; put() releases a slice and every slice taken after it.
+struct Workspace {
+    char *base = nullptr;
+    size_t cap = 0, top = 0;
+    bool fixed() const { return base != nullptr; }
+    hipError_t get(void **p, size_t bytes, hipStream_t s) {
+        if (!base) return hipMallocAsync(p, bytes, s);
+        const size_t b = (bytes + 255) & ~size_t(255);
+        if (b > cap - top) return hipErrorOutOfMemory;
+        *p = base + top;
+        top += b;
+        return hipSuccess;
+    }
+    void put(void *p, hipStream_t s) {
+        if (!p) return;
+        if (!base) {
+            (void)hipFreeAsync(p, s);
+            return;
+        }
+        char *c = (char *)p;
+        if (c >= base && c < base + top) top = (size_t)(c - base);
+    }
 };
 
 }  // namespace accsk

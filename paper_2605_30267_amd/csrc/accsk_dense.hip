@@ -133,10 +133,12 @@ __global__ __launch_bounds__(1024) void setup_marginals(const DenseArgs *__restr
         A.lnb[j] = log(v);
     }
     __syncthreads();
+    if (tid < 32) A.bar[tid] = 0ull;  // the grid barrier's counter and flag lines (256 bytes)
     if (tid == 0) {
         A.gscal[0] = mx;
         A.gscal[1] = exp2(mx);
         A.status[0] = (bad & 2) ? ACCSK_NONFINITE : ((bad & 1) ? ACCSK_INVALID_ARG : ACCSK_OK);
+        A.res->t0 = dev_clock();
     }
 }
 
@@ -217,6 +219,8 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
             r.fval = NAN;
             r.cost = NAN;
             r.status = A.status[0];
+            r.t0 = A.res->t0;
+            r.t1 = dev_clock();
             *A.res = r;
         }
         return;
@@ -877,6 +881,8 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
         r.cost = NAN;
         r.converged = (status == ACCSK_OK && fin.err < A.tol_stop) ? 1 : 0;
         r.status = status;
+        r.t0 = A.res->t0;
+        r.t1 = dev_clock();
         *A.res = r;
     }
 }
@@ -1041,12 +1047,12 @@ int device_cu_count() {
 
 accsk_status run_eval(const float *C, long long n, long long m, long long ldc, double eps, const double *a,
                       const double *b, const double *f, const double *g, double *out_dev, DevResult *res,
-                      hipStream_t s) {
+                      hipStream_t s, Workspace &ws) {
     const int G = (int)std::min<long long>(n, 1024);
     const int RS = (int)std::min<long long>(n, 64);
     double *buf = nullptr;
     const size_t bytes = ((size_t)RS * m + (size_t)G * 3 + m) * 8;
-    if (hipMallocAsync((void **)&buf, bytes, s) != hipSuccess) return ACCSK_OOM;
+    if (ws.get((void **)&buf, bytes, s) != hipSuccess) return ACCSK_OOM;
     double *colpart = buf, *rowscal = buf + (size_t)RS * m, *colerr = rowscal + (size_t)G * 3;
     hipLaunchKernelGGL(eval_rows, dim3(G), dim3(kEvalTPB), 0, s, C, n, m, ldc, 1.0 / eps, a, f, g, rowscal);
     hipLaunchKernelGGL(eval_colpart, dim3((unsigned)((m + kEvalTPB - 1) / kEvalTPB), RS), dim3(kEvalTPB), 0, s,
@@ -1056,7 +1062,7 @@ accsk_status run_eval(const float *C, long long n, long long m, long long ldc, d
     hipLaunchKernelGGL(eval_final, dim3(1), dim3(1024), 0, s, n, m, G, eps, a, b, f, g, rowscal, colerr,
                        out_dev, res);
     hipError_t e = hipGetLastError();
-    (void)hipFreeAsync(buf, s);
+    ws.put(buf, s);
     return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
 }
 
@@ -1070,10 +1076,11 @@ struct HostProb {
 };
 
 // Solves problems [k0, k1) of `hp` with one cooperative launch, gp workgroups
-// per problem.  Results go to res[k0..k1).
+// per problem.  Results go to res[k0..k1).  Over a fixed workspace region the
+// kernel time comes from the device clock (no events are created).
 template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false>
 accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const accsk_params *p,
-                         accsk_result *res, hipStream_t s, int num_cu) {
+                         accsk_result *res, hipStream_t s, int num_cu, Workspace &ws) {
     const int cnt = k1 - k0;
     long long nmax = 0, mmax = 0, nmin = 1LL << 62;
     for (int k = k0; k < k1; k++) {
@@ -1124,7 +1131,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         off = align_up(off + (2 * (size_t)gp * kNS + gp) * 8);  // bscal, uapart
     }
     char *base = nullptr;
-    if (hipMallocAsync((void **)&base, off, s) != hipSuccess) return ACCSK_OOM;
+    if (ws.get((void **)&base, off, s) != hipSuccess) return ACCSK_OOM;
     std::vector<DenseArgs> args(cnt);
     for (int q = 0; q < cnt; q++) {
         const HostProb &h = hp[k0 + q];
@@ -1176,10 +1183,12 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     }
     DenseArgs *d_args = (DenseArgs *)(base + o_args);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
-    if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+    if (!ws.fixed()) {
+        if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+        if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+    }
+    // (setup_marginals also zeroes each problem's barrier words)
     hipError_t e = hipMemcpyAsync(d_args, args.data(), sizeof(DenseArgs) * cnt, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(base + o_bar, 0, 256 * (size_t)cnt, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(setup_marginals, dim3(cnt), dim3(1024), 0, s, (const DenseArgs *)d_args);
         e = hipGetLastError();
@@ -1199,7 +1208,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         for (int q = 0; q < cnt && st == ACCSK_OK; q++) {
             const DenseArgs &A = args[q];
             // <C,P> and the dual value at the returned potentials, FP64, with normalized marginals
-            st = run_eval(A.C, A.n, A.m, A.ldc, A.eps, A.an, A.bn, A.f_out, A.g_out, A.gscal + 1, A.res, s);
+            st = run_eval(A.C, A.n, A.m, A.ldc, A.eps, A.an, A.bn, A.f_out, A.g_out, A.gscal + 1, A.res, s, ws);
         }
     }
     std::vector<DevResult> hr(cnt);
@@ -1212,56 +1221,40 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     if (st == ACCSK_OK && ev0 && ev1 && hipEventElapsedTime(&kms, ev0, ev1) != hipSuccess) kms = -1.f;
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
-    (void)hipFreeAsync(base, s);
+    ws.put(base, s);
     if (st != ACCSK_OK) return st;
-    for (int q = 0; q < cnt; q++) {
-        const DevResult &r = hr[q];
-        accsk_result &o = res[k0 + q];
-        o.iters = r.iters;
-        o.sinkhorn_steps = r.steps;
-        o.fallback_steps = r.fallback;
-        o.fval_increases = r.incr;
-        o.restarts = r.restarts;
-        o.marginal_err = r.err;
-        o.eot_value = r.eot;
-        o.transport_cost = r.cost;
-        o.dual_fval = r.fval;
-        o.kernel_ms = kms;
-        o.converged = r.converged;
-        o.status = r.status;
-        if (r.status == ACCSK_OK && !r.converged) o.status = ACCSK_NOT_CONVERGED;
-    }
+    for (int q = 0; q < cnt; q++) fill_result(res[k0 + q], hr[q], (double)kms);
     return ACCSK_OK;
 }
 
 template <bool VEC, bool TR>
 accsk_status dense_chunk_cfg_t(long long mmax, const std::vector<HostProb> &hp, int k0, int k1,
-                               const accsk_params *p, accsk_result *res, hipStream_t s, int cu) {
+                               const accsk_params *p, accsk_result *res, hipStream_t s, int cu, Workspace &ws) {
     // Up to 1024 columns each wave owns whole rows (4 to 16 columns per lane):
     // 20-34 % faster per step than rows spread over the workgroup, whose
     // cross-wave row reductions cost more than the row's arithmetic.  With
     // 2048 columns the wave-rows kernel needs 328 registers (one wave per SIMD):
     // it wins only when a launch holds 16 or more problems (never a traced one).
-    if (mmax <= 256) return dense_chunk<256, 1, 1, VEC, 1, TR>(hp, k0, k1, p, res, s, cu);
-    if (mmax <= 512) return dense_chunk<256, 1, 1, VEC, 2, TR>(hp, k0, k1, p, res, s, cu);
-    if (mmax <= 1024) return dense_chunk<256, 1, 1, VEC, 4, TR>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 256) return dense_chunk<256, 1, 1, VEC, 1, TR>(hp, k0, k1, p, res, s, cu, ws);
+    if (mmax <= 512) return dense_chunk<256, 1, 1, VEC, 2, TR>(hp, k0, k1, p, res, s, cu, ws);
+    if (mmax <= 1024) return dense_chunk<256, 1, 1, VEC, 4, TR>(hp, k0, k1, p, res, s, cu, ws);
     if (mmax <= 2048) {
         if constexpr (!TR)
-            if (k1 - k0 >= 16) return dense_chunk<256, 2, 1, VEC, 8>(hp, k0, k1, p, res, s, cu);
-        return dense_chunk<512, 1, 4, VEC, 0, TR>(hp, k0, k1, p, res, s, cu);
+            if (k1 - k0 >= 16) return dense_chunk<256, 2, 1, VEC, 8>(hp, k0, k1, p, res, s, cu, ws);
+        return dense_chunk<512, 1, 4, VEC, 0, TR>(hp, k0, k1, p, res, s, cu, ws);
     }
-    if (mmax <= 4096) return dense_chunk<1024, 1, 2, VEC, 0, TR>(hp, k0, k1, p, res, s, cu);
-    return dense_chunk<1024, 2, 1, VEC, 0, TR>(hp, k0, k1, p, res, s, cu);
+    if (mmax <= 4096) return dense_chunk<1024, 1, 2, VEC, 0, TR>(hp, k0, k1, p, res, s, cu, ws);
+    return dense_chunk<1024, 2, 1, VEC, 0, TR>(hp, k0, k1, p, res, s, cu, ws);
 }
 
 // A launch with the per-step trace holds one problem (the batch entry points
 // refuse a trace for several) and runs the traced instantiation.
 template <bool VEC>
 accsk_status dense_chunk_cfg(long long mmax, const std::vector<HostProb> &hp, int k0, int k1,
-                             const accsk_params *p, accsk_result *res, hipStream_t s, int cu) {
+                             const accsk_params *p, accsk_result *res, hipStream_t s, int cu, Workspace &ws) {
     if (p->err_trace && p->trace_len > 0 && k1 - k0 == 1)
-        return dense_chunk_cfg_t<VEC, true>(mmax, hp, k0, k1, p, res, s, cu);
-    return dense_chunk_cfg_t<VEC, false>(mmax, hp, k0, k1, p, res, s, cu);
+        return dense_chunk_cfg_t<VEC, true>(mmax, hp, k0, k1, p, res, s, cu, ws);
+    return dense_chunk_cfg_t<VEC, false>(mmax, hp, k0, k1, p, res, s, cu, ws);
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -1292,9 +1285,10 @@ accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, cons
                                hipStream_t s);
 
 // Persistent multi-problem path, also used by the batch entry point for
-// problems with more than 1024 columns.
+// problems with more than 1024 columns.  Over a fixed workspace region a
+// problem that would need the tiled solver is refused (SHAPE).
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                               accsk_result *res, hipStream_t s) {
+                               accsk_result *res, hipStream_t s, Workspace &ws) {
     using namespace accsk;
     const int cu = device_cu_count();
     if (cu <= 0) return ACCSK_HIP_ERROR;
@@ -1319,12 +1313,13 @@ accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const 
                 mmax = std::max(mmax, h.m);
                 vec = vec && (h.ldc % 4) == 0 && (h.m % 4) == 0 && (((uintptr_t)h.C) & 15) == 0;
             }
-            st = vec ? dense_chunk_cfg<true>(mmax, hp, (int)k0, (int)k1, p, res, s, cu)
-                     : dense_chunk_cfg<false>(mmax, hp, (int)k0, (int)k1, p, res, s, cu);
+            st = vec ? dense_chunk_cfg<true>(mmax, hp, (int)k0, (int)k1, p, res, s, cu, ws)
+                     : dense_chunk_cfg<false>(mmax, hp, (int)k0, (int)k1, p, res, s, cu, ws);
             if (st != ACCSK_SHAPE || k1 - k0 == 1) break;
             k1 = k0 + (k1 - k0) / 2;
         }
         if (st == ACCSK_SHAPE) {
+            if (ws.fixed()) return ACCSK_SHAPE;
             const HostProb &h = hp[(size_t)k0];
             st = accsk_tiled_solve(h.C, h.ldc, nullptr, nullptr, 0, 0, 1.0, h.n, h.m, h.a, h.b, p, h.eps, h.f, h.g,
                                    &res[k0], s);
@@ -1343,6 +1338,24 @@ size_t accsk_small_workspace_bound(int64_t count);
 
 // Upper bound of the workspace of the FP64 evaluation pass (run_eval) on n x m.
 static size_t eval_workspace_bound(long long m) { return (size_t)(64 * m + 3 * 1024 + m) * 8 + 256; }
+
+// Upper bound of the workspace accsk_solve_dense takes for one n x m problem
+// (m <= 8192) on its one-workgroup or cooperative route, slices rounded to
+// 256 bytes as Workspace hands them out; the tiled route is not counted.
+size_t accsk_dense_single_bound(int64_t n, int64_t m, int cu) {
+    using namespace accsk;
+    const size_t un = (size_t)n, um = (size_t)m;
+    const size_t eval = align_up(((size_t)std::min<int64_t>(n, 64) * um + (size_t)std::min<int64_t>(n, 1024) * 3 + um) * 8);
+    // one workgroup: descriptors and results, then (released) the FP64 re-evaluation
+    const size_t small = std::max(align_up(accsk_small_workspace_bound(1)), align_up((un + um + 8) * 8) + eval);
+    // cooperative launch of one problem, gp <= min(CUs, n) workgroups, plus the evaluation
+    const size_t gp = (size_t)std::max<int64_t>(1, std::min<int64_t>(cu, n));
+    const size_t coop = align_up(align_up(sizeof(DenseArgs)) + align_up(sizeof(DevResult)) + align_up(8 * 8) +
+                                 align_up(64) + align_up(256) + align_up(4 * un * 8) + align_up(3 * um * 8) +
+                                 align_up(gp * um * 4) + align_up(2 * gp * um * 8) + align_up((2 * gp * kNS + gp) * 8)) +
+                        eval;
+    return std::max(small, coop);
+}
 
 extern "C" accsk_status accsk_workspace_bytes(int64_t n, int64_t m, int64_t count, size_t *bytes) {
     using namespace accsk;
@@ -1368,9 +1381,22 @@ extern "C" accsk_status accsk_workspace_bytes(int64_t n, int64_t m, int64_t coun
     return ACCSK_OK;
 }
 
-extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc, const double *a,
-                                          const double *b, const accsk_params *p, double *f_out,
-                                          double *g_out, accsk_result *res, void *stream) {
+// Host validation of a single dense solve's parameters (eps included).
+accsk_status accsk_check_dense_params(const accsk_params *p) {
+    using namespace accsk;
+    if (!p || !finite_pos(p->eps)) return ACCSK_INVALID_ARG;
+    return check_params(p);
+}
+
+// Batch solve of accsk_small.hip with its workspace.
+accsk_status accsk_solve_batch_ws(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                                  accsk_result *res, void *stream, accsk::Workspace &ws);
+
+// accsk_solve_dense with its workspace.  Over a fixed region the tiled solver
+// (m > 8192, or row blocks too large for on-chip memory) is not used (SHAPE).
+accsk_status accsk_solve_dense_ws(const float *C, int64_t n, int64_t m, int64_t ldc, const double *a,
+                                  const double *b, const accsk_params *p, double *f_out, double *g_out,
+                                  accsk_result *res, void *stream, accsk::Workspace &ws) {
     using namespace accsk;
     if (res) {
         res->status = ACCSK_INVALID_ARG;
@@ -1382,6 +1408,7 @@ extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, 
     if (st != ACCSK_OK) return st;
     if (n < 1 || m < 1 || ldc < m) return ACCSK_SHAPE;
     if (m > 8192) {
+        if (ws.fixed()) return ACCSK_SHAPE;
         st = accsk_tiled_solve(C, ldc, nullptr, nullptr, 0, 0, 1.0, n, m, a, b, p, p->eps, f_out, g_out, res,
                                (hipStream_t)stream);
         return st;
@@ -1390,7 +1417,7 @@ extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, 
     // cooperating workgroups (or the tiled solver when its row blocks do not
     // fit on chip).
     accsk_problem q{C, n, m, ldc, a, b, f_out, g_out, p->eps};
-    st = accsk_solve_batch(&q, 1, p, res, stream);
+    st = accsk_solve_batch_ws(&q, 1, p, res, stream, ws);
     if ((st != ACCSK_OK && st != ACCSK_NOT_CONVERGED) || (p->flags & ACCSK_FLAG_NO_COST) ||
         !accsk_on_one_workgroup(n, m, 1))
         return st;
@@ -1398,22 +1425,29 @@ extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, 
     // re-evaluate both in FP64 at the returned potentials, as the other solvers do.
     hipStream_t s = (hipStream_t)stream;
     double *buf = nullptr;
-    if (hipMallocAsync((void **)&buf, (size_t)(n + m + 8) * 8, s) != hipSuccess) return ACCSK_OOM;
+    if (ws.get((void **)&buf, (size_t)(n + m + 8) * 8, s) != hipSuccess) return ACCSK_OOM;
     double *an = buf, *bn = buf + n, *out = buf + n + m;
     hipLaunchKernelGGL(normalize_pair, dim3(1), dim3(1024), 0, s, a, n, b, m, an, bn);
     accsk_status se = hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
-    if (se == ACCSK_OK) se = run_eval(C, n, m, ldc, p->eps, an, bn, f_out, g_out, out, nullptr, s);
+    if (se == ACCSK_OK) se = run_eval(C, n, m, ldc, p->eps, an, bn, f_out, g_out, out, nullptr, s, ws);
     double h[5] = {0, 0, 0, 0, 0};
     if (se == ACCSK_OK) {
         hipError_t e = hipMemcpyAsync(h, out, 5 * 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) se = ACCSK_HIP_ERROR;
     }
-    (void)hipFreeAsync(buf, s);
+    ws.put(buf, s);
     if (se != ACCSK_OK) return se;
     res->eot_value = h[2];
     res->transport_cost = h[3];
     return st;
+}
+
+extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc, const double *a,
+                                          const double *b, const accsk_params *p, double *f_out,
+                                          double *g_out, accsk_result *res, void *stream) {
+    accsk::Workspace ws;  // stream-ordered allocations
+    return accsk_solve_dense_ws(C, n, m, ldc, a, b, p, f_out, g_out, res, stream, ws);
 }
 
 extern "C" accsk_status accsk_plan_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,
@@ -1445,8 +1479,9 @@ extern "C" accsk_status accsk_eval_dense(const float *C, int64_t n, int64_t m, i
     if (n < 1 || m < 1 || ldc < m) return ACCSK_SHAPE;
     hipStream_t s = (hipStream_t)stream;
     double *dout = nullptr;
+    Workspace ws;
     if (hipMallocAsync((void **)&dout, 8 * 8, s) != hipSuccess) return ACCSK_OOM;
-    accsk_status st = run_eval(C, n, m, ldc, eps, a, b, f, g, dout, nullptr, s);
+    accsk_status st = run_eval(C, n, m, ldc, eps, a, b, f, g, dout, nullptr, s, ws);
     if (st == ACCSK_OK) {
         hipError_t e = hipMemcpyAsync(out, dout, 5 * 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);

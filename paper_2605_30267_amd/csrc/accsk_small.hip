@@ -47,7 +47,7 @@ using namespace accsk;
 // Persistent multi-problem solver of accsk_dense.hip (problems that do not fit
 // one workgroup).
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                               accsk_result *res, hipStream_t s);
+                               accsk_result *res, hipStream_t s, Workspace &ws);
 
 // Dynamic on-chip memory one workgroup may take (of 160 KiB per CU).
 static constexpr size_t kSmallLdsMax = 150 * 1024;
@@ -68,8 +68,10 @@ bool accsk_on_one_workgroup(int64_t n, int64_t m, int64_t count) {
     return accsk_small_fits(n, m) && (n * m <= 65536 || count > 64);
 }
 
+// One launch, one workgroup per problem.  Over a fixed workspace region the
+// kernel time comes from the device clock (no events are created).
 static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, const SmallCtl &ctl,
-                                      accsk_result *res, hipStream_t s) {
+                                      accsk_result *res, hipStream_t s, Workspace &ws) {
     const int64_t count = (int64_t)probs.size();
     long long mmax = 0;
     size_t lds = 0;  // each workgroup lays out its own problem: the launch needs the largest one
@@ -85,12 +87,14 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
     if (lds > kSmallLdsMax) return ACCSK_SHAPE;
     const size_t bytes_p = sizeof(SmallProb) * (size_t)count, bytes_r = sizeof(DevResult) * (size_t)count;
     char *buf = nullptr;
-    if (hipMallocAsync((void **)&buf, bytes_p + bytes_r + 256, s) != hipSuccess) return ACCSK_OOM;
+    if (ws.get((void **)&buf, bytes_p + bytes_r + 256, s) != hipSuccess) return ACCSK_OOM;
     SmallProb *d_probs = (SmallProb *)buf;
     DevResult *d_res = (DevResult *)(buf + ((bytes_p + 255) & ~size_t(255)));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
-    if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+    if (!ws.fixed()) {
+        if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+        if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+    }
     hipError_t e = hipMemcpyAsync(d_probs, hp.data(), bytes_p, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
     if (e == hipSuccess)
@@ -104,30 +108,16 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
     if (e == hipSuccess && ev0 && ev1 && hipEventElapsedTime(&kms, ev0, ev1) != hipSuccess) kms = -1.f;
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
-    (void)hipFreeAsync(buf, s);
+    ws.put(buf, s);
     if (e != hipSuccess) return ACCSK_HIP_ERROR;
-    for (int64_t k = 0; k < count; k++) {
-        const DevResult &r = hr[(size_t)k];
-        accsk_result &o = res[k];
-        o.iters = r.iters;
-        o.sinkhorn_steps = r.steps;
-        o.fallback_steps = r.fallback;
-        o.fval_increases = r.incr;
-        o.restarts = r.restarts;
-        o.marginal_err = r.err;
-        o.eot_value = r.eot;
-        o.transport_cost = r.cost;
-        o.dual_fval = r.fval;
-        o.kernel_ms = kms;  // the whole batch's launch
-        o.converged = r.converged;
-        o.status = r.status;
-        if (r.status == ACCSK_OK && !r.converged) o.status = ACCSK_NOT_CONVERGED;
-    }
+    // with events: the whole batch's launch; else the problem's own device clock
+    for (int64_t k = 0; k < count; k++) fill_result(res[k], hr[(size_t)k], ws.fixed() ? -1.0 : (double)kms);
     return ACCSK_OK;
 }
 
-extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                                          accsk_result *res, void *stream) {
+// accsk_solve_batch with its workspace (a fixed region: no allocation).
+accsk_status accsk_solve_batch_ws(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                                  accsk_result *res, void *stream, Workspace &ws) {
     if (!probs || !res || !p || count < 0) return ACCSK_INVALID_ARG;
     if (count == 0) return ACCSK_OK;
     if (p->err_trace && count > 1) return ACCSK_INVALID_ARG;  // one trace buffer: one problem
@@ -152,11 +142,11 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
     hipStream_t s = (hipStream_t)stream;
     std::vector<accsk_result> rs(small.size()), rb(big.size());
     if (!small.empty()) {
-        st = solve_small_batch(small, ctl, rs.data(), s);
+        st = solve_small_batch(small, ctl, rs.data(), s, ws);
         if (st != ACCSK_OK) return st;
     }
     if (!big.empty()) {
-        st = accsk_dense_multi(big.data(), (int64_t)big.size(), p, rb.data(), s);
+        st = accsk_dense_multi(big.data(), (int64_t)big.size(), p, rb.data(), s, ws);
         if (st != ACCSK_OK) return st;
     }
     for (size_t k = 0; k < small.size(); k++) res[small_idx[k]] = rs[k];
@@ -169,6 +159,12 @@ extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t co
             worst = (accsk_status)stk;
     }
     return worst;
+}
+
+extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                                          accsk_result *res, void *stream) {
+    Workspace ws;  // stream-ordered allocations
+    return accsk_solve_batch_ws(probs, count, p, res, stream, ws);
 }
 
 extern "C" accsk_status accsk_solve_batch_strided(const float *C, int64_t batch, int64_t n, int64_t m, int64_t ldc,

@@ -167,6 +167,7 @@ __global__ __launch_bounds__(1024) void tiled_setup(const TiledArgs *__restrict_
         A.gscal[0] = mx;
         A.gscal[1] = exp2(mx);
         A.status[0] = (bad & 2) ? ACCSK_NONFINITE : ((bad & 1) ? ACCSK_INVALID_ARG : ACCSK_OK);
+        A.res->t0 = dev_clock();
     }
 }
 
@@ -200,6 +201,8 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
             r.fval = NAN;
             r.cost = NAN;
             r.status = A.status[0];
+            r.t0 = A.res->t0;
+            r.t1 = dev_clock();
             *A.res = r;
         }
         return;
@@ -683,6 +686,8 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         r.cost = cost_total;
         r.converged = (status == ACCSK_OK && err < A.tol_stop) ? 1 : 0;
         r.status = status;
+        r.t0 = A.res->t0;
+        r.t1 = dev_clock();
         *A.res = r;
     }
 }
@@ -769,19 +774,7 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     if (ev1) (void)hipEventDestroy(ev1);
     (void)hipFreeAsync(base, s);
     if (e != hipSuccess) return ACCSK_HIP_ERROR;
-    res->iters = hr.iters;
-    res->sinkhorn_steps = hr.steps;
-    res->fallback_steps = hr.fallback;
-    res->fval_increases = hr.incr;
-    res->restarts = hr.restarts;
-    res->marginal_err = hr.err;
-    res->eot_value = hr.eot;
-    res->transport_cost = hr.cost;
-    res->dual_fval = hr.fval;
-    res->kernel_ms = kms;
-    res->converged = hr.converged;
-    res->status = hr.status;
-    if (hr.status == ACCSK_OK && !hr.converged) res->status = ACCSK_NOT_CONVERGED;
+    fill_result(*res, hr, (double)kms);
     return ACCSK_OK;
 }
 

@@ -130,6 +130,7 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
     double *afac = rowS + n;    // [n] a_i / max a
     double *wpart = afac + n;   // [NW][m] per-wave column sums
 
+    if (tid == 0) res->t0 = dev_clock();
     // ---------------- set-up: validation, unit mass (eq:Fc), logs ----------------
     int bad = 0;
     double sa = 0.0, sb = 0.0;
@@ -157,6 +158,8 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
             r.fval = NAN;
             r.cost = NAN;
             r.status = (badall & 2) ? ACCSK_NONFINITE : ACCSK_INVALID_ARG;
+            r.t0 = res->t0;
+            r.t1 = dev_clock();
             *res = r;
         }
         return;
@@ -428,6 +431,8 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
         r.cost = (ctl.flags & ACCSK_FLAG_NO_COST) ? NAN : cst;
         r.converged = (status == ACCSK_OK && err < ctl.tol_stop) ? 1 : 0;
         r.status = status;
+        r.t0 = res->t0;
+        r.t1 = dev_clock();
         *res = r;
     }
 }

@@ -172,3 +172,22 @@ def test_host_validation_read_bandwidth(lib):
     assert f(4096, 8, 1, ctypes.byref(out), None) == accsk.INVALID_ARG
     assert f(4097, 1 << 20, 1, ctypes.byref(out), None) == accsk.INVALID_ARG
     assert f(4096, 1 << 20, 1, None, None) == accsk.INVALID_ARG
+
+
+def test_host_validation_noalloc(lib):
+    """The allocation-free dense solve validates on the host before touching the device."""
+    f = lib.accsk_solve_dense_noalloc
+    r = accsk.Result()
+    fake = ctypes.c_void_p(4096)  # never dereferenced
+
+    def call(n, m, ldc, ptr=fake, **kw):
+        p = accsk.default_params(**kw)
+        return f(ptr, n, m, ldc, fake, fake, ctypes.byref(p), fake, fake, ctypes.byref(r), None)
+
+    assert call(4, 4, 4, ptr=None) == accsk.INVALID_ARG
+    assert call(4, 4, 4, eps=-1.0) == accsk.INVALID_ARG
+    assert call(4, 4, 4, tol=0.0) == accsk.INVALID_ARG
+    assert call(0, 4, 4) == accsk.SHAPE
+    assert call(4, 4, 3) == accsk.SHAPE
+    assert call(4, 9000, 9000) == accsk.SHAPE
+    assert r.status == accsk.INVALID_ARG and r.converged == 0
