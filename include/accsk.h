@@ -24,6 +24,17 @@
  *   (sum_j g_j = 0, the gauge of eq:Fc).
  * - Calls that fill an accsk_result (host pointer) block until their work on
  *   `stream` has finished.  Other calls only enqueue work.
+ * - Stream-ordered forms (names ending in _async) take the result records in
+ *   device memory (or host-mapped pinned memory) instead and only enqueue
+ *   work: the records are written by the device when the stream reaches the
+ *   end of the solve, so several solves can be queued back to back, overlap
+ *   host work, and be waited for with one event or stream synchronization.
+ *   Their return value reports what the host can check before enqueueing
+ *   (INVALID_ARG, SHAPE, OOM, HIP_ERROR); a problem's own outcome (OK,
+ *   NOT_CONVERGED, NONFINITE, INVALID_ARG for a non-positive marginal entry,
+ *   DIVERGED) is in its record's `status`, and its kernel_ms is measured on the
+ *   device clock.  Input buffers must stay valid until the stream has passed
+ *   the call's work.
  * - Errors are reported by the return value; no exception crosses the ABI.
  *   On any status other than ACCSK_OK / ACCSK_NOT_CONVERGED the output
  *   buffers are unspecified.
@@ -161,6 +172,16 @@ accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, int64_t ldc
                                double *f_out, double *g_out, accsk_result *res, void *stream);
 
 /*
+ * Stream-ordered form of accsk_solve_dense (same arguments, routing, kernels
+ * and results): res is a device pointer (or host-mapped pinned memory) to one
+ * accsk_result, written by the device; the call returns once the work is
+ * enqueued (Sec. 2 problem statement: (C; a, b; eps; tol) -> (f, g, cost, It)).
+ */
+accsk_status accsk_solve_dense_async(const float *C, int64_t n, int64_t m, int64_t ldc,
+                                     const double *a, const double *b, const accsk_params *p,
+                                     double *f_out, double *g_out, accsk_result *res, void *stream);
+
+/*
  * For callers that cannot allocate device memory (code under stream capture,
  * serving loops or harnesses that forbid hipMalloc): accsk_solve_dense with
  * the same arguments, routing, kernels and results, but no device allocation
@@ -246,6 +267,14 @@ accsk_status accsk_solve_batch_strided(const float *C, int64_t batch, int64_t n,
                                        const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
                                        void *stream);
 
+/* Stream-ordered form of accsk_solve_batch_strided: res is a device array of
+ * `batch` records written by the device (eps, when given, is still a host
+ * array); returns once the work is enqueued. */
+accsk_status accsk_solve_batch_strided_async(const float *C, int64_t batch, int64_t n, int64_t m, int64_t ldc,
+                                             int64_t stride_c, const double *a, const double *b, const double *eps,
+                                             const accsk_params *p, double *f_out, double *g_out,
+                                             accsk_result *res, void *stream);
+
 /*
  * Cost matrix from point clouds (Sec. 5: squared Euclidean for colour
  * transfer, cosine for word alignment).  X: device FP32 n x d, Y: device FP32
@@ -322,6 +351,14 @@ accsk_status accsk_solve_points_batched(const float *X, const float *Y, int64_t 
                                         int64_t d, int kind, double cost_scale, const double *a,
                                         const double *b, const accsk_params *p, double *f_out, double *g_out,
                                         accsk_result *res, void *stream);
+
+/* Stream-ordered form of accsk_solve_points_batched (and, with batch = 1, of
+ * accsk_solve_points): res is a device array of `batch` records written by the
+ * device; returns once the work is enqueued. */
+accsk_status accsk_solve_points_batched_async(const float *X, const float *Y, int64_t batch, int64_t n,
+                                              int64_t m, int64_t d, int kind, double cost_scale, const double *a,
+                                              const double *b, const accsk_params *p, double *f_out,
+                                              double *g_out, accsk_result *res, void *stream);
 
 /*
  * Gradients of the EOT value at the potentials (f, g) by the envelope theorem

@@ -85,6 +85,9 @@ def lib():
         L.accsk_solve_dense.restype = ctypes.c_int
         L.accsk_solve_dense_noalloc.argtypes = L.accsk_solve_dense.argtypes
         L.accsk_solve_dense_noalloc.restype = ctypes.c_int
+        L.accsk_solve_dense_async.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, ctypes.POINTER(Params), _vp, _vp,
+                                              _vp, _vp]
+        L.accsk_solve_dense_async.restype = ctypes.c_int
         L.accsk_plan_dense.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _i64, _vp, _i64, _vp]
         L.accsk_plan_dense.restype = ctypes.c_int
         L.accsk_eval_dense.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _vp, _vp,
@@ -96,6 +99,9 @@ def lib():
         L.accsk_solve_batch_strided.argtypes = [_vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp,
                                                 ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(Result), _vp]
         L.accsk_solve_batch_strided.restype = ctypes.c_int
+        L.accsk_solve_batch_strided_async.argtypes = [_vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp,
+                                                      ctypes.POINTER(Params), _vp, _vp, _vp, _vp]
+        L.accsk_solve_batch_strided_async.restype = ctypes.c_int
         L.accsk_workspace_bytes.argtypes = [_i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)]
         L.accsk_workspace_bytes.restype = ctypes.c_int
         L.accsk_read_bandwidth.argtypes = [_vp, _i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _vp]
@@ -297,6 +303,70 @@ def solve_batch_strided(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0
     return f, g, results_as_arrays(res), st
 
 
+def result_records(count, device):
+    """Device memory for `count` accsk_result records (the stream-ordered entry points write them)."""
+    import torch
+    return torch.empty(count * ctypes.sizeof(Result), dtype=torch.uint8, device=device)
+
+
+def read_records(rec):
+    """Host copy of device result records as a list of dicts (the copy follows the stream's work)."""
+    raw = rec.cpu().numpy().tobytes()
+    sz = ctypes.sizeof(Result)
+    return [Result.from_buffer_copy(raw, k * sz).to_dict() for k in range(len(raw) // sz)]
+
+
+def solve_dense_async(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=None, w_rule=None,
+                      flags=0, f_out=None, g_out=None, rec=None):
+    """Stream-ordered solve_dense: enqueues the solve and returns (f, g, rec) at once; rec holds the
+    device result record (read it with read_records after the stream has passed the work)."""
+    import torch
+    _check_dev(C, torch.float32, "C", 2)
+    _check_dev(a, torch.float64, "a", 1)
+    _check_dev(b, torch.float64, "b", 1)
+    if C.stride(1) != 1:
+        raise ValueError("C must have unit column stride")
+    n, m = C.shape
+    if not (a.is_contiguous() and b.is_contiguous()):
+        raise ValueError("a and b must be contiguous (the call returns before the solve reads them)")
+    if f_out is None:
+        f_out = torch.empty(n, dtype=torch.float64, device=C.device)
+    if g_out is None:
+        g_out = torch.empty(m, dtype=torch.float64, device=C.device)
+    if rec is None:
+        rec = result_records(1, C.device)
+    p = default_params(method=method, eps=float(eps), tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0,
+                       w_rule=w_rule, flags=int(flags))
+    st = lib().accsk_solve_dense_async(_ptr(C), n, m, C.stride(0), _ptr(a), _ptr(b), ctypes.byref(p),
+                                       _ptr(f_out), _ptr(g_out), _ptr(rec), _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_solve_dense_async")
+    return f_out, g_out, rec
+
+
+def solve_batch_strided_async(C, a, b, eps, tol=1e-6, method=ACC, max_iter=100000, mu0=None, m0=None,
+                              w_rule=None, flags=0, rec=None):
+    """Stream-ordered solve_batch_strided (eps: one float): returns (f [B, n], g [B, m], rec) at once."""
+    import torch
+    _check_dev(C, torch.float32, "C", 3)
+    _check_dev(a, torch.float64, "a", 2)
+    _check_dev(b, torch.float64, "b", 2)
+    if C.stride(2) != 1 or not (a.is_contiguous() and b.is_contiguous()):
+        raise ValueError("C must have unit column stride, a and b must be contiguous")
+    B, n, m = C.shape
+    f = torch.empty((B, n), dtype=torch.float64, device=C.device)
+    g = torch.empty((B, m), dtype=torch.float64, device=C.device)
+    if rec is None:
+        rec = result_records(B, C.device)
+    p = default_params(eps=float(eps), method=method, tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0,
+                       w_rule=w_rule, flags=int(flags))
+    st = lib().accsk_solve_batch_strided_async(_ptr(C), B, n, m, C.stride(1), C.stride(0), _ptr(a), _ptr(b), None,
+                                               ctypes.byref(p), _ptr(f), _ptr(g), _ptr(rec), _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_solve_batch_strided_async")
+    return f, g, rec
+
+
 def results_as_arrays(res):
     """A ctypes array of Result as a dict of numpy arrays, one per field (no per-problem objects)."""
     import numpy as np
@@ -352,6 +422,9 @@ def _register_points(L):
     L.accsk_solve_points_batched.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.c_int, _dbl, _vp, _vp,
                                              ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(Result), _vp]
     L.accsk_solve_points_batched.restype = ctypes.c_int
+    L.accsk_solve_points_batched_async.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.c_int, _dbl, _vp, _vp,
+                                                   ctypes.POINTER(Params), _vp, _vp, _vp, _vp]
+    L.accsk_solve_points_batched_async.restype = ctypes.c_int
     L.accsk_backward_points.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.accsk_backward_points.restype = ctypes.c_int
@@ -506,6 +579,31 @@ def solve_points(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e
     if single:
         return f[0], g[0], out
     return f, g, out
+
+
+def solve_points_async(X, Y, a, b, eps, kind=SQEUCLID, cost_scale=1.0, split=0, tol=1e-6, method=ACC,
+                       max_iter=100000, mu0=None, m0=None, w_rule=None, flags=0, on_the_fly=False, rec=None):
+    """Stream-ordered solve_points (batched shapes [B, n, d] or single [n, d]): returns (f, g, rec) at once."""
+    if on_the_fly:
+        flags = int(flags) | FLAG_ON_THE_FLY
+    import torch
+    single, X, Y, a, b = _as_batched(X, Y, a, b)
+    B, n, d = X.shape
+    m = Y.shape[1]
+    f = torch.empty((B, n), dtype=torch.float64, device=X.device)
+    g = torch.empty((B, m), dtype=torch.float64, device=X.device)
+    if rec is None:
+        rec = result_records(B, X.device)
+    p = default_params(method=method, eps=float(eps), tol=float(tol), max_iter=int(max_iter), mu0=mu0, m0=m0,
+                       w_rule=w_rule, split=int(split), flags=int(flags))
+    st = _points_lib().accsk_solve_points_batched_async(_ptr(X), _ptr(Y), B, n, m, d, int(kind),
+                                                        float(cost_scale), _ptr(a), _ptr(b), ctypes.byref(p),
+                                                        _ptr(f), _ptr(g), _ptr(rec), _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_solve_points_batched_async")
+    if single:
+        return f[0], g[0], rec
+    return f, g, rec
 
 
 def backward_points(X, Y, a, b, f, g, eps, kind=SQEUCLID, cost_scale=1.0, grad_scale=None, marginals=True):

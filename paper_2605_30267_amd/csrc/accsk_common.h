@@ -245,6 +245,50 @@ inline void fill_result(accsk_result &o, const DevResult &r, double kms) {
     if (r.status == ACCSK_OK && !r.converged) o.status = ACCSK_NOT_CONVERGED;
 }
 
+// Device form of fill_result for the stream-ordered entry points: the record
+// is written by the device, the duration taken from the device clock stamps.
+__device__ inline void publish_record(accsk_result *o, const DevResult &r, double tick_ms) {
+    o->iters = r.iters;
+    o->sinkhorn_steps = r.steps;
+    o->fallback_steps = r.fallback;
+    o->fval_increases = r.incr;
+    o->restarts = r.restarts;
+    o->marginal_err = r.err;
+    o->eot_value = r.eot;
+    o->transport_cost = r.cost;
+    o->dual_fval = r.fval;
+    o->kernel_ms = (tick_ms > 0.0 && r.t1 >= r.t0) ? (double)(r.t1 - r.t0) * tick_ms : -1.0;
+    o->converged = r.converged;
+    o->status = (r.status == ACCSK_OK && !r.converged) ? ACCSK_NOT_CONVERGED : r.status;
+}
+
+// Host-to-device copy of a small host array through kernel arguments, for the
+// stream-ordered entry points: the runtime copies a launch's arguments when
+// the launch is enqueued, so the host array may go away as soon as the call
+// returns, and nothing waits for earlier work on the stream (a hipMemcpyAsync
+// from pageable host memory may).
+struct ArgBlob {
+    unsigned char b[2048];
+};
+namespace {
+__global__ __launch_bounds__(256) void upload_blob(ArgBlob blob, unsigned nbytes, unsigned char *dst) {
+    for (unsigned i = threadIdx.x; i < nbytes; i += 256) dst[i] = blob.b[i];
+}
+}  // namespace
+inline hipError_t upload_args(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    const unsigned char *p = (const unsigned char *)src;
+    unsigned char *d = (unsigned char *)dst;
+    for (size_t off = 0; off < bytes; off += sizeof(ArgBlob)) {
+        ArgBlob blob;
+        const size_t nb = bytes - off < sizeof(ArgBlob) ? bytes - off : sizeof(ArgBlob);
+        for (size_t i = 0; i < nb; i++) blob.b[i] = p[off + i];
+        hipLaunchKernelGGL(upload_blob, dim3(1), dim3(256), 0, s, blob, (unsigned)nb, d + off);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Device workspace of one library call.  By default it is stream-ordered
 // (hipMallocAsync / hipFreeAsync on the call's stream).  Over a fixed region
 // (base != nullptr) it hands out 256-byte aligned slices in stack order and

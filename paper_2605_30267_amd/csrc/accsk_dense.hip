@@ -60,6 +60,7 @@ struct DenseArgs {
     int *status;                  // setup status
     unsigned long long *bar;      // grid barrier counter
     DevResult *res;
+    accsk_result *pub;  // stream-ordered calls: the caller's device result record (else null)
     double *f_out, *g_out;
     double eps, kappa, tol, tol_stop, mu0;
     long long max_iter, m0;
@@ -971,7 +972,7 @@ __global__ __launch_bounds__(1024) void eval_final(long long n, long long m, int
                                                    const double *__restrict__ g,
                                                    const double *__restrict__ rowscal,
                                                    const double *__restrict__ colerr,
-                                                   double *__restrict__ out, DevResult *res) {
+                                                   double *__restrict__ out, DevResult *res, accsk_result *pub) {
     __shared__ double red[16];
     const int tid = threadIdx.x;
     double re = 0.0, mass = 0.0, cost = 0.0, ce = 0.0, fa = 0.0, gb = 0.0;
@@ -1001,7 +1002,17 @@ __global__ __launch_bounds__(1024) void eval_final(long long n, long long m, int
             res->cost = cost;
             res->eot = fa + gb - eps * mass;
         }
+        if (pub) {
+            pub->transport_cost = cost;
+            pub->eot_value = fa + gb - eps * mass;
+        }
     }
+}
+
+// Stream-ordered calls: each problem's result record, written to the caller's device memory.
+__global__ __launch_bounds__(64) void publish_dense(const DenseArgs *__restrict__ probs, int cnt, double tick_ms) {
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k < cnt && probs[k].pub) publish_record(probs[k].pub, *probs[k].res, tick_ms);
 }
 
 // an = a / sum a, bn = b / sum b (one workgroup; FP64 sums).
@@ -1045,9 +1056,11 @@ int device_cu_count() {
     return cu;
 }
 
+// res / pub (either may be null): the device result record whose dual value
+// and <C,P> the evaluation replaces.
 accsk_status run_eval(const float *C, long long n, long long m, long long ldc, double eps, const double *a,
                       const double *b, const double *f, const double *g, double *out_dev, DevResult *res,
-                      hipStream_t s, Workspace &ws) {
+                      hipStream_t s, Workspace &ws, accsk_result *pub = nullptr) {
     const int G = (int)std::min<long long>(n, 1024);
     const int RS = (int)std::min<long long>(n, 64);
     double *buf = nullptr;
@@ -1060,7 +1073,7 @@ accsk_status run_eval(const float *C, long long n, long long m, long long ldc, d
     hipLaunchKernelGGL(eval_cols, dim3((unsigned)((m + kEvalTPB - 1) / kEvalTPB)), dim3(kEvalTPB), 0, s, m, RS,
                        b, colpart, colerr);
     hipLaunchKernelGGL(eval_final, dim3(1), dim3(1024), 0, s, n, m, G, eps, a, b, f, g, rowscal, colerr,
-                       out_dev, res);
+                       out_dev, res, pub);
     hipError_t e = hipGetLastError();
     ws.put(buf, s);
     return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
@@ -1073,11 +1086,14 @@ struct HostProb {
     const double *a, *b;
     double *f, *g;
     double eps;
+    accsk_result *pub;  // stream-ordered calls: device result record (else null)
 };
 
 // Solves problems [k0, k1) of `hp` with one cooperative launch, gp workgroups
-// per problem.  Results go to res[k0..k1).  Over a fixed workspace region the
-// kernel time comes from the device clock (no events are created).
+// per problem.  Results go to res[k0..k1) (the call waits for the stream), or,
+// when the problems carry device result records (pub), are written there by
+// the device and nothing waits.  Over a fixed workspace region, and for
+// device records, the kernel time comes from the device clock (no events).
 template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false>
 accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const accsk_params *p,
                          accsk_result *res, hipStream_t s, int num_cu, Workspace &ws) {
@@ -1177,18 +1193,21 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         A.bscal = (double *)q0;
         A.uapart = A.bscal + 2 * (size_t)gp * kNS;
         A.res = (DevResult *)(base + o_res) + q;
+        A.pub = h.pub;
         A.gscal = (double *)(base + o_gscal) + 8 * q;
         A.status = (int *)(base + o_stat + 64 * (size_t)q);
         A.bar = (unsigned long long *)(base + o_bar + 256 * (size_t)q);
     }
     DenseArgs *d_args = (DenseArgs *)(base + o_args);
+    const bool async = hp[k0].pub != nullptr;  // all problems of a call, or none
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (!ws.fixed()) {
+    if (!ws.fixed() && !async) {
         if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
         if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
     }
     // (setup_marginals also zeroes each problem's barrier words)
-    hipError_t e = hipMemcpyAsync(d_args, args.data(), sizeof(DenseArgs) * cnt, hipMemcpyHostToDevice, s);
+    hipError_t e = async ? upload_args(d_args, args.data(), sizeof(DenseArgs) * cnt, s)
+                         : hipMemcpyAsync(d_args, args.data(), sizeof(DenseArgs) * cnt, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(setup_marginals, dim3(cnt), dim3(1024), 0, s, (const DenseArgs *)d_args);
         e = hipGetLastError();
@@ -1210,6 +1229,15 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
             // <C,P> and the dual value at the returned potentials, FP64, with normalized marginals
             st = run_eval(A.C, A.n, A.m, A.ldc, A.eps, A.an, A.bn, A.f_out, A.g_out, A.gscal + 1, A.res, s, ws);
         }
+    }
+    if (async) {
+        if (st == ACCSK_OK) {
+            hipLaunchKernelGGL(publish_dense, dim3((unsigned)((cnt + 63) / 64)), dim3(64), 0, s,
+                               (const DenseArgs *)d_args, cnt, wall_tick_ms());
+            if (hipGetLastError() != hipSuccess) st = ACCSK_HIP_ERROR;
+        }
+        ws.put(base, s);
+        return st;
     }
     std::vector<DevResult> hr(cnt);
     if (st == ACCSK_OK) {
@@ -1282,20 +1310,21 @@ bool accsk_on_one_workgroup(int64_t n, int64_t m, int64_t count);
 accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, const float *Y, int64_t d, int kind,
                                double cost_scale, int64_t n, int64_t m, const double *a, const double *b,
                                const accsk_params *p, double eps, double *f_out, double *g_out, accsk_result *res,
-                               hipStream_t s);
+                               hipStream_t s, accsk_result *pub);
 
 // Persistent multi-problem path, also used by the batch entry point for
 // problems with more than 1024 columns.  Over a fixed workspace region a
-// problem that would need the tiled solver is refused (SHAPE).
+// problem that would need the tiled solver is refused (SHAPE).  pub (null, or
+// `count` device result records): the stream-ordered form, res unused.
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                               accsk_result *res, hipStream_t s, Workspace &ws) {
+                               accsk_result *res, hipStream_t s, Workspace &ws, accsk_result *const *pub) {
     using namespace accsk;
     const int cu = device_cu_count();
     if (cu <= 0) return ACCSK_HIP_ERROR;
     std::vector<HostProb> hp((size_t)count);
     for (int64_t k = 0; k < count; k++) {
         const accsk_problem &q = probs[k];
-        hp[(size_t)k] = HostProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps};
+        hp[(size_t)k] = HostProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps, pub ? pub[k] : nullptr};
     }
     // At most one CU's worth of problems per cooperative launch.  A launch
     // whose row blocks do not fit on chip (many rows per block) is split in
@@ -1322,8 +1351,8 @@ accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const 
             if (ws.fixed()) return ACCSK_SHAPE;
             const HostProb &h = hp[(size_t)k0];
             st = accsk_tiled_solve(h.C, h.ldc, nullptr, nullptr, 0, 0, 1.0, h.n, h.m, h.a, h.b, p, h.eps, h.f, h.g,
-                                   &res[k0], s);
-            // per-problem outcomes are in res[k0]; only call failures stop the batch
+                                   res ? &res[k0] : nullptr, s, h.pub);
+            // per-problem outcomes are in res[k0] (or its device record); only call failures stop the batch
             if (st == ACCSK_OOM || st == ACCSK_HIP_ERROR || st == ACCSK_SHAPE) return st;
             st = ACCSK_OK;
         }
@@ -1390,19 +1419,21 @@ accsk_status accsk_check_dense_params(const accsk_params *p) {
 
 // Batch solve of accsk_small.hip with its workspace.
 accsk_status accsk_solve_batch_ws(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                                  accsk_result *res, void *stream, accsk::Workspace &ws);
+                                  accsk_result *res, void *stream, accsk::Workspace &ws, accsk_result *const *pub);
 
 // accsk_solve_dense with its workspace.  Over a fixed region the tiled solver
 // (m > 8192, or row blocks too large for on-chip memory) is not used (SHAPE).
+// pub: null, or the device result record of the stream-ordered form (then res
+// is unused and nothing waits for the stream).
 accsk_status accsk_solve_dense_ws(const float *C, int64_t n, int64_t m, int64_t ldc, const double *a,
                                   const double *b, const accsk_params *p, double *f_out, double *g_out,
-                                  accsk_result *res, void *stream, accsk::Workspace &ws) {
+                                  accsk_result *res, void *stream, accsk::Workspace &ws, accsk_result *pub) {
     using namespace accsk;
     if (res) {
         res->status = ACCSK_INVALID_ARG;
         res->converged = 0;
     }
-    if (!C || !a || !b || !p || !f_out || !g_out || !res) return ACCSK_INVALID_ARG;
+    if (!C || !a || !b || !p || !f_out || !g_out || !(res || pub)) return ACCSK_INVALID_ARG;
     if (!finite_pos(p->eps)) return ACCSK_INVALID_ARG;
     accsk_status st = check_params(p);
     if (st != ACCSK_OK) return st;
@@ -1410,14 +1441,15 @@ accsk_status accsk_solve_dense_ws(const float *C, int64_t n, int64_t m, int64_t 
     if (m > 8192) {
         if (ws.fixed()) return ACCSK_SHAPE;
         st = accsk_tiled_solve(C, ldc, nullptr, nullptr, 0, 0, 1.0, n, m, a, b, p, p->eps, f_out, g_out, res,
-                               (hipStream_t)stream);
+                               (hipStream_t)stream, pub);
         return st;
     }
     // A batch of one: one workgroup up to 256 x 256 entries, else a group of
     // cooperating workgroups (or the tiled solver when its row blocks do not
     // fit on chip).
     accsk_problem q{C, n, m, ldc, a, b, f_out, g_out, p->eps};
-    st = accsk_solve_batch_ws(&q, 1, p, res, stream, ws);
+    accsk_result *const pubs[1] = {pub};
+    st = accsk_solve_batch_ws(&q, 1, p, res, stream, ws, pub ? pubs : nullptr);
     if ((st != ACCSK_OK && st != ACCSK_NOT_CONVERGED) || (p->flags & ACCSK_FLAG_NO_COST) ||
         !accsk_on_one_workgroup(n, m, 1))
         return st;
@@ -1429,7 +1461,11 @@ accsk_status accsk_solve_dense_ws(const float *C, int64_t n, int64_t m, int64_t 
     double *an = buf, *bn = buf + n, *out = buf + n + m;
     hipLaunchKernelGGL(normalize_pair, dim3(1), dim3(1024), 0, s, a, n, b, m, an, bn);
     accsk_status se = hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
-    if (se == ACCSK_OK) se = run_eval(C, n, m, ldc, p->eps, an, bn, f_out, g_out, out, nullptr, s, ws);
+    if (se == ACCSK_OK) se = run_eval(C, n, m, ldc, p->eps, an, bn, f_out, g_out, out, nullptr, s, ws, pub);
+    if (pub) {  // the evaluation has replaced the values in the device record
+        ws.put(buf, s);
+        return se;
+    }
     double h[5] = {0, 0, 0, 0, 0};
     if (se == ACCSK_OK) {
         hipError_t e = hipMemcpyAsync(h, out, 5 * 8, hipMemcpyDeviceToHost, s);
@@ -1447,7 +1483,15 @@ extern "C" accsk_status accsk_solve_dense(const float *C, int64_t n, int64_t m, 
                                           const double *b, const accsk_params *p, double *f_out,
                                           double *g_out, accsk_result *res, void *stream) {
     accsk::Workspace ws;  // stream-ordered allocations
-    return accsk_solve_dense_ws(C, n, m, ldc, a, b, p, f_out, g_out, res, stream, ws);
+    return accsk_solve_dense_ws(C, n, m, ldc, a, b, p, f_out, g_out, res, stream, ws, nullptr);
+}
+
+extern "C" accsk_status accsk_solve_dense_async(const float *C, int64_t n, int64_t m, int64_t ldc, const double *a,
+                                                const double *b, const accsk_params *p, double *f_out,
+                                                double *g_out, accsk_result *res, void *stream) {
+    if (!res) return ACCSK_INVALID_ARG;
+    accsk::Workspace ws;  // stream-ordered allocations
+    return accsk_solve_dense_ws(C, n, m, ldc, a, b, p, f_out, g_out, nullptr, stream, ws, res);
 }
 
 extern "C" accsk_status accsk_plan_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,

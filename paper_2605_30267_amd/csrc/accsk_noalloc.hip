@@ -11,7 +11,7 @@ using namespace accsk;
 
 accsk_status accsk_solve_dense_ws(const float *C, int64_t n, int64_t m, int64_t ldc, const double *a,
                                   const double *b, const accsk_params *p, double *f_out, double *g_out,
-                                  accsk_result *res, void *stream, Workspace &ws);
+                                  accsk_result *res, void *stream, Workspace &ws, accsk_result *pub);
 size_t accsk_dense_single_bound(int64_t n, int64_t m, int cu);
 accsk_status accsk_check_dense_params(const accsk_params *p);
 
@@ -69,5 +69,5 @@ extern "C" accsk_status accsk_solve_dense_noalloc(const float *C, int64_t n, int
     Workspace ws;
     ws.base = base;
     ws.cap = kScratchBytes;
-    return accsk_solve_dense_ws(C, n, m, ldc, a, b, p, f_out, g_out, res, stream, ws);
+    return accsk_solve_dense_ws(C, n, m, ldc, a, b, p, f_out, g_out, res, stream, ws, nullptr);
 }

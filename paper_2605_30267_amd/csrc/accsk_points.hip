@@ -34,12 +34,12 @@
 #include "accsk_common.h"
 #include "cost_tiles.h"
 
-accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                               accsk_result *res, hipStream_t s);
 accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, const float *Y, int64_t d, int kind,
                                double cost_scale, int64_t n, int64_t m, const double *a, const double *b,
                                const accsk_params *p, double eps, double *f_out, double *g_out, accsk_result *res,
-                               hipStream_t s);
+                               hipStream_t s, accsk_result *pub);
+accsk_status accsk_solve_batch_ws(const accsk_problem *probs, int64_t count, const accsk_params *p,
+                                  accsk_result *res, void *stream, accsk::Workspace &ws, accsk_result *const *pub);
 
 namespace accsk {
 namespace {
@@ -542,11 +542,12 @@ extern "C" accsk_status accsk_cost_max_points(const float *X, const float *Y, in
 }
 
 // Tiled solves of a batch of point-cloud problems, one after the other: costs on
-// the fly (d <= 16), else built explicitly one problem at a time.
+// the fly (d <= 16), else built explicitly one problem at a time.  dres (device
+// records, one per problem): the stream-ordered form, res unused.
 static accsk_status solve_points_tiled(const float *X, const float *Y, int64_t batch, int64_t n, int64_t m,
                                        int64_t d, int kind, double cost_scale, const double *a, const double *b,
                                        const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
-                                       hipStream_t s) {
+                                       accsk_result *dres, hipStream_t s) {
     float *C = nullptr;
     double *nws = nullptr;
     const long long ldc = (m + 3) / 4 * 4;
@@ -561,30 +562,40 @@ static accsk_status solve_points_tiled(const float *X, const float *Y, int64_t b
     for (int64_t k = 0; k < batch; k++) {
         const float *Xk = X + k * n * d, *Yk = Y + k * m * d;
         accsk_status st;
+        accsk_result *rk = res ? &res[k] : nullptr, *pk = dres ? dres + k : nullptr;
         if (d <= 16) {
             st = accsk_tiled_solve(nullptr, 0, Xk, Yk, d, kind, cost_scale, n, m, a + k * n, b + k * m, p, p->eps,
-                                   f_out + k * n, g_out + k * m, &res[k], s);
+                                   f_out + k * n, g_out + k * m, rk, s, pk);
         } else {
             st = build_cost(Xk, Yk, n, m, d, kind, cost_scale, p->split, C, ldc, nws, s);
             if (st == ACCSK_OK)
                 st = accsk_tiled_solve(C, ldc, nullptr, nullptr, 0, kind, 1.0, n, m, a + k * n, b + k * m, p, p->eps,
-                                       f_out + k * n, g_out + k * m, &res[k], s);
+                                       f_out + k * n, g_out + k * m, rk, s, pk);
+        }
+        if (dres) {
+            if (st != ACCSK_OK) {  // a call failure: later problems are not enqueued
+                if (C) (void)hipFreeAsync(C, s);
+                return st;
+            }
+            continue;
         }
         if (st != ACCSK_OK && st != ACCSK_NOT_CONVERGED && res[k].status == ACCSK_OK) res[k].status = st;
         if (st == ACCSK_OK) continue;
         if (worst == ACCSK_OK || (worst == ACCSK_NOT_CONVERGED && st != ACCSK_NOT_CONVERGED)) worst = st;
     }
     if (C) (void)hipFreeAsync(C, s);
+    if (dres) return ACCSK_OK;
     if (hipStreamSynchronize(s) != hipSuccess) return ACCSK_HIP_ERROR;
     return worst;
 }
 
-extern "C" accsk_status accsk_solve_points_batched(const float *X, const float *Y, int64_t batch, int64_t n,
-                                                   int64_t m, int64_t d, int kind, double cost_scale,
-                                                   const double *a, const double *b, const accsk_params *p,
-                                                   double *f_out, double *g_out, accsk_result *res,
-                                                   void *stream) {
-    if (!p || !a || !b || !f_out || !g_out || !res || batch < 1) return ACCSK_INVALID_ARG;
+// Batch of point-cloud problems: host records (res, the call waits) or device
+// records (dres, stream-ordered).
+static accsk_status solve_points_batched(const float *X, const float *Y, int64_t batch, int64_t n, int64_t m,
+                                         int64_t d, int kind, double cost_scale, const double *a, const double *b,
+                                         const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
+                                         accsk_result *dres, void *stream) {
+    if (!p || !a || !b || !f_out || !g_out || !(res || dres) || batch < 1) return ACCSK_INVALID_ARG;
     if (p->err_trace && batch > 1) return ACCSK_INVALID_ARG;  // one trace buffer: one problem
     if (p->trace_len < 0 || (p->trace_len > 0 && !p->err_trace)) return ACCSK_INVALID_ARG;
     accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, p->split);
@@ -593,7 +604,7 @@ extern "C" accsk_status accsk_solve_points_batched(const float *X, const float *
     hipStream_t s = (hipStream_t)stream;
     if ((p->flags & ACCSK_FLAG_ON_THE_FLY) || m > 8192) {
         if ((p->flags & ACCSK_FLAG_ON_THE_FLY) && d > 16) return ACCSK_SHAPE;
-        return solve_points_tiled(X, Y, batch, n, m, d, kind, cost_scale, a, b, p, f_out, g_out, res, s);
+        return solve_points_tiled(X, Y, batch, n, m, d, kind, cost_scale, a, b, p, f_out, g_out, res, dres, s);
     }
     const long long ldc = (m + 3) / 4 * 4;
     const size_t cbytes = (size_t)batch * n * ldc * sizeof(float);
@@ -609,11 +620,39 @@ extern "C" accsk_status accsk_solve_points_batched(const float *X, const float *
         for (int64_t k = 0; k < batch; k++)
             probs[(size_t)k] = accsk_problem{C + k * n * ldc, n, m, ldc, a + k * n, b + k * m,
                                              f_out + k * n, g_out + k * m, p->eps};
-        st = accsk_solve_batch(probs.data(), batch, p, res, stream);
+        Workspace bws;  // stream-ordered allocations
+        if (dres) {
+            std::vector<accsk_result *> pub((size_t)batch);
+            for (int64_t k = 0; k < batch; k++) pub[(size_t)k] = dres + k;
+            st = accsk_solve_batch_ws(probs.data(), batch, p, nullptr, stream, bws, pub.data());
+        } else {
+            st = accsk_solve_batch_ws(probs.data(), batch, p, res, stream, bws, nullptr);
+        }
     }
     (void)hipFreeAsync(ws, s);
+    if (dres) return st;
     if (hipStreamSynchronize(s) != hipSuccess) return ACCSK_HIP_ERROR;
     return st;
+}
+
+extern "C" accsk_status accsk_solve_points_batched(const float *X, const float *Y, int64_t batch, int64_t n,
+                                                   int64_t m, int64_t d, int kind, double cost_scale,
+                                                   const double *a, const double *b, const accsk_params *p,
+                                                   double *f_out, double *g_out, accsk_result *res,
+                                                   void *stream) {
+    if (!res) return ACCSK_INVALID_ARG;
+    return solve_points_batched(X, Y, batch, n, m, d, kind, cost_scale, a, b, p, f_out, g_out, res, nullptr,
+                                stream);
+}
+
+extern "C" accsk_status accsk_solve_points_batched_async(const float *X, const float *Y, int64_t batch, int64_t n,
+                                                         int64_t m, int64_t d, int kind, double cost_scale,
+                                                         const double *a, const double *b, const accsk_params *p,
+                                                         double *f_out, double *g_out, accsk_result *res,
+                                                         void *stream) {
+    if (!res) return ACCSK_INVALID_ARG;
+    return solve_points_batched(X, Y, batch, n, m, d, kind, cost_scale, a, b, p, f_out, g_out, nullptr, res,
+                                stream);
 }
 
 extern "C" accsk_status accsk_solve_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,

@@ -39,6 +39,13 @@ hipError_t launch_small_cfg(long long mmax, const SmallProb *d_probs, int count,
     return launch_small<4, 64, 16, VEC>(d_probs, count, ctl, d_res, lds, s);
 }
 
+// Stream-ordered calls: each problem's result record, written to the caller's device memory.
+__global__ __launch_bounds__(64) void publish_small(const DevResult *__restrict__ res,
+                                                   accsk_result *const *__restrict__ pub, int cnt, double tick_ms) {
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k < cnt) publish_record(pub[k], res[k], tick_ms);
+}
+
 }  // namespace
 }  // namespace accsk
 
@@ -47,7 +54,7 @@ using namespace accsk;
 // Persistent multi-problem solver of accsk_dense.hip (problems that do not fit
 // one workgroup).
 accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                               accsk_result *res, hipStream_t s, Workspace &ws);
+                               accsk_result *res, hipStream_t s, Workspace &ws, accsk_result *const *pub);
 
 // Dynamic on-chip memory one workgroup may take (of 160 KiB per CU).
 static constexpr size_t kSmallLdsMax = 150 * 1024;
@@ -69,9 +76,12 @@ bool accsk_on_one_workgroup(int64_t n, int64_t m, int64_t count) {
 }
 
 // One launch, one workgroup per problem.  Over a fixed workspace region the
-// kernel time comes from the device clock (no events are created).
+// kernel time comes from the device clock (no events are created).  pub
+// (non-empty: one device record per problem): the stream-ordered form, the
+// device writes the records and nothing waits (res unused).
 static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, const SmallCtl &ctl,
-                                      accsk_result *res, hipStream_t s, Workspace &ws) {
+                                      accsk_result *res, hipStream_t s, Workspace &ws,
+                                      const std::vector<accsk_result *> &pub) {
     const int64_t count = (int64_t)probs.size();
     long long mmax = 0;
     size_t lds = 0;  // each workgroup lays out its own problem: the launch needs the largest one
@@ -86,21 +96,36 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
     }
     if (lds > kSmallLdsMax) return ACCSK_SHAPE;
     const size_t bytes_p = sizeof(SmallProb) * (size_t)count, bytes_r = sizeof(DevResult) * (size_t)count;
+    const bool async = !pub.empty();
+    const size_t bytes_q = async ? sizeof(accsk_result *) * (size_t)count : 0;
+    const size_t o_res = (bytes_p + 255) & ~size_t(255), o_pub = (o_res + bytes_r + 255) & ~size_t(255);
     char *buf = nullptr;
-    if (ws.get((void **)&buf, bytes_p + bytes_r + 256, s) != hipSuccess) return ACCSK_OOM;
+    if (ws.get((void **)&buf, o_pub + bytes_q + 256, s) != hipSuccess) return ACCSK_OOM;
     SmallProb *d_probs = (SmallProb *)buf;
-    DevResult *d_res = (DevResult *)(buf + ((bytes_p + 255) & ~size_t(255)));
+    DevResult *d_res = (DevResult *)(buf + o_res);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (!ws.fixed()) {
+    if (!ws.fixed() && !async) {
         if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
         if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
     }
-    hipError_t e = hipMemcpyAsync(d_probs, hp.data(), bytes_p, hipMemcpyHostToDevice, s);
+    hipError_t e = async ? upload_args(d_probs, hp.data(), bytes_p, s)
+                         : hipMemcpyAsync(d_probs, hp.data(), bytes_p, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
     if (e == hipSuccess)
         e = vec ? launch_small_cfg<true>(mmax, d_probs, (int)count, ctl, d_res, lds, s)
                 : launch_small_cfg<false>(mmax, d_probs, (int)count, ctl, d_res, lds, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    if (async) {
+        accsk_result **d_pub = (accsk_result **)(buf + o_pub);
+        if (e == hipSuccess) e = upload_args(d_pub, pub.data(), bytes_q, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(publish_small, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, s,
+                               (const DevResult *)d_res, (accsk_result *const *)d_pub, (int)count, wall_tick_ms());
+            e = hipGetLastError();
+        }
+        ws.put(buf, s);
+        return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+    }
     std::vector<DevResult> hr((size_t)count);
     if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), d_res, bytes_r, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -115,10 +140,12 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
     return ACCSK_OK;
 }
 
-// accsk_solve_batch with its workspace (a fixed region: no allocation).
+// accsk_solve_batch with its workspace (a fixed region: no allocation).  pub
+// (null, or `count` device result records): the stream-ordered form, where the
+// device writes the records, nothing waits, and res is unused.
 accsk_status accsk_solve_batch_ws(const accsk_problem *probs, int64_t count, const accsk_params *p,
-                                  accsk_result *res, void *stream, Workspace &ws) {
-    if (!probs || !res || !p || count < 0) return ACCSK_INVALID_ARG;
+                                  accsk_result *res, void *stream, Workspace &ws, accsk_result *const *pub) {
+    if (!probs || !(res || pub) || !p || count < 0) return ACCSK_INVALID_ARG;
     if (count == 0) return ACCSK_OK;
     if (p->err_trace && count > 1) return ACCSK_INVALID_ARG;  // one trace buffer: one problem
     SmallCtl ctl;
@@ -140,13 +167,27 @@ accsk_status accsk_solve_batch_ws(const accsk_problem *probs, int64_t count, con
         }
     }
     hipStream_t s = (hipStream_t)stream;
+    if (pub) {
+        for (int64_t k = 0; k < count; k++)
+            if (!pub[k]) return ACCSK_INVALID_ARG;
+        std::vector<accsk_result *> ps, pb;
+        for (int64_t k : small_idx) ps.push_back(pub[k]);
+        for (int64_t k : big_idx) pb.push_back(pub[k]);
+        if (!small.empty()) {
+            st = solve_small_batch(small, ctl, nullptr, s, ws, ps);
+            if (st != ACCSK_OK) return st;
+        }
+        if (!big.empty()) st = accsk_dense_multi(big.data(), (int64_t)big.size(), p, nullptr, s, ws, pb.data());
+        return st;
+    }
     std::vector<accsk_result> rs(small.size()), rb(big.size());
+    const std::vector<accsk_result *> none;
     if (!small.empty()) {
-        st = solve_small_batch(small, ctl, rs.data(), s, ws);
+        st = solve_small_batch(small, ctl, rs.data(), s, ws, none);
         if (st != ACCSK_OK) return st;
     }
     if (!big.empty()) {
-        st = accsk_dense_multi(big.data(), (int64_t)big.size(), p, rb.data(), s, ws);
+        st = accsk_dense_multi(big.data(), (int64_t)big.size(), p, rb.data(), s, ws, nullptr);
         if (st != ACCSK_OK) return st;
     }
     for (size_t k = 0; k < small.size(); k++) res[small_idx[k]] = rs[k];
@@ -164,21 +205,43 @@ accsk_status accsk_solve_batch_ws(const accsk_problem *probs, int64_t count, con
 extern "C" accsk_status accsk_solve_batch(const accsk_problem *probs, int64_t count, const accsk_params *p,
                                           accsk_result *res, void *stream) {
     Workspace ws;  // stream-ordered allocations
-    return accsk_solve_batch_ws(probs, count, p, res, stream, ws);
+    return accsk_solve_batch_ws(probs, count, p, res, stream, ws, nullptr);
 }
 
-extern "C" accsk_status accsk_solve_batch_strided(const float *C, int64_t batch, int64_t n, int64_t m, int64_t ldc,
-                                                  int64_t stride_c, const double *a, const double *b,
-                                                  const double *eps, const accsk_params *p, double *f_out,
-                                                  double *g_out, accsk_result *res, void *stream) {
-    if (!C || !a || !b || !p || !f_out || !g_out || !res || batch < 0) return ACCSK_INVALID_ARG;
+// Strided batch: host records (res) or, stream-ordered, device records (dres).
+static accsk_status solve_batch_strided(const float *C, int64_t batch, int64_t n, int64_t m, int64_t ldc,
+                                        int64_t stride_c, const double *a, const double *b, const double *eps,
+                                        const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
+                                        accsk_result *dres, void *stream) {
+    if (!C || !a || !b || !p || !f_out || !g_out || !(res || dres) || batch < 0) return ACCSK_INVALID_ARG;
     if (batch == 0) return ACCSK_OK;
     if (n < 1 || m < 1 || ldc < m || stride_c < (n - 1) * ldc + m) return ACCSK_SHAPE;
     std::vector<accsk_problem> probs((size_t)batch);
     for (int64_t k = 0; k < batch; k++)
         probs[(size_t)k] = accsk_problem{C + k * stride_c, n, m, ldc, a + k * n, b + k * m, f_out + k * n,
                                          g_out + k * m, eps ? eps[k] : p->eps};
-    return accsk_solve_batch(probs.data(), batch, p, res, stream);
+    Workspace ws;  // stream-ordered allocations
+    if (!dres) return accsk_solve_batch_ws(probs.data(), batch, p, res, stream, ws, nullptr);
+    std::vector<accsk_result *> pub((size_t)batch);
+    for (int64_t k = 0; k < batch; k++) pub[(size_t)k] = dres + k;
+    return accsk_solve_batch_ws(probs.data(), batch, p, nullptr, stream, ws, pub.data());
+}
+
+extern "C" accsk_status accsk_solve_batch_strided(const float *C, int64_t batch, int64_t n, int64_t m, int64_t ldc,
+                                                  int64_t stride_c, const double *a, const double *b,
+                                                  const double *eps, const accsk_params *p, double *f_out,
+                                                  double *g_out, accsk_result *res, void *stream) {
+    if (!res) return ACCSK_INVALID_ARG;
+    return solve_batch_strided(C, batch, n, m, ldc, stride_c, a, b, eps, p, f_out, g_out, res, nullptr, stream);
+}
+
+extern "C" accsk_status accsk_solve_batch_strided_async(const float *C, int64_t batch, int64_t n, int64_t m,
+                                                        int64_t ldc, int64_t stride_c, const double *a,
+                                                        const double *b, const double *eps, const accsk_params *p,
+                                                        double *f_out, double *g_out, accsk_result *res,
+                                                        void *stream) {
+    if (!res) return ACCSK_INVALID_ARG;
+    return solve_batch_strided(C, batch, n, m, ldc, stride_c, a, b, eps, p, f_out, g_out, nullptr, res, stream);
 }
 
 // Upper bound of the workspace of one-workgroup launches over `count` problems

@@ -79,6 +79,7 @@ struct TiledArgs {
     int *status;
     unsigned long long *bar;
     DevResult *res;
+    accsk_result *pub;  // stream-ordered calls: the caller's device result record (else null)
     double *f_out, *g_out;
     double eps, tol, tol_stop, mu0;
     long long max_iter, m0;
@@ -163,6 +164,7 @@ __global__ __launch_bounds__(1024) void tiled_setup(const TiledArgs *__restrict_
         A.colL[j] = mx;  // first step: shift max log2 a, every term <= 1
     }
     __syncthreads();
+    if (tid < 32) A.bar[tid] = 0ull;  // the grid barrier's counter and flag lines (256 bytes)
     if (tid == 0) {
         A.gscal[0] = mx;
         A.gscal[1] = exp2(mx);
@@ -694,6 +696,11 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Stream-ordered calls: the result record, written to the caller's device memory.
+__global__ __launch_bounds__(64) void publish_tiled(const TiledArgs *__restrict__ pa, double tick_ms) {
+    if (threadIdx.x == 0 && pa->pub) publish_record(pa->pub, *pa->res, tick_ms);
+}
+
 template <int D, bool TR>
 accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res, hipStream_t s) {
     int dev = 0, cu = 0, occ = 0;
@@ -748,11 +755,15 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     A.w_rule = p->w_rule;
     A.flags = p->flags;
     TiledArgs *d_args = (TiledArgs *)(base + o_args);
+    const bool async = A.pub != nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
-    if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
-    hipError_t e = hipMemcpyAsync(d_args, &A, sizeof(TiledArgs), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(base + o_bar, 0, 256, s);
+    if (!async) {
+        if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+        if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+    }
+    // (tiled_setup also zeroes the barrier words)
+    hipError_t e = async ? upload_args(d_args, &A, sizeof(TiledArgs), s)
+                         : hipMemcpyAsync(d_args, &A, sizeof(TiledArgs), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(tiled_setup, dim3(1), dim3(1024), 0, s, (const TiledArgs *)d_args);
         e = hipGetLastError();
@@ -765,6 +776,14 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
         e = hipLaunchCooperativeKernel((const void *)tiled_solve<D, TR>, dim3((unsigned)G), dim3(kTT), kargs, lds, s);
     }
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    if (async) {
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(publish_tiled, dim3(1), dim3(64), 0, s, (const TiledArgs *)d_args, wall_tick_ms());
+            e = hipGetLastError();
+        }
+        (void)hipFreeAsync(base, s);
+        return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+    }
     DevResult hr{};
     if (e == hipSuccess) e = hipMemcpyAsync(&hr, base + o_res, sizeof(DevResult), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -784,10 +803,12 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
 using namespace accsk;
 
 // Tiled solve of one problem (explicit C when X is null, else points with d <= 16).
+// pub: null (results to *res, the call waits), or the device result record of
+// the stream-ordered form (res unused, nothing waits).
 accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, const float *Y, int64_t d, int kind,
                                double cost_scale, int64_t n, int64_t m, const double *a, const double *b,
                                const accsk_params *p, double eps, double *f_out, double *g_out, accsk_result *res,
-                               hipStream_t s) {
+                               hipStream_t s, accsk_result *pub) {
     TiledArgs A{};
     A.C = C;
     A.ldc = ldc;
@@ -803,6 +824,7 @@ accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, cons
     A.f_out = f_out;
     A.g_out = g_out;
     A.eps = eps;
+    A.pub = pub;
     accsk_status st;
     const bool tr = p->err_trace && p->trace_len > 0;
     if (!X) st = tr ? tiled_launch<0, true>(A, p, res, s) : tiled_launch<0, false>(A, p, res, s);
@@ -810,7 +832,7 @@ accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, cons
     else if (d <= 8) st = tr ? tiled_launch<8, true>(A, p, res, s) : tiled_launch<8, false>(A, p, res, s);
     else if (d <= 16) st = tr ? tiled_launch<16, true>(A, p, res, s) : tiled_launch<16, false>(A, p, res, s);
     else st = ACCSK_SHAPE;
-    if (st != ACCSK_OK) return st;
+    if (st != ACCSK_OK || pub) return st;
     return (accsk_status)res->status;
 }
 

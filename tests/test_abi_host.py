@@ -191,3 +191,21 @@ def test_host_validation_noalloc(lib):
     assert call(4, 4, 3) == accsk.SHAPE
     assert call(4, 9000, 9000) == accsk.SHAPE
     assert r.status == accsk.INVALID_ARG and r.converged == 0
+
+
+def test_host_validation_async(lib):
+    """Stream-ordered entry points: a missing record array or bad shapes fail on the host."""
+    fake = ctypes.c_void_p(4096)  # never dereferenced
+    p = accsk.default_params()
+    f = lib.accsk_solve_dense_async
+    assert f(fake, 4, 4, 4, fake, fake, ctypes.byref(p), fake, fake, None, None) == accsk.INVALID_ARG
+    assert f(fake, 0, 4, 4, fake, fake, ctypes.byref(p), fake, fake, fake, None) == accsk.SHAPE
+    assert f(fake, 4, 4, 3, fake, fake, ctypes.byref(p), fake, fake, fake, None) == accsk.SHAPE
+    bad = accsk.default_params(eps=-1.0)
+    assert f(fake, 4, 4, 4, fake, fake, ctypes.byref(bad), fake, fake, fake, None) == accsk.INVALID_ARG
+    g = lib.accsk_solve_batch_strided_async
+    assert g(fake, 2, 4, 4, 4, 16, fake, fake, None, ctypes.byref(p), fake, fake, None, None) == accsk.INVALID_ARG
+    assert g(fake, 2, 4, 4, 3, 16, fake, fake, None, ctypes.byref(p), fake, fake, fake, None) == accsk.SHAPE
+    h = accsk._points_lib().accsk_solve_points_batched_async
+    assert h(fake, fake, 2, 4, 4, 3, 0, 1.0, fake, fake, ctypes.byref(p), fake, fake, None, None) == accsk.INVALID_ARG
+    assert h(fake, fake, 2, 4, 4, 0, 0, 1.0, fake, fake, ctypes.byref(p), fake, fake, fake, None) == accsk.SHAPE
