@@ -101,6 +101,13 @@ typedef struct {
                                       rises (stability monitor), reset the extrapolation w <- alpha x.  A
                                       safeguard of this library (function-value restart), not the paper's
                                       algorithm; off by default */
+#define ACCSK_FLAG_CONDITIONS 16   /* Acc-Sinkhorn: evaluate, in FP64 at every iterate, the two boundedness
+                                      conditions of Theorem thm:condition-boundedness (App. B) with the metric
+                                      D(p(x)) of eq:D (the logarithmic mean of the column sums c and b) and the
+                                      shifted Lyapunov function of its proof, and count violations and rises
+                                      (accsk_result.cond1_violations, cond2_violations, lyap_increases).  A
+                                      monitor: the iterates are unchanged.  Costs O(m) FP64 work per step,
+                                      done by one workgroup; batches of several problems and servers refuse it */
 
 typedef struct {
     int64_t iters;          /* It: accepted iterates after x_0 (Sinkhorn: v-updates) */
@@ -109,6 +116,14 @@ typedef struct {
     int64_t fval_increases; /* stability monitor: steps at which f(x) = 1 - <u,a> - <x,b> (Lemma coercivity)
                                rose by more than 1e-8 + 1e-12 |f| over the previous iterate */
     int64_t restarts;       /* extrapolation resets done under ACCSK_FLAG_RESTART */
+    int64_t cond1_violations; /* ACCSK_FLAG_CONDITIONS: iterates at which the first condition of Theorem
+                                 thm:condition-boundedness, ||grad f(x_k)||^2 in the metric D_k^-1 D_k+1 D_k^-1
+                                 < (4 - alpha^2 - 2 alpha^(1/2)) / (2 alpha (1+alpha)^2) D_phi*(0, grad f(x_k)),
+                                 failed (pairs of consecutive iterates of one homotopy stage); -1 if not evaluated */
+    int64_t cond2_violations; /* the same for the second condition, ||v_k||^2 in the metric D_k+1 - D_k
+                                 < alpha^(3/2) ||v_k+1||^2 in D_k+1 (v = w/alpha - x) */
+    int64_t lyap_increases;   /* rises of the proof's shifted Lyapunov function f(x) + (mu/2)||v||_D^2
+                                 - theta/(1+alpha) D_phi*(0, grad f(x)) within a stage; -1 if not evaluated */
     double marginal_err;    /* eq:l1tol at the returned iterate, column part (row part is 0 by the exact row solve) */
     double eot_value;       /* dual value <f,a> + <g,b> - eps*sum P (equals the EOT optimum at
                                convergence), FP64-evaluated unless ACCSK_FLAG_NO_COST; problems that

@@ -168,14 +168,164 @@ static int stability_increase(double fval, double fprev)
     return fval > fprev + (1e-8 + 1e-12 * fabs(fval));
 }
 
-int oracle_solve_ex(int method, const double *C, int64_t n, int64_t m, double eps,
-                    const double *a, const double *b, double tol, int64_t max_iter,
-                    double mu0, int64_t m0, int w_rule, int restart,
-                    double *f, double *g, int64_t *iters, int64_t *steps, double *err_out,
-                    double *trace_err, double *trace_fval, double *trace_x,
-                    int64_t *n_increase, int64_t *n_restart)
+/*
+ * Boundedness conditions of the Acc iterates (App. B, Theorem
+ * thm:condition-boundedness) and the shifted Lyapunov function of its proof,
+ * evaluated along the run (a monitor: the solve itself is unchanged).
+ *
+ * For an iterate (x_k, w_k) with column sums c = c_P(u(x_k), x_k):
+ *   grad f(x_k) = xi = c - b                                   eq:grad-f
+ *   p = grad phi*(xi) = log(c ./ b)                            Sec. 3
+ *   D_k = diag(b (e^p - 1) ./ p) = diag(xi ./ p)               eq:D (the logarithmic mean of c_j and b_j,
+ *                                                              b_j at c_j = b_j: series for |p| < 1e-3)
+ *   K_k = D_phi*(0, xi) = sum_j (xi_j - b_j p_j) = KL(b || c)  (generalized KL; series for |p| < 1e-3)
+ *   v_k = y_k - x_k = w_k / alpha - x_k                        (w = alpha y, Sec. 4)
+ *   E_k = f(x_k) + (mu/2) ||v_k||^2_{D_k} - theta/(1+alpha) K_k,  theta = (1/2 + alpha)/(1 + alpha)
+ *     (the proof's shifted Lyapunov function with L = 1, without the constant f(x*))
+ * and for consecutive iterates (k, k+1) of one homotopy stage:
+ *   condition 1:  ||xi_k||^2_{D_k^-1 D_k+1 D_k^-1} < (4 - alpha^2 - 2 alpha^(1/2)) / (2 alpha (1+alpha)^2) K_k
+ *   condition 2:  ||v_k||^2_{D_k+1 - D_k} < alpha^(3/2) ||v_k+1||^2_{D_k+1}
+ *     (the printed ||v_k||_{D_k+1 - D_k} < alpha^(3/4) ||v_k+1||_{D_k+1}, squared; a negative left side
+ *     satisfies it)
+ *   Lyapunov rise:  E_k+1 > E_k + 1e-8 + 1e-12 |f(x_k+1)| + 1e-6 ((mu/2) ||v_k+1||^2_D + ||xi_k+1||_1)
+ *     (a noise threshold for values computed from FP32 exponentials).
+ * Both conditions are checked with the alpha the algorithm runs with (the
+ * theorem states them for alpha^2 = mu/L).  The iterate w_k is the value
+ * carried to the next x update (after a restart reset).  At a stage change the
+ * last iterate, with w as handed to the new stage and the new stage's alpha
+ * and mu, is the first iterate of the next stage.
+ */
+typedef struct {
+    int64_t m;
+    double *xi, *D, *v;   /* the last iterate's grad f, metric diagonal and v */
+    double K, E, fval;    /* its D_phi*(0, grad f), shifted Lyapunov value and f(x) */
+    int have;
+    int64_t n1, n2, nl;   /* violations of conditions 1 and 2, Lyapunov rises */
+} cond_mon;
+
+/* D_jj (eq:D) and the j-term of D_phi*(0, xi) from c_j and b_j:
+ * D = b (e^p - 1)/p = b sum_{k>=0} p^k/(k+1)!,  K = b (e^p - 1 - p) = b sum_{k>=2} p^k/k!,
+ * summed as series for |p| < 1e-2 (where e^p - 1 - p would cancel), else in closed form. */
+static void metric_terms(double c, double b, double *xi, double *D, double *K)
+{
+    *xi = c - b;
+    const double p = log1p(*xi / b);
+    if (fabs(p) < 1e-2) {
+        double term = 1.0, sd = 0.0, sk = 0.0;  /* term = p^k / (k+1)! */
+        for (int k = 0; k <= 8; k++) {
+            sd += term;
+            if (k >= 1) sk += term * p;          /* p^(k+1)/(k+1)!, k+1 >= 2 */
+            term *= p / (double)(k + 2);
+        }
+        *D = b * sd;
+        *K = b * sk;
+    } else {
+        *D = *xi / p;
+        *K = *xi - b * p;
+    }
+}
+
+static double lyap_theta(double alpha) { return (0.5 + alpha) / (1.0 + alpha); }
+
+/* The monitor's metric for given column sums: D_jj (eq:D) and the terms of
+ * D_phi*(0, c - b) (exposed for the tests that pin them). */
+void oracle_cond_metric(const double *c, const double *b, int64_t m, double *D, double *K)
+{
+    for (int64_t j = 0; j < m; j++) {
+        double xi;
+        metric_terms(c[j], b[j], &xi, &D[j], &K[j]);
+    }
+}
+
+/* The Lyapunov value of the stored iterate under (alpha, mu); v recomputed from w, x. */
+static double mon_rebase(cond_mon *M, const double *x, const double *w, double alpha, double mu)
+{
+    double vd = 0.0;
+    for (int64_t j = 0; j < M->m; j++) {
+        M->v[j] = w[j] / alpha - x[j];
+        vd += M->v[j] * M->v[j] * M->D[j];
+    }
+    M->E = M->fval + 0.5 * mu * vd - lyap_theta(alpha) / (1.0 + alpha) * M->K;
+    return M->E;
+}
+
+/* A new iterate (x, w) with column sums c; trace5 (may be NULL) receives
+ * lhs1, rhs1, lhs2, rhs2, E of this iterate (NaN where there is no predecessor). */
+static void mon_iterate(cond_mon *M, const double *x, const double *w, const double *c, const double *b,
+                        double alpha, double mu, double fval, double *trace5)
+{
+    const int64_t m = M->m;
+    double lhs1 = 0.0, lhs2 = 0.0, vd = 0.0, K = 0.0, l1 = 0.0;
+    for (int64_t j = 0; j < m; j++) {
+        double xi, D, Kj;
+        metric_terms(c[j], b[j], &xi, &D, &Kj);
+        const double v = w[j] / alpha - x[j];
+        if (M->have) {
+            lhs1 += M->xi[j] * M->xi[j] * D / (M->D[j] * M->D[j]);
+            lhs2 += M->v[j] * M->v[j] * (D - M->D[j]);
+        }
+        vd += v * v * D;
+        K += Kj;
+        l1 += fabs(xi);
+        M->xi[j] = xi;  /* the old values of column j are no longer needed */
+        M->D[j] = D;
+        M->v[j] = v;
+    }
+    const double E = fval + 0.5 * mu * vd - lyap_theta(alpha) / (1.0 + alpha) * K;
+    double rhs1 = NAN, rhs2 = NAN;
+    if (M->have) {
+        rhs1 = (4.0 - alpha * alpha - 2.0 * sqrt(alpha)) / (2.0 * alpha * (1.0 + alpha) * (1.0 + alpha)) * M->K;
+        rhs2 = pow(alpha, 1.5) * vd;
+        if (!(lhs1 < rhs1)) M->n1++;
+        if (!(lhs2 < rhs2)) M->n2++;
+        if (E > M->E + 1e-8 + 1e-12 * fabs(fval) + 1e-6 * (0.5 * mu * vd + l1)) M->nl++;
+    } else {
+        lhs1 = lhs2 = NAN;
+    }
+    if (trace5) {
+        trace5[0] = lhs1;
+        trace5[1] = rhs1;
+        trace5[2] = lhs2;
+        trace5[3] = rhs2;
+        trace5[4] = E;
+    }
+    M->K = K;
+    M->E = E;
+    M->fval = fval;
+    M->have = 1;
+}
+
+/* Column sums c_j = exp(x_j + ell_j) of the plan at (u(x), x). */
+static void col_sums(const double *x, const double *ell, int64_t m, double *c)
+{
+    for (int64_t j = 0; j < m; j++) c[j] = exp(x[j] + ell[j]);
+}
+
+/*
+ * cond_counts (may be NULL; Acc only): [0] violations of condition 1, [1] of
+ * condition 2, [2] Lyapunov rises, as the monitor above defines them.
+ * trace_cond (may be NULL; length 5 (max_iter+1)): per It the monitor's
+ * lhs1, rhs1, lhs2, rhs2, E.
+ */
+int oracle_solve_mon(int method, const double *C, int64_t n, int64_t m, double eps,
+                     const double *a, const double *b, double tol, int64_t max_iter,
+                     double mu0, int64_t m0, int w_rule, int restart,
+                     double *f, double *g, int64_t *iters, int64_t *steps, double *err_out,
+                     double *trace_err, double *trace_fval, double *trace_x,
+                     int64_t *n_increase, int64_t *n_restart, int64_t *cond_counts, double *trace_cond)
 {
     int64_t ninc = 0, nrst = 0;
+    const int mon = method != ORACLE_SINKHORN && (cond_counts || trace_cond);
+    cond_mon M;
+    memset(&M, 0, sizeof(M));
+    M.m = m;
+    double *cs = NULL;
+    if (mon) {
+        M.xi = (double *)malloc(sizeof(double) * (size_t)m);
+        M.D = (double *)malloc(sizeof(double) * (size_t)m);
+        M.v = (double *)malloc(sizeof(double) * (size_t)m);
+        cs = (double *)malloc(sizeof(double) * (size_t)m);
+    }
     double *x = (double *)calloc((size_t)m, sizeof(double));
     double *w = (double *)calloc((size_t)m, sizeof(double));
     double *S = (double *)malloc(sizeof(double) * (size_t)m);
@@ -208,6 +358,10 @@ int oracle_solve_ex(int method, const double *C, int64_t n, int64_t m, double ep
         double mu = mu0;
         int64_t mstage = m0;
         int done = (err < tol) || (it >= max_iter);
+        if (mon) {  /* iterate 0: x_0 = w_0 = 0 */
+            col_sums(x, ell, m, cs);
+            mon_iterate(&M, x, w, cs, b, sqrt(2.0 * mu), mu, fval, trace_cond);
+        }
         while (!done) {
             double alpha = sqrt(2.0 * mu);
             for (int64_t k = 0; k < mstage && !done; k++) {
@@ -225,6 +379,10 @@ int oracle_solve_ex(int method, const double *C, int64_t n, int64_t m, double ep
                 }
                 fprev = fval;
                 it++;
+                if (mon) {
+                    col_sums(x, ell, m, cs);
+                    mon_iterate(&M, x, w, cs, b, alpha, mu, fval, trace_cond ? trace_cond + 5 * it : NULL);
+                }
                 if (trace_err) trace_err[it] = err;
                 if (trace_fval) trace_fval[it] = fval;
                 if (trace_x) memcpy(trace_x + it * m, x, sizeof(double) * (size_t)m);
@@ -238,9 +396,16 @@ int oracle_solve_ex(int method, const double *C, int64_t n, int64_t m, double ep
                 }
                 mu = mu_new;
                 mstage = (int64_t)floor(sqrt(2.0) * (double)mstage) + 1;
+                if (mon) mon_rebase(&M, x, w, sqrt(2.0 * mu), mu);
             }
         }
     }
+    if (cond_counts) {
+        cond_counts[0] = mon ? M.n1 : -1;
+        cond_counts[1] = mon ? M.n2 : -1;
+        cond_counts[2] = mon ? M.nl : -1;
+    }
+    free(M.xi); free(M.D); free(M.v); free(cs);
     converged = err < tol;
     for (int64_t i = 0; i < n; i++) f[i] = eps * u[i];
     for (int64_t j = 0; j < m; j++) g[j] = eps * x[j];
@@ -251,6 +416,17 @@ int oracle_solve_ex(int method, const double *C, int64_t n, int64_t m, double ep
     if (n_restart) *n_restart = nrst;
     free(x); free(w); free(S); free(ell); free(u);
     return converged;
+}
+
+int oracle_solve_ex(int method, const double *C, int64_t n, int64_t m, double eps,
+                    const double *a, const double *b, double tol, int64_t max_iter,
+                    double mu0, int64_t m0, int w_rule, int restart,
+                    double *f, double *g, int64_t *iters, int64_t *steps, double *err_out,
+                    double *trace_err, double *trace_fval, double *trace_x,
+                    int64_t *n_increase, int64_t *n_restart)
+{
+    return oracle_solve_mon(method, C, n, m, eps, a, b, tol, max_iter, mu0, m0, w_rule, restart, f, g, iters,
+                            steps, err_out, trace_err, trace_fval, trace_x, n_increase, n_restart, NULL, NULL);
 }
 
 int oracle_solve(int method, const double *C, int64_t n, int64_t m, double eps,

@@ -75,6 +75,10 @@ def _load():
                                         _d, _d, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _d,
                                         _d, _d, _d, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
         lib.oracle_solve_ex.restype = ctypes.c_int
+        lib.oracle_solve_mon.argtypes = lib.oracle_solve_ex.argtypes + [ctypes.POINTER(_i64), _d]
+        lib.oracle_solve_mon.restype = ctypes.c_int
+        lib.oracle_cond_metric.argtypes = [_d, _d, _i64, _d, _d]
+        lib.oracle_cond_metric.restype = None
         lib.oracle_eval.argtypes = [_d, _i64, _i64, ctypes.c_double, _d, _d, _d, _d, _d, _d, _d, _d, _d]
         lib.oracle_eval.restype = None
         lib.oracle_eval_points.argtypes = [ctypes.c_int, _d, _d, _i64, _i64, _i64, ctypes.c_double,
@@ -135,11 +139,16 @@ def sstep(C, eps, a, b, x):
 
 
 def solve(C, a, b, eps, tol=1e-6, max_iter=100000, method=ACC, mu0=0.5, m0=1,
-          w_rule=W_LITERAL, trace=False, trace_x=False, normalize_marginals=True, restart=False):
+          w_rule=W_LITERAL, trace=False, trace_x=False, normalize_marginals=True, restart=False,
+          conditions=False):
     """Solve EOT(C, a, b, eps) with plain Sinkhorn or Acc-Sinkhorn (FP64).
 
     Returns a dict with f, g (potentials in cost units, g centred), iters, steps,
     err, converged and, if asked, per-iteration traces of err, f(x) and x.
+    conditions=True (Acc) adds the boundedness monitor (App. B, Theorem
+    thm:condition-boundedness): cond_counts = [violations of condition 1, of
+    condition 2, rises of the shifted Lyapunov function] and trace_cond, per It
+    the row (lhs1, rhs1, lhs2, rhs2, E).
     """
     C = _f64(C)
     n, m = C.shape
@@ -157,19 +166,35 @@ def solve(C, a, b, eps, tol=1e-6, max_iter=100000, method=ACC, mu0=0.5, m0=1,
     tx = np.empty((max_iter + 1, m)) if trace_x else None
     null = ctypes.cast(None, _d)
     ninc, nrst = _i64(), _i64()
-    conv = _load().oracle_solve_ex(int(method), _p(C), n, m, float(eps), _p(a), _p(b), float(tol),
-                                   int(max_iter), float(mu0), int(m0), int(w_rule), int(bool(restart)), _p(f),
-                                   _p(g), ctypes.byref(it), ctypes.byref(st), ctypes.byref(err),
-                                   _p(te) if trace else null, _p(tf) if trace else null,
-                                   _p(tx) if trace_x else null, ctypes.byref(ninc), ctypes.byref(nrst))
+    cc = (_i64 * 3)(-1, -1, -1)
+    tc = np.full((max_iter + 1, 5), np.nan) if conditions else None
+    conv = _load().oracle_solve_mon(int(method), _p(C), n, m, float(eps), _p(a), _p(b), float(tol),
+                                    int(max_iter), float(mu0), int(m0), int(w_rule), int(bool(restart)), _p(f),
+                                    _p(g), ctypes.byref(it), ctypes.byref(st), ctypes.byref(err),
+                                    _p(te) if trace else null, _p(tf) if trace else null,
+                                    _p(tx) if trace_x else null, ctypes.byref(ninc), ctypes.byref(nrst),
+                                    cc if conditions else ctypes.cast(None, ctypes.POINTER(_i64)),
+                                    _p(tc) if conditions else null)
     out = dict(f=f, g=g, iters=it.value, steps=st.value, err=err.value, converged=bool(conv),
                a=a, b=b, fval_increases=ninc.value, restarts=nrst.value)
+    if conditions:
+        out["cond_counts"] = [cc[0], cc[1], cc[2]]
+        out["trace_cond"] = tc[: it.value + 1].copy()
     if trace:
         out["trace_err"] = te[: it.value + 1].copy()
         out["trace_fval"] = tf[: it.value + 1].copy()
     if trace_x:
         out["trace_x"] = tx[: it.value + 1].copy()
     return out
+
+
+def cond_metric(c, b):
+    """Monitor metric for column sums c: (D diagonal of eq:D, per-column terms of D_phi*(0, c - b))."""
+    c, b = _f64(c), _f64(b)
+    D = np.empty(len(c))
+    K = np.empty(len(c))
+    _load().oracle_cond_metric(_p(c), _p(b), len(c), _p(D), _p(K))
+    return D, K
 
 
 def evaluate(C, eps, a, b, f, g):

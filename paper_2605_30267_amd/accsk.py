@@ -23,6 +23,7 @@ FLAG_NO_COST = 1
 FLAG_NO_SERPENTINE = 2
 FLAG_ON_THE_FLY = 4
 FLAG_RESTART = 8
+FLAG_CONDITIONS = 16
 
 
 class AccskError(RuntimeError):
@@ -41,7 +42,9 @@ class Params(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("sinkhorn_steps", ctypes.c_int64),
                 ("fallback_steps", ctypes.c_int64), ("fval_increases", ctypes.c_int64),
-                ("restarts", ctypes.c_int64), ("marginal_err", ctypes.c_double),
+                ("restarts", ctypes.c_int64), ("cond1_violations", ctypes.c_int64),
+                ("cond2_violations", ctypes.c_int64), ("lyap_increases", ctypes.c_int64),
+                ("marginal_err", ctypes.c_double),
                 ("eot_value", ctypes.c_double), ("transport_cost", ctypes.c_double),
                 ("dual_fval", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("converged", ctypes.c_int32),

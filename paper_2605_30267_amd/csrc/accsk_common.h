@@ -22,6 +22,7 @@ constexpr long kBarrierSpinLimit = 1L << 22;
 __device__ __attribute__((noinline)) inline double dlog2(double x) { return log2(x); }
 __device__ __attribute__((noinline)) inline double dexp2(double x) { return exp2(x); }
 __device__ __attribute__((noinline)) inline double dsqrt(double x) { return sqrt(x); }
+__device__ __attribute__((noinline)) inline double dexpm1(double x) { return expm1(x); }
 
 // Empty asm barriers that make a value opaque to the optimizer (no code emitted).
 template <typename T>
@@ -196,6 +197,127 @@ __device__ __forceinline__ bool fval_rose(double fval, double fprev) {
     return fval > fprev + (1e-8 + 1e-12 * fabs(fval));
 }
 
+// Boundedness monitor of the Acc iterates (App. B, Theorem
+// thm:condition-boundedness, and the shifted Lyapunov function of its proof),
+// evaluated under ACCSK_FLAG_CONDITIONS.  For an iterate (x_k, w_k):
+//   p = log(c ./ b) with c the column sums of P at (u(x_k), x_k),
+//   xi = grad f(x_k) = c - b = b (e^p - 1),
+//   D_k = diag(b (e^p - 1) ./ p) (eq:D: the logarithmic mean of c and b),
+//   K_k = D_phi*(0, xi) = sum_j b_j (e^p_j - 1 - p_j),
+//   v_k = w_k / alpha - x_k,
+//   E_k = f(x_k) + (mu/2) ||v_k||^2_{D_k} - theta/(1 + alpha) K_k, theta = (1/2 + alpha)/(1 + alpha),
+// and for consecutive iterates of one homotopy stage the two conditions
+//   sum xi_k^2 D_k+1 / D_k^2 < (4 - alpha^2 - 2 alpha^(1/2)) / (2 alpha (1 + alpha)^2) K_k,
+//   sum v_k^2 (D_k+1 - D_k)  < alpha^(3/2) sum v_k+1^2 D_k+1,
+// and a rise of E above 1e-8 + 1e-12 |f| + 1e-6 ((mu/2) ||v||^2_D + ||xi||_1) (the rounding of
+// values formed from FP32 exponentials).  At a stage change the last iterate, with w as handed to
+// the new stage and the new alpha and mu, starts the next stage's comparisons.
+struct CondTerms {
+    double xi, D, K;
+};
+// xi, D and K of one column from p = log(c_j / b_j): Horner forms of
+// b sum p^k/(k+1)! (D) and b sum_{k>=2} p^k/k! (K) for |p| < 1e-2, where
+// e^p - 1 - p would cancel; closed forms otherwise.
+__device__ inline CondTerms cond_terms(double p, double b) {
+    CondTerms t;
+    if (fabs(p) < 1e-2) {
+        // q = sum_{k=0..8} p^k/(k+1)!  (e^p - 1 = p q);  r = sum_{k=0..7} p^k/(k+2)!  (e^p - 1 - p = p^2 r)
+        double r = 1.0 / 3628800.0;
+        r = fma(r, p, 1.0 / 362880.0);
+        r = fma(r, p, 1.0 / 40320.0);
+        r = fma(r, p, 1.0 / 5040.0);
+        r = fma(r, p, 1.0 / 720.0);
+        r = fma(r, p, 1.0 / 120.0);
+        r = fma(r, p, 1.0 / 24.0);
+        r = fma(r, p, 1.0 / 6.0);
+        r = fma(r, p, 0.5);
+        const double q = fma(r, p, 1.0);
+        t.xi = b * p * q;
+        t.D = b * q;
+        t.K = b * p * p * r;
+    } else {
+        const double em = dexpm1(p);
+        t.xi = b * em;
+        t.D = t.xi / p;
+        t.K = b * (em - p);
+    }
+    return t;
+}
+// Running state of the monitor (identical wherever it is kept).
+struct CondState {
+    double Kb, Eb;          // the last iterate's K and E
+    long long n1, n2, nl;   // violations of conditions 1 and 2, rises of E
+};
+__device__ inline double cond_lyap(double fval, double vd, double K, double alpha, double mu) {
+    return fval + 0.5 * mu * vd - (0.5 + alpha) / ((1.0 + alpha) * (1.0 + alpha)) * K;
+}
+// One new iterate from the sums over its columns: lhs1 = sum xi_b^2 D / D_b^2,
+// lhs2 = sum v_b^2 (D - D_b), vd = sum v^2 D, K = sum K_j, l1 = sum |xi|
+// (b: the previous iterate).  have: a previous iterate of the same stage exists.
+__device__ inline void cond_decide(CondState &s, bool have, double lhs1, double lhs2, double vd, double K,
+                                   double l1, double fval, double alpha, double mu) {
+    const double E = cond_lyap(fval, vd, K, alpha, mu);
+    if (have) {
+        const double sa = dsqrt(alpha);
+        const double k1 = (4.0 - alpha * alpha - 2.0 * sa) / (2.0 * alpha * (1.0 + alpha) * (1.0 + alpha));
+        if (!(lhs1 < k1 * s.Kb)) s.n1++;
+        if (!(lhs2 < alpha * sa * vd)) s.n2++;
+        if (E > s.Eb + 1e-8 + 1e-12 * fabs(fval) + 1e-6 * (0.5 * mu * vd + l1)) s.nl++;
+    }
+    s.Kb = K;
+    s.Eb = E;
+}
+
+// The columns the monitor walks: x, w, S^ in log2 units (S^ not centred), b
+// normalized; xib, Db, vb hold grad f, D and v of the previous iterate and
+// receive those of the new one.
+struct CondCols {
+    const double *x, *w, *sh, *b;
+    double *xib, *Db, *vb;
+};
+struct CondSums {
+    double lhs1, lhs2, vd, K, l1, vd2;  // vd2: sum v^2 D with v rebased to the next stage
+};
+namespace {
+// Per-thread monitor sums over columns j0 + t, j0 + t + stride, ... < j1.  The
+// new iterate's w_k is w as stored (upd 0), (w + c2 x + 2 (sh - mean)) inv_w
+// (upd 1, the A2MD w update not yet applied) or alpha x (upd 2, a restart).
+// have: compare with the previous iterate; stage: the iterate also starts the
+// next stage (v rebased with w * ratio / a_new).  Only the diagnostic
+// instantiations of the solver kernels contain it (its FP64 transcendentals
+// would otherwise enter the register allocation of the production kernels).
+__device__ __forceinline__ CondSums cond_cols(CondCols c, long long j0, long long j1, long long stride,
+                                                        int upd, double mean, double c2, double inv_w, double alpha,
+                                                        int have, int stage, double ratio, double a_new) {
+    CondSums s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (long long j = j0; j < j1; j += stride) {
+        const double xv = c.x[j], sh = c.sh[j];
+        double w = c.w[j];
+        if (upd == 1) w = (w + c2 * xv + 2.0 * (sh - mean)) * inv_w;
+        else if (upd == 2) w = alpha * xv;
+        const CondTerms t = cond_terms((xv - sh) * kLn2, c.b[j]);
+        const double v = (w / alpha - xv) * kLn2;
+        if (have) {
+            const double xo = c.xib[j], dd = c.Db[j], vo = c.vb[j];
+            s.lhs1 += xo * xo * t.D / (dd * dd);
+            s.lhs2 += vo * vo * (t.D - dd);
+        }
+        s.vd += v * v * t.D;
+        s.K += t.K;
+        s.l1 += fabs(t.xi);
+        double vn = v;
+        if (stage) {
+            vn = (w * ratio / a_new - xv) * kLn2;
+            s.vd2 += vn * vn * t.D;
+        }
+        c.xib[j] = t.xi;
+        c.Db[j] = t.D;
+        c.vb[j] = vn;
+    }
+    return s;
+}
+}  // namespace
+
 // Device-side result record copied back to the host accsk_result.
 struct DevResult {
     long long iters;
@@ -203,6 +325,7 @@ struct DevResult {
     long long fallback;
     long long incr;      // steps at which the reduced dual objective rose (stability monitor)
     long long restarts;  // extrapolation resets (ACCSK_FLAG_RESTART)
+    long long cond1, cond2, lyap;  // boundedness monitor counts (-1: not evaluated)
     double err;
     double eot;
     double fval;
@@ -231,6 +354,9 @@ inline void fill_result(accsk_result &o, const DevResult &r, double kms) {
     o.fallback_steps = r.fallback;
     o.fval_increases = r.incr;
     o.restarts = r.restarts;
+    o.cond1_violations = r.cond1;
+    o.cond2_violations = r.cond2;
+    o.lyap_increases = r.lyap;
     o.marginal_err = r.err;
     o.eot_value = r.eot;
     o.transport_cost = r.cost;
@@ -253,6 +379,9 @@ __device__ inline void publish_record(accsk_result *o, const DevResult &r, doubl
     o->fallback_steps = r.fallback;
     o->fval_increases = r.incr;
     o->restarts = r.restarts;
+    o->cond1_violations = r.cond1;
+    o->cond2_violations = r.cond2;
+    o->lyap_increases = r.lyap;
     o->marginal_err = r.err;
     o->eot_value = r.eot;
     o->transport_cost = r.cost;

@@ -65,6 +65,7 @@ struct DenseArgs {
     double eps, kappa, tol, tol_stop, mu0;
     long long max_iter, m0;
     int method, w_rule, serpentine, restart;
+    double *cond;  // ACCSK_FLAG_CONDITIONS: [3][m] grad f, D and v of the last iterate (block 0), else null
 };
 
 // ---------------------------------------------------------------------------
@@ -190,13 +191,14 @@ __device__ __forceinline__ float f4get(const float4 &v, int e) {
 // wave owns whole rows, lane l holding columns 4 (l + 64 k) + e for k < WK
 // (m <= 256 WK); row sums stay inside the wave and the waves' column sums are
 // combined once per step.
-// TR: write the per-step error trace (trace / trace_len).  A separate
-// instantiation, so that untraced solves carry no trace code at all.
+// TR: write the per-step error trace (trace / trace_len); CD (with TR): also run
+// the boundedness monitor (ACCSK_FLAG_CONDITIONS).  Separate instantiations,
+// so that other solves carry no diagnostic code at all.
 // With 32 columns per lane (WK = 8) the wave-rows pass holds one row in
 // flight and is capped at two waves per SIMD (256 registers, a few spills):
 // 224 instead of 268 us per step on 64 problems of 2048 x 2048.  Without
 // 16-byte loads the cap would spill ~90 registers, so it applies to VEC only.
-template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false>
+template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false, bool CD = false>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(WK >= 8 && VEC ? 2 : 1)))
 void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict__ trace, long long trace_len) {
     // gp workgroups per problem; problem p owns blocks [p*gp, (p+1)*gp)
@@ -220,6 +222,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
             r.fval = NAN;
             r.cost = NAN;
             r.status = A.status[0];
+            r.cond1 = r.cond2 = r.lyap = -1;
             r.t0 = A.res->t0;
             r.t1 = dev_clock();
             *A.res = r;
@@ -271,6 +274,8 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
     // Loop-carried scalars (the same in every thread) stay in LDS between update
     // phases, so they occupy no registers during the streaming pass.
     __shared__ LoopState ls;
+    __shared__ CondState lcs;  // boundedness monitor (diagnostic instantiation, block 0)
+    if (CD && tid == 0) lcs = CondState{0.0, 0.0, 0, 0, 0};
     if (tid == 0) {
         ls.mu = A.mu0;
         ls.alpha = dsqrt(2.0 * A.mu0);
@@ -790,7 +795,7 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
             // The step's decisions are uniform, so they are taken first; then
             // one pass over the thread's columns reads S, w and x once each.
             const bool upd_w = !st.first;
-            const double alpha0 = st.alpha;
+            const double alpha0 = st.alpha, mu0s = st.mu;
             const double c2 = alpha0 * alpha0 - 2.0, inv_w = 1.0 / (1.0 + alpha0);
             bool reset = false;  // safeguard: reset the extrapolation, w <- alpha x
             if (upd_w) {
@@ -805,11 +810,13 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                 }
             }
             double ratio = 1.0;  // w scale at a stage change (exact no-op otherwise)
+            bool stage = false;
             if (st.err < A.tol_stop || st.it >= A.max_iter) {
                 stop = true;
             } else {
                 if (!st.first && st.kin == st.mstage) {
                     // Algorithm A2MD-homotopy: mu <- mu/2, m <- floor(sqrt(2) m) + 1
+                    stage = true;
                     const double mu_new = st.mu / 2.0;
                     if (A.w_rule == ACCSK_W_Y_CONTINUOUS) ratio = dsqrt(2.0 * mu_new) / st.alpha;
                     st.mu = mu_new;
@@ -818,6 +825,28 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
                     st.kin = 0;
                 }
                 st.first = 0;
+            }
+            if (CD && A.cond && bid == 0) {
+                // Boundedness monitor over all m columns, before x and w are overwritten: the new
+                // iterate is (x, w_k) with w_k the value carried to the next x update.
+                const CondCols cc{xl_lds, wl_lds, L.shat, L.bn, A.cond, A.cond + m, A.cond + 2 * m};
+                const CondSums cs = cond_cols(cc, tid, mi, TPB, upd_w ? (reset ? 2 : 1) : 0, mean, c2, inv_w,
+                                              alpha0, upd_w ? 1 : 0, stage ? 1 : 0, ratio, st.alpha);
+                const double s6[6] = {cs.lhs1, cs.lhs2, cs.vd, cs.K, cs.l1, cs.vd2};
+#pragma unroll
+                for (int q = 0; q < 6; q++) {
+                    const double v = wave_sum(s6[q]);
+                    if (lane == 0) sred[wid][q] = v;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    double r6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    for (int wq = 0; wq < NW; wq++)
+#pragma unroll
+                        for (int q = 0; q < 6; q++) r6[q] += sred[wq][q];
+                    cond_decide(lcs, upd_w, r6[0], r6[1], r6[2], r6[3], r6[4], fval, alpha0, mu0s);
+                    if (stage) lcs.Eb = cond_lyap(fval, r6[5], r6[3], st.alpha, st.mu);
+                }
             }
             const double inv_x = 1.0 / (1.0 + st.alpha);
 #pragma unroll
@@ -882,6 +911,10 @@ void dense_solve(const DenseArgs *__restrict__ probs, int gp, double *__restrict
         r.cost = NAN;
         r.converged = (status == ACCSK_OK && fin.err < A.tol_stop) ? 1 : 0;
         r.status = status;
+        const bool mon = CD && A.cond && A.method == ACCSK_ACC;
+        r.cond1 = mon ? lcs.n1 : -1;
+        r.cond2 = mon ? lcs.n2 : -1;
+        r.lyap = mon ? lcs.nl : -1;
         r.t0 = A.res->t0;
         r.t1 = dev_clock();
         *A.res = r;
@@ -1094,7 +1127,7 @@ struct HostProb {
 // when the problems carry device result records (pub), are written there by
 // the device and nothing waits.  Over a fixed workspace region, and for
 // device records, the kernel time comes from the device clock (no events).
-template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false>
+template <int TPB, int NG, int RB, bool VEC, int WK = 0, bool TR = false, bool CD = false>
 accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const accsk_params *p,
                          accsk_result *res, hipStream_t s, int num_cu, Workspace &ws) {
     const int cnt = k1 - k0;
@@ -1113,7 +1146,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     const long long mextra = WK > 0 ? mmax : 0;  // column sums of the wave-rows pass
     const size_t dyn_probe = (size_t)(2 * mmax + mextra + 5) * sizeof(double);
     ACCSK_HIP_TRY(
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC, WK, TR>, TPB, dyn_probe));
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_solve<TPB, NG, RB, VEC, WK, TR, CD>, TPB, dyn_probe));
     if (occ < 1) return ACCSK_SHAPE;
     const long long total = (long long)std::min(occ, 2) * num_cu;
     const long long want = std::max((nmax + 15) / 16, (nmax * mmax + 65535) / 65536);
@@ -1125,7 +1158,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     if (dyn > 150 * 1024) return ACCSK_SHAPE;
     int occ2 = 0;
     ACCSK_HIP_TRY(
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, dense_solve<TPB, NG, RB, VEC, WK, TR>, TPB, dyn));
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, dense_solve<TPB, NG, RB, VEC, WK, TR, CD>, TPB, dyn));
     if (occ2 < 1 || (long long)cnt * gp > (long long)occ2 * num_cu) return ACCSK_SHAPE;
 
     // workspace: shared arrays first (args, results, scalars, barriers), then per-problem slices
@@ -1136,6 +1169,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     const size_t o_stat = off; off = align_up(off + 64 * (size_t)cnt);
     const size_t o_bar = off; off = align_up(off + 256 * (size_t)cnt);
     std::vector<size_t> o_prob(cnt);
+    const bool cond = (p->flags & ACCSK_FLAG_CONDITIONS) && p->method == ACCSK_ACC;
     for (int q = 0; q < cnt; q++) {
         const HostProb &h = hp[k0 + q];
         const size_t n = h.n, m = h.m;
@@ -1145,6 +1179,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         off = align_up(off + (size_t)gp * m * 4);           // partf
         off = align_up(off + 2 * (size_t)gp * m * 8);       // part, partmax
         off = align_up(off + (2 * (size_t)gp * kNS + gp) * 8);  // bscal, uapart
+        if (cond) off = align_up(off + 3 * m * 8);          // boundedness monitor
     }
     char *base = nullptr;
     if (ws.get((void **)&base, off, s) != hipSuccess) return ACCSK_OOM;
@@ -1192,6 +1227,8 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         q0 += align_up(2 * (size_t)gp * m * 8);
         A.bscal = (double *)q0;
         A.uapart = A.bscal + 2 * (size_t)gp * kNS;
+        q0 += align_up((2 * (size_t)gp * kNS + gp) * 8);
+        A.cond = cond ? (double *)q0 : nullptr;
         A.res = (DevResult *)(base + o_res) + q;
         A.pub = h.pub;
         A.gscal = (double *)(base + o_gscal) + 8 * q;
@@ -1218,7 +1255,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
         double *tr = TR ? p->err_trace : nullptr;  // traced launches hold one problem
         long long tl = TR ? p->trace_len : 0;
         void *kargs[] = {&d_args, &gpi, &tr, &tl};
-        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, RB, VEC, WK, TR>, dim3((unsigned)(cnt * gp)),
+        e = hipLaunchCooperativeKernel((const void *)dense_solve<TPB, NG, RB, VEC, WK, TR, CD>, dim3((unsigned)(cnt * gp)),
                                        dim3(TPB), kargs, dyn, s);
     }
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
@@ -1255,7 +1292,7 @@ accsk_status dense_chunk(const std::vector<HostProb> &hp, int k0, int k1, const 
     return ACCSK_OK;
 }
 
-template <bool VEC, bool TR>
+template <bool VEC, bool TR, bool CD>
 accsk_status dense_chunk_cfg_t(long long mmax, const std::vector<HostProb> &hp, int k0, int k1,
                                const accsk_params *p, accsk_result *res, hipStream_t s, int cu, Workspace &ws) {
     // Up to 1024 columns each wave owns whole rows (4 to 16 columns per lane):
@@ -1263,26 +1300,29 @@ accsk_status dense_chunk_cfg_t(long long mmax, const std::vector<HostProb> &hp, 
     // cross-wave row reductions cost more than the row's arithmetic.  With
     // 2048 columns the wave-rows kernel needs 328 registers (one wave per SIMD):
     // it wins only when a launch holds 16 or more problems (never a traced one).
-    if (mmax <= 256) return dense_chunk<256, 1, 1, VEC, 1, TR>(hp, k0, k1, p, res, s, cu, ws);
-    if (mmax <= 512) return dense_chunk<256, 1, 1, VEC, 2, TR>(hp, k0, k1, p, res, s, cu, ws);
-    if (mmax <= 1024) return dense_chunk<256, 1, 1, VEC, 4, TR>(hp, k0, k1, p, res, s, cu, ws);
+    if (mmax <= 256) return dense_chunk<256, 1, 1, VEC, 1, TR, CD>(hp, k0, k1, p, res, s, cu, ws);
+    if (mmax <= 512) return dense_chunk<256, 1, 1, VEC, 2, TR, CD>(hp, k0, k1, p, res, s, cu, ws);
+    if (mmax <= 1024) return dense_chunk<256, 1, 1, VEC, 4, TR, CD>(hp, k0, k1, p, res, s, cu, ws);
     if (mmax <= 2048) {
         if constexpr (!TR)
             if (k1 - k0 >= 16) return dense_chunk<256, 2, 1, VEC, 8>(hp, k0, k1, p, res, s, cu, ws);
-        return dense_chunk<512, 1, 4, VEC, 0, TR>(hp, k0, k1, p, res, s, cu, ws);
+        return dense_chunk<512, 1, 4, VEC, 0, TR, CD>(hp, k0, k1, p, res, s, cu, ws);
     }
-    if (mmax <= 4096) return dense_chunk<1024, 1, 2, VEC, 0, TR>(hp, k0, k1, p, res, s, cu, ws);
-    return dense_chunk<1024, 2, 1, VEC, 0, TR>(hp, k0, k1, p, res, s, cu, ws);
+    if (mmax <= 4096) return dense_chunk<1024, 1, 2, VEC, 0, TR, CD>(hp, k0, k1, p, res, s, cu, ws);
+    return dense_chunk<1024, 2, 1, VEC, 0, TR, CD>(hp, k0, k1, p, res, s, cu, ws);
 }
 
-// A launch with the per-step trace holds one problem (the batch entry points
-// refuse a trace for several) and runs the traced instantiation.
+// A launch with the per-step trace or the boundedness monitor holds one
+// problem (the batch entry points refuse them for several) and runs the
+// diagnostic instantiation.
 template <bool VEC>
 accsk_status dense_chunk_cfg(long long mmax, const std::vector<HostProb> &hp, int k0, int k1,
                              const accsk_params *p, accsk_result *res, hipStream_t s, int cu, Workspace &ws) {
+    if ((p->flags & ACCSK_FLAG_CONDITIONS) && p->method == ACCSK_ACC && k1 - k0 == 1)
+        return dense_chunk_cfg_t<VEC, true, true>(mmax, hp, k0, k1, p, res, s, cu, ws);
     if (p->err_trace && p->trace_len > 0 && k1 - k0 == 1)
-        return dense_chunk_cfg_t<VEC, true>(mmax, hp, k0, k1, p, res, s, cu, ws);
-    return dense_chunk_cfg_t<VEC, false>(mmax, hp, k0, k1, p, res, s, cu, ws);
+        return dense_chunk_cfg_t<VEC, true, false>(mmax, hp, k0, k1, p, res, s, cu, ws);
+    return dense_chunk_cfg_t<VEC, false, false>(mmax, hp, k0, k1, p, res, s, cu, ws);
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -1363,7 +1403,7 @@ accsk_status accsk_dense_multi(const accsk_problem *probs, int64_t count, const 
 }
 
 size_t accsk_tiled_workspace_bound(int64_t n, int64_t m, int cu);
-size_t accsk_small_workspace_bound(int64_t count);
+size_t accsk_small_workspace_bound(int64_t count, int64_t m);
 
 // Upper bound of the workspace of the FP64 evaluation pass (run_eval) on n x m.
 static size_t eval_workspace_bound(long long m) { return (size_t)(64 * m + 3 * 1024 + m) * 8 + 256; }
@@ -1376,12 +1416,13 @@ size_t accsk_dense_single_bound(int64_t n, int64_t m, int cu) {
     const size_t un = (size_t)n, um = (size_t)m;
     const size_t eval = align_up(((size_t)std::min<int64_t>(n, 64) * um + (size_t)std::min<int64_t>(n, 1024) * 3 + um) * 8);
     // one workgroup: descriptors and results, then (released) the FP64 re-evaluation
-    const size_t small = std::max(align_up(accsk_small_workspace_bound(1)), align_up((un + um + 8) * 8) + eval);
+    const size_t small = std::max(align_up(accsk_small_workspace_bound(1, m)), align_up((un + um + 8) * 8) + eval);
     // cooperative launch of one problem, gp <= min(CUs, n) workgroups, plus the evaluation
     const size_t gp = (size_t)std::max<int64_t>(1, std::min<int64_t>(cu, n));
     const size_t coop = align_up(align_up(sizeof(DenseArgs)) + align_up(sizeof(DevResult)) + align_up(8 * 8) +
                                  align_up(64) + align_up(256) + align_up(4 * un * 8) + align_up(3 * um * 8) +
-                                 align_up(gp * um * 4) + align_up(2 * gp * um * 8) + align_up((2 * gp * kNS + gp) * 8)) +
+                                 align_up(gp * um * 4) + align_up(2 * gp * um * 8) + align_up((2 * gp * kNS + gp) * 8) +
+                                 align_up(3 * um * 8)) +
                         eval;
     return std::max(small, coop);
 }
@@ -1393,13 +1434,13 @@ extern "C" accsk_status accsk_workspace_bytes(int64_t n, int64_t m, int64_t coun
     const int cu = device_cu_count();
     if (cu <= 0) return ACCSK_HIP_ERROR;
     // one-workgroup launches (+ the FP64 re-evaluation of a single problem)
-    size_t b = accsk_small_workspace_bound(count) + (size_t)(n + m + 8) * 8 + eval_workspace_bound(m);
+    size_t b = accsk_small_workspace_bound(count, m) + (size_t)(n + m + 8) * 8 + eval_workspace_bound(m);
     if (m <= 8192) {
         // one cooperative launch holds k <= min(count, CUs) problems with k * gp <= 2 CUs
         const size_t k = (size_t)std::min<int64_t>(count, cu), G = 2 * (size_t)cu;
         size_t d = align_up(sizeof(DenseArgs) * k) + align_up(sizeof(DevResult) * k) + align_up(64 * k) +
                    align_up(64 * k) + align_up(256 * k);
-        d += k * (align_up(4 * (size_t)n * 8) + align_up(3 * (size_t)m * 8) + 3 * 256);
+        d += k * (align_up(4 * (size_t)n * 8) + 2 * align_up(3 * (size_t)m * 8) + 3 * 256);  // (+ the monitor)
         d += G * (size_t)m * (4 + 16) + (2 * G * kNS + G) * 8 + 2 * k * 256;
         d += eval_workspace_bound(m);  // allocated while the launch's workspace is still held
         b = std::max(b, d);

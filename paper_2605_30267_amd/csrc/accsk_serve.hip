@@ -417,6 +417,7 @@ struct accsk_server {
             r.res.fallback_steps = d.fallback;
             r.res.fval_increases = d.incr;
             r.res.restarts = d.restarts;
+            r.res.cond1_violations = r.res.cond2_violations = r.res.lyap_increases = -1;  // not evaluated here
             r.res.marginal_err = d.err;
             r.res.eot_value = d.eot;
             r.res.transport_cost = d.cost;
@@ -544,6 +545,7 @@ extern "C" accsk_status accsk_server_create(size_t hbm_budget, int max_slots, co
     if (!out || !p) return ACCSK_INVALID_ARG;
     *out = nullptr;
     if (p->err_trace || p->trace_len != 0) return ACCSK_INVALID_ARG;  // no per-step trace when serving
+    if (p->flags & ACCSK_FLAG_CONDITIONS) return ACCSK_INVALID_ARG;    // nor the boundedness monitor
     SmallCtl ctl;
     accsk_status st = small_ctl_from_params(p, &ctl);
     if (st != ACCSK_OK) return st;

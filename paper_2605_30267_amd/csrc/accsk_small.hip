@@ -13,30 +13,32 @@
 namespace accsk {
 namespace {
 
-template <int NW, int LPR, int NCL, bool VEC>
+template <int NW, int LPR, int NCL, bool VEC, bool DG>
 __global__ __launch_bounds__(64 * NW) void small_solve(const SmallProb *__restrict__ probs, SmallCtl ctl,
                                                        DevResult *__restrict__ results) {
     extern __shared__ double lds[];
     __shared__ double red[NW];
     __shared__ int sflag;
-    small_body<NW, LPR, NCL, VEC>(probs[blockIdx.x], ctl, results + blockIdx.x, lds, red, sflag);
+    small_body<NW, LPR, NCL, VEC, DG>(probs[blockIdx.x], ctl, results + blockIdx.x, lds, red, sflag);
 }
 
-template <int NW, int LPR, int NCL, bool VEC>
+template <int NW, int LPR, int NCL, bool VEC, bool DG>
 hipError_t launch_small(const SmallProb *d_probs, int count, const SmallCtl &ctl, DevResult *d_res, size_t lds,
                         hipStream_t s) {
-    hipLaunchKernelGGL((small_solve<NW, LPR, NCL, VEC>), dim3(count), dim3(64 * NW), lds, s, d_probs, ctl, d_res);
+    hipLaunchKernelGGL((small_solve<NW, LPR, NCL, VEC, DG>), dim3(count), dim3(64 * NW), lds, s, d_probs, ctl,
+                       d_res);
     return hipGetLastError();
 }
 
-template <bool VEC>
+// DG: the diagnostic instantiation (boundedness monitor).
+template <bool VEC, bool DG>
 hipError_t launch_small_cfg(long long mmax, const SmallProb *d_probs, int count, const SmallCtl &ctl,
                             DevResult *d_res, size_t lds, hipStream_t s) {
-    if (mmax <= 64) return launch_small<4, 16, 4, VEC>(d_probs, count, ctl, d_res, lds, s);
-    if (mmax <= 128) return launch_small<4, 16, 8, VEC>(d_probs, count, ctl, d_res, lds, s);
-    if (mmax <= 256) return launch_small<4, 16, 16, VEC>(d_probs, count, ctl, d_res, lds, s);
-    if (mmax <= 512) return launch_small<4, 64, 8, VEC>(d_probs, count, ctl, d_res, lds, s);
-    return launch_small<4, 64, 16, VEC>(d_probs, count, ctl, d_res, lds, s);
+    if (mmax <= 64) return launch_small<4, 16, 4, VEC, DG>(d_probs, count, ctl, d_res, lds, s);
+    if (mmax <= 128) return launch_small<4, 16, 8, VEC, DG>(d_probs, count, ctl, d_res, lds, s);
+    if (mmax <= 256) return launch_small<4, 16, 16, VEC, DG>(d_probs, count, ctl, d_res, lds, s);
+    if (mmax <= 512) return launch_small<4, 64, 8, VEC, DG>(d_probs, count, ctl, d_res, lds, s);
+    return launch_small<4, 64, 16, VEC, DG>(d_probs, count, ctl, d_res, lds, s);
 }
 
 // Stream-ordered calls: each problem's result record, written to the caller's device memory.
@@ -92,17 +94,30 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
         mmax = std::max<long long>(mmax, q.m);
         lds = std::max(lds, small_lds_bytes(q.n, q.m, 4));
         vec = vec && (q.m % 4 == 0) && (q.ldc % 4 == 0) && ((((uintptr_t)q.C) & 15) == 0);
-        hp[(size_t)k] = SmallProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps, q.m - 4};
+        hp[(size_t)k] = SmallProb{q.C, q.n, q.m, q.ldc, q.a, q.b, q.f, q.g, q.eps, q.m - 4, nullptr};
     }
     if (lds > kSmallLdsMax) return ACCSK_SHAPE;
     const size_t bytes_p = sizeof(SmallProb) * (size_t)count, bytes_r = sizeof(DevResult) * (size_t)count;
     const bool async = !pub.empty();
     const size_t bytes_q = async ? sizeof(accsk_result *) * (size_t)count : 0;
+    // boundedness monitor: [3][m] doubles per problem
+    const bool cond = (ctl.flags & ACCSK_FLAG_CONDITIONS) && ctl.method == ACCSK_ACC;
+    size_t bytes_c = 0;
+    if (cond)
+        for (int64_t k = 0; k < count; k++) bytes_c += 3 * (size_t)hp[(size_t)k].m * sizeof(double);
     const size_t o_res = (bytes_p + 255) & ~size_t(255), o_pub = (o_res + bytes_r + 255) & ~size_t(255);
+    const size_t o_cond = (o_pub + bytes_q + 255) & ~size_t(255);
     char *buf = nullptr;
-    if (ws.get((void **)&buf, o_pub + bytes_q + 256, s) != hipSuccess) return ACCSK_OOM;
+    if (ws.get((void **)&buf, o_cond + bytes_c + 256, s) != hipSuccess) return ACCSK_OOM;
     SmallProb *d_probs = (SmallProb *)buf;
     DevResult *d_res = (DevResult *)(buf + o_res);
+    if (cond) {
+        double *cp = (double *)(buf + o_cond);
+        for (int64_t k = 0; k < count; k++) {
+            hp[(size_t)k].cond = cp;
+            cp += 3 * hp[(size_t)k].m;
+        }
+    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (!ws.fixed() && !async) {
         if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
@@ -112,8 +127,10 @@ static accsk_status solve_small_batch(const std::vector<accsk_problem> &probs, c
                          : hipMemcpyAsync(d_probs, hp.data(), bytes_p, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
     if (e == hipSuccess)
-        e = vec ? launch_small_cfg<true>(mmax, d_probs, (int)count, ctl, d_res, lds, s)
-                : launch_small_cfg<false>(mmax, d_probs, (int)count, ctl, d_res, lds, s);
+        e = cond ? (vec ? launch_small_cfg<true, true>(mmax, d_probs, (int)count, ctl, d_res, lds, s)
+                        : launch_small_cfg<false, true>(mmax, d_probs, (int)count, ctl, d_res, lds, s))
+                 : (vec ? launch_small_cfg<true, false>(mmax, d_probs, (int)count, ctl, d_res, lds, s)
+                        : launch_small_cfg<false, false>(mmax, d_probs, (int)count, ctl, d_res, lds, s));
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     if (async) {
         accsk_result **d_pub = (accsk_result **)(buf + o_pub);
@@ -148,6 +165,7 @@ accsk_status accsk_solve_batch_ws(const accsk_problem *probs, int64_t count, con
     if (!probs || !(res || pub) || !p || count < 0) return ACCSK_INVALID_ARG;
     if (count == 0) return ACCSK_OK;
     if (p->err_trace && count > 1) return ACCSK_INVALID_ARG;  // one trace buffer: one problem
+    if ((p->flags & ACCSK_FLAG_CONDITIONS) && count > 1) return ACCSK_INVALID_ARG;  // the monitor: one problem
     SmallCtl ctl;
     accsk_status st = small_ctl_from_params(p, &ctl);
     if (st != ACCSK_OK) return st;
@@ -246,6 +264,8 @@ extern "C" accsk_status accsk_solve_batch_strided_async(const float *C, int64_t 
 
 // Upper bound of the workspace of one-workgroup launches over `count` problems
 // (descriptors and result records).
-size_t accsk_small_workspace_bound(int64_t count) {
-    return sizeof(SmallProb) * (size_t)count + sizeof(DevResult) * (size_t)count + 512;
+// (descriptors, result records, device record pointers and the boundedness monitor's [3][m] doubles).
+size_t accsk_small_workspace_bound(int64_t count, int64_t m) {
+    return (sizeof(SmallProb) + sizeof(DevResult) + sizeof(void *) + 3 * (size_t)m * sizeof(double)) * (size_t)count +
+           1024;
 }

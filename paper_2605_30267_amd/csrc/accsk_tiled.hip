@@ -30,6 +30,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "accsk_common.h"
@@ -84,6 +85,16 @@ struct TiledArgs {
     double eps, tol, tol_stop, mu0;
     long long max_iter, m0;
     int method, w_rule, flags;
+    double *cond;   // ACCSK_FLAG_CONDITIONS (Acc): [3][m] grad f, D and v of the last iterate (slice-owned)
+    double *cscal;  // [2][G][8] per-block sums of the boundedness monitor, by step parity
+};
+
+// Boundedness monitor of the tiled solver: every block sums its column slice;
+// block 0 takes the decision after the next grid barrier, when all sums are in.
+struct CondPending {
+    CondState cs;
+    double fval, alpha, mu, a_new, mu_new;
+    int have, stage, par, valid;
 };
 
 __device__ double tblock_sum(double v, double *red) {
@@ -182,7 +193,7 @@ __device__ __forceinline__ double readlane63_f64(double v) {
 
 // TR: write the per-step error trace (trace / trace_len).  A separate
 // instantiation, so that untraced solves carry no trace code at all.
-template <int D, bool TR = false>
+template <int D, bool TR = false, bool CD = false>
 __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__ pa, double *__restrict__ trace,
                                                    long long trace_len) {
     using Cf = TCfg<D>;
@@ -192,6 +203,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
     __shared__ double tot[kTNS];
     __shared__ double sred[kTW * 64];
     __shared__ int bflag, sflag;
+    __shared__ CondPending cpend;  // used by block 0 only
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int G = gridDim.x, bid = blockIdx.x;
@@ -203,6 +215,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
             r.fval = NAN;
             r.cost = NAN;
             r.status = A.status[0];
+            r.cond1 = r.cond2 = r.lyap = -1;
             r.t0 = A.res->t0;
             r.t1 = dev_clock();
             *A.res = r;
@@ -451,6 +464,24 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
     unsigned long long gen = 0;
     int status = ACCSK_OK;
     double err = 0.0, last_mass = 0.0, last_xb2 = 0.0, eot = 0.0, fval = 0.0, cost_total = NAN;
+    const bool mon = CD && A.cond != nullptr && A.method == ACCSK_ACC;  // diagnostic instantiation only
+    if (mon && bid == 0 && tid == 0) {
+        cpend.cs = CondState{0.0, 0.0, 0, 0, 0};
+        cpend.valid = 0;
+    }
+    // Block 0, after a grid barrier: the decision for the iterate whose slice sums are complete.
+    auto cond_settle = [&]() {
+        if (!(mon && bid == 0 && tid == 0 && cpend.valid)) return;
+        const double *cs = A.cscal + (size_t)cpend.par * G * 8;
+        double r6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < G; b++)
+            for (int q = 0; q < 6; q++) r6[q] += xload(&cs[(size_t)b * 8 + q]);
+        CondState c = cpend.cs;
+        cond_decide(c, cpend.have != 0, r6[0], r6[1], r6[2], r6[3], r6[4], cpend.fval, cpend.alpha, cpend.mu);
+        if (cpend.stage) c.Eb = cond_lyap(cpend.fval, r6[5], r6[3], cpend.a_new, cpend.mu_new);
+        cpend.cs = c;
+        cpend.valid = 0;
+    };
 
     for (long long step = 0;; step++) {
         const int par = (int)(step & 1);
@@ -458,6 +489,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         row_sweep();
         col_sweep(false);
         if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
+        cond_settle();
 
         bool exact = false;
         for (int pass = 0; pass < 2; pass++) {
@@ -606,6 +638,32 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                     }
                 }
             }
+            if (CD && mon) {
+                // Boundedness monitor over this block's columns (each thread reads the columns it
+                // updated above); the new iterate is (x, w_k) with w_k as carried to the next x update
+                const bool stage = !(err < A.tol_stop || it >= A.max_iter) && !first && kin == mstage;
+                const double a_new = dsqrt(mu), ratio = A.w_rule == ACCSK_W_Y_CONTINUOUS ? a_new / alpha : 1.0;
+                const CondCols cc{A.xg, A.wg, A.shat, A.bn, A.cond, A.cond + m, A.cond + 2 * m};
+                const CondSums cv = cond_cols(cc, j0 + tid, j1, kTT, 0, 0.0, 0.0, 0.0, alpha, first ? 0 : 1,
+                                              stage ? 1 : 0, ratio, a_new);
+                double s6[6] = {cv.lhs1, cv.lhs2, cv.vd, cv.K, cv.l1, cv.vd2};
+                for (int q = 0; q < 6; q++) s6[q] = tblock_sum(s6[q], sred);
+                if (tid == 0) {
+                    double *cs = A.cscal + ((size_t)par * G + bid) * 8;
+                    for (int q = 0; q < 6; q++) xstore(&cs[q], s6[q]);
+                    if (bid == 0) {
+                        cpend.fval = fval;
+                        cpend.alpha = alpha;
+                        cpend.mu = mu;
+                        cpend.a_new = a_new;
+                        cpend.mu_new = 0.5 * mu;
+                        cpend.have = first ? 0 : 1;
+                        cpend.stage = stage ? 1 : 0;
+                        cpend.par = par;
+                        cpend.valid = 1;
+                    }
+                }
+            }
             if (err < A.tol_stop || it >= A.max_iter) stop = true;
             else {
                 if (!first && kin == mstage) {
@@ -663,6 +721,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
             xstore(&A.costpart[bid], cst);
         }
         if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) status = ACCSK_HIP_ERROR;
+        if (status != ACCSK_HIP_ERROR) cond_settle();  // the last iterate
         if (bid == 0 && tid == 0 && status != ACCSK_HIP_ERROR) {
             double ua2 = 0.0, c2 = 0.0;
             for (int b = 0; b < G; b++) {
@@ -688,6 +747,9 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         r.cost = cost_total;
         r.converged = (status == ACCSK_OK && err < A.tol_stop) ? 1 : 0;
         r.status = status;
+        r.cond1 = mon ? cpend.cs.n1 : -1;
+        r.cond2 = mon ? cpend.cs.n2 : -1;
+        r.lyap = mon ? cpend.cs.nl : -1;
         r.t0 = A.res->t0;
         r.t1 = dev_clock();
         *A.res = r;
@@ -701,13 +763,13 @@ __global__ __launch_bounds__(64) void publish_tiled(const TiledArgs *__restrict_
     if (threadIdx.x == 0 && pa->pub) publish_record(pa->pub, *pa->res, tick_ms);
 }
 
-template <int D, bool TR>
+template <int D, bool TR, bool CD>
 accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res, hipStream_t s) {
     int dev = 0, cu = 0, occ = 0;
     ACCSK_HIP_TRY(hipGetDevice(&dev));
     ACCSK_HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
     const size_t lds = tiled_lds_bytes<D>();
-    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tiled_solve<D, TR>, kTT, lds));
+    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tiled_solve<D, TR, CD>, kTT, lds));
     if (occ < 1) return ACCSK_SHAPE;
     const long long G = (long long)std::min(occ, 2) * cu;
     const size_t n = A.n, m = A.m;
@@ -721,6 +783,8 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     const size_t o_pf = off; off = align_up(off + (size_t)G * m * 4);
     const size_t o_pe = off; off = align_up(off + 2 * (size_t)G * m * 8);
     const size_t o_bs = off; off = align_up(off + (2 * (size_t)G * kTNS + 2 * (size_t)G) * 8);
+    const bool cond = (p->flags & ACCSK_FLAG_CONDITIONS) && p->method == ACCSK_ACC;
+    const size_t o_cond = off; off = align_up(off + (cond ? (3 * m + 2 * (size_t)G * 8) * 8 : 0));
     char *base = nullptr;
     if (hipMallocAsync((void **)&base, off, s) != hipSuccess) return ACCSK_OOM;
     double *pn = (double *)(base + o_n), *pm = (double *)(base + o_m);
@@ -746,6 +810,8 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     A.status = (int *)(A.gscal + 8);
     A.bar = (unsigned long long *)(base + o_bar);
     A.res = (DevResult *)(base + o_res);
+    A.cond = cond ? (double *)(base + o_cond) : nullptr;
+    A.cscal = cond ? A.cond + 3 * m : nullptr;
     A.tol = p->tol;
     A.tol_stop = p->tol * (1.0 - 1.0 / 16.0);
     A.mu0 = p->mu0;
@@ -773,7 +839,7 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
         double *tr = TR ? p->err_trace : nullptr;
         long long tl = TR ? p->trace_len : 0;
         void *kargs[] = {&d_args, &tr, &tl};
-        e = hipLaunchCooperativeKernel((const void *)tiled_solve<D, TR>, dim3((unsigned)G), dim3(kTT), kargs, lds, s);
+        e = hipLaunchCooperativeKernel((const void *)tiled_solve<D, TR, CD>, dim3((unsigned)G), dim3(kTT), kargs, lds, s);
     }
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     if (async) {
@@ -827,10 +893,17 @@ accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, cons
     A.pub = pub;
     accsk_status st;
     const bool tr = p->err_trace && p->trace_len > 0;
-    if (!X) st = tr ? tiled_launch<0, true>(A, p, res, s) : tiled_launch<0, false>(A, p, res, s);
-    else if (d <= 3) st = tr ? tiled_launch<3, true>(A, p, res, s) : tiled_launch<3, false>(A, p, res, s);
-    else if (d <= 8) st = tr ? tiled_launch<8, true>(A, p, res, s) : tiled_launch<8, false>(A, p, res, s);
-    else if (d <= 16) st = tr ? tiled_launch<16, true>(A, p, res, s) : tiled_launch<16, false>(A, p, res, s);
+    const bool cd = (p->flags & ACCSK_FLAG_CONDITIONS) && p->method == ACCSK_ACC;
+    // diagnostic instantiations: the per-step trace; the boundedness monitor (with the trace code)
+    auto launch = [&](auto dtag) {
+        constexpr int DD = decltype(dtag)::value;
+        if (cd) return tiled_launch<DD, true, true>(A, p, res, s);
+        return tr ? tiled_launch<DD, true, false>(A, p, res, s) : tiled_launch<DD, false, false>(A, p, res, s);
+    };
+    if (!X) st = launch(std::integral_constant<int, 0>{});
+    else if (d <= 3) st = launch(std::integral_constant<int, 3>{});
+    else if (d <= 8) st = launch(std::integral_constant<int, 8>{});
+    else if (d <= 16) st = launch(std::integral_constant<int, 16>{});
     else st = ACCSK_SHAPE;
     if (st != ACCSK_OK || pub) return st;
     return (accsk_status)res->status;
@@ -843,5 +916,6 @@ size_t accsk_tiled_workspace_bound(int64_t n, int64_t m, int cu) {
     const size_t G = 2 * (size_t)cu;
     return align_up(sizeof(TiledArgs)) + align_up(sizeof(DevResult)) + align_up(64 * 8) + align_up(256) +
            align_up(5 * (size_t)n * 8) + align_up(7 * (size_t)m * 8) + align_up(G * (size_t)m * 4) +
-           align_up(2 * G * (size_t)m * 8) + align_up((2 * G * kTNS + 2 * G) * 8);
+           align_up(2 * G * (size_t)m * 8) + align_up((2 * G * kTNS + 2 * G) * 8) +
+           align_up((3 * (size_t)m + 2 * G * 8) * 8);
 }

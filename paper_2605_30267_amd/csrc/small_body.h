@@ -32,6 +32,7 @@ struct SmallProb {
     double *f, *g;
     double eps;
     long long vlim;  // VEC loads: last float4 start inside every row (m - 4, or ldc - 4 for padded rows)
+    double *cond;    // ACCSK_FLAG_CONDITIONS (Acc): [3][m] grad f, D and v of the last iterate, else null
 };
 
 struct SmallCtl {
@@ -105,7 +106,9 @@ __device__ __forceinline__ double wg_max(double v, double *red) {
 // The solve of one problem by one workgroup of 64*NW threads.  lds: dynamic
 // on-chip memory of small_lds_bytes(n, m, NW); red: NW doubles; sflag: one int
 // (both on-chip).  The result record is written by thread 0 to *res.
-template <int NW, int LPR, int NCL, bool VEC>
+// DG: the diagnostic instantiation, which also runs the boundedness monitor
+// (P.cond, ACCSK_FLAG_CONDITIONS); other instantiations carry none of its code.
+template <int NW, int LPR, int NCL, bool VEC, bool DG = false>
 __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &ctl, DevResult *res, double *lds,
                                            double *red, int &sflag) {
     constexpr int TPB = 64 * NW;
@@ -158,6 +161,7 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
             r.fval = NAN;
             r.cost = NAN;
             r.status = (badall & 2) ? ACCSK_NONFINITE : ACCSK_INVALID_ARG;
+            r.cond1 = r.cond2 = r.lyap = -1;
             r.t0 = res->t0;
             r.t1 = dev_clock();
             *res = r;
@@ -189,6 +193,8 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
     int status = ACCSK_OK;
     double err = 0.0, mass = 0.0, xb2 = 0.0;
     const int nrows_iter = (n + RS - 1) / RS;
+    const bool mon = DG && P.cond != nullptr && ctl.method == ACCSK_ACC;
+    CondState cs{0.0, 0.0, 0, 0, 0};
 
     for (;;) {
         // ---------------- strip: row solve and column sums from one read ----------------
@@ -373,6 +379,19 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
                     }
                 }
             }
+            if (DG && mon) {  // (every thread reads only the columns it wrote in the update above)
+                // Boundedness monitor: the new iterate is (x, w_k), w_k as carried to the next x update
+                const bool stage = !(err < ctl.tol_stop || it >= ctl.max_iter) && !first && kin == mstage;
+                const double a_new = dsqrt(mu), ratio = ctl.w_rule == ACCSK_W_Y_CONTINUOUS ? a_new / alpha : 1.0;
+                const CondCols cc{xl, wl, wpart, bn, P.cond, P.cond + m, P.cond + 2 * m};
+                const CondSums cv = cond_cols(cc, tid, m, TPB, 0, 0.0, 0.0, 0.0, alpha, first ? 0 : 1,
+                                              stage ? 1 : 0, ratio, a_new);
+                double s6[6] = {cv.lhs1, cv.lhs2, cv.vd, cv.K, cv.l1, cv.vd2};
+#pragma unroll
+                for (int q = 0; q < 6; q++) s6[q] = wg_sum<NW>(s6[q], red);
+                cond_decide(cs, !first, s6[0], s6[1], s6[2], s6[3], s6[4], fval, alpha, mu);
+                if (stage) cs.Eb = cond_lyap(fval, s6[5], s6[3], a_new, 0.5 * mu);
+            }
             if (err < ctl.tol_stop || it >= ctl.max_iter) break;
             if (!first && kin == mstage) {
                 const double mu_new = mu / 2.0;
@@ -431,6 +450,9 @@ __device__ __forceinline__ void small_body(const SmallProb &P, const SmallCtl &c
         r.cost = (ctl.flags & ACCSK_FLAG_NO_COST) ? NAN : cst;
         r.converged = (status == ACCSK_OK && err < ctl.tol_stop) ? 1 : 0;
         r.status = status;
+        r.cond1 = mon ? cs.n1 : -1;
+        r.cond2 = mon ? cs.n2 : -1;
+        r.lyap = mon ? cs.nl : -1;
         r.t0 = res->t0;
         r.t1 = dev_clock();
         *res = r;
