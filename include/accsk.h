@@ -96,7 +96,9 @@ typedef struct {
 #define ACCSK_FLAG_NO_COST 1       /* skip the final <C,P> pass */
 #define ACCSK_FLAG_NO_SERPENTINE 2 /* traverse C in the same row order every step */
 #define ACCSK_FLAG_ON_THE_FLY 4    /* point-cloud solves: form C_ij on the fly in every step (never stored);
-                                      implied when m > 8192; needs d <= 16 */
+                                      implied when m > 8192.  FP64 dot products for d <= 16; the BF16
+                                      matrix-core cross term of p->split (2 or 3) pieces for 16 < d <= 128
+                                      (split 0 with d > 16 is SHAPE) */
 #define ACCSK_FLAG_RESTART 8       /* Acc-Sinkhorn: when the reduced dual objective f(x) = 1 - <u,a> - <x,b>
                                       rises (stability monitor), reset the extrapolation w <- alpha x.  A
                                       safeguard of this library (function-value restart), not the paper's
@@ -308,9 +310,13 @@ accsk_status accsk_cost_points(const float *X, const float *Y, int64_t n, int64_
  * p->split) into library scratch memory and solves EOT on it.  a, b, f_out,
  * g_out as for accsk_solve_dense.  With ACCSK_FLAG_ON_THE_FLY, or when
  * m > 8192, the cost is instead formed on the fly in every step from X and Y
- * (FP64 arguments, nothing of size n x m is stored; d <= 16) by the tiled
- * solver; for m > 8192 and d > 16 the cost is built explicitly and solved by
- * the tiled solver.  Limits: d <= 512.
+ * by the tiled solver (a row sweep and a column sweep per step; nothing of
+ * size n x m is stored): FP64 dot products for d <= 16, and for
+ * 16 < d <= 128 with p->split 2 or 3 the cross term x_i . y_j on BF16 matrix
+ * cores (Sec. 5 costs: |x|^2 + |y|^2 - 2 x.y or 1 - x.y, norms in FP64) with
+ * all products of a 16 x 16 tile accumulated in FP32.  For m > 8192 with
+ * d > 128, or with split 0 and d > 16, the cost is built explicitly and
+ * solved by the tiled solver.  Limits: d <= 512.
  */
 accsk_status accsk_solve_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
                                 double cost_scale, const double *a, const double *b, const accsk_params *p,

@@ -542,8 +542,9 @@ extern "C" accsk_status accsk_cost_max_points(const float *X, const float *Y, in
 }
 
 // Tiled solves of a batch of point-cloud problems, one after the other: costs on
-// the fly (d <= 16), else built explicitly one problem at a time.  dres (device
-// records, one per problem): the stream-ordered form, res unused.
+// the fly (FP64 dot products for d <= 16, the matrix-core cross term for
+// 16 < d <= 128 with split 2 or 3), else built explicitly one problem at a time.
+// dres (device records, one per problem): the stream-ordered form, res unused.
 static accsk_status solve_points_tiled(const float *X, const float *Y, int64_t batch, int64_t n, int64_t m,
                                        int64_t d, int kind, double cost_scale, const double *a, const double *b,
                                        const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
@@ -551,7 +552,8 @@ static accsk_status solve_points_tiled(const float *X, const float *Y, int64_t b
     float *C = nullptr;
     double *nws = nullptr;
     const long long ldc = (m + 3) / 4 * 4;
-    if (d > 16) {
+    const bool fly = d <= 16 || (d <= 128 && p->split != 0);
+    if (!fly) {
         const size_t cbytes = ((size_t)n * ldc * sizeof(float) + 255) & ~size_t(255);
         char *ws = nullptr;
         if (hipMallocAsync((void **)&ws, cbytes + (size_t)(n + m) * 8, s) != hipSuccess) return ACCSK_OOM;
@@ -563,7 +565,7 @@ static accsk_status solve_points_tiled(const float *X, const float *Y, int64_t b
         const float *Xk = X + k * n * d, *Yk = Y + k * m * d;
         accsk_status st;
         accsk_result *rk = res ? &res[k] : nullptr, *pk = dres ? dres + k : nullptr;
-        if (d <= 16) {
+        if (fly) {
             st = accsk_tiled_solve(nullptr, 0, Xk, Yk, d, kind, cost_scale, n, m, a + k * n, b + k * m, p, p->eps,
                                    f_out + k * n, g_out + k * m, rk, s, pk);
         } else {
@@ -603,7 +605,7 @@ static accsk_status solve_points_batched(const float *X, const float *Y, int64_t
     if (!finite_pos(p->eps)) return ACCSK_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     if ((p->flags & ACCSK_FLAG_ON_THE_FLY) || m > 8192) {
-        if ((p->flags & ACCSK_FLAG_ON_THE_FLY) && d > 16) return ACCSK_SHAPE;
+        if ((p->flags & ACCSK_FLAG_ON_THE_FLY) && d > 16 && (p->split == 0 || d > 128)) return ACCSK_SHAPE;
         return solve_points_tiled(X, Y, batch, n, m, d, kind, cost_scale, a, b, p, f_out, g_out, res, dres, s);
     }
     const long long ldc = (m + 3) / 4 * 4;

@@ -1,5 +1,6 @@
 // Tiled solver for large problems: explicit FP32 costs with m > 8192, and
-// costs formed on the fly from point clouds (d <= 16), never materialized.
+// costs formed on the fly from point clouds, never materialized: FP64 dot
+// products for d <= 16, the BF16x3 matrix-core cross term for 16 < d <= 128.
 //
 // One cooperative (persistent) launch runs the whole solve (paper Sec. 2 row
 // solve eq:u-update, normalized column step eq:normalized-sinkhorn; Sec. 4
@@ -23,6 +24,13 @@
 //    column term xh_j = x_j - kappa_s |y_j|^2 (cosine: x_j - kappa_s) and a row
 //    term r_i = -kappa_s |x_i|^2 (cosine: 0), xt_i = 2 kappa_s x_i (cosine:
 //    kappa_s x_i), kappa_s = log2(e) / (eps s).  C_ij is never stored.
+//  * points with 16 < d <= 128 (D = 32, 64, 128): the sums over k above are
+//    x_i . y_j from v_mfma_f32_16x16x32_bf16 on a 3-piece BF16 split of X and
+//    Y (or 2 pieces, split 2), all products of a 16 x 16 tile accumulated in
+//    one FP32 accumulator, small products first; the rest of the argument is
+//    FP64 as above.  Each wave owns a 16-row tile of the block's rows (its X
+//    pieces stay in registers), the block stages 128 columns of Y pieces in
+//    LDS in the operand layout, and both sweeps walk the same tiles.
 // If a combined column sum leaves [2^-64, 2^64] (the column mass changed that
 // much in one step), an exact column sweep with a per-column maximum redoes the
 // column side of that step.
@@ -34,6 +42,7 @@
 #include <vector>
 
 #include "accsk_common.h"
+#include "cost_tiles.h"
 
 namespace accsk {
 namespace {
@@ -52,8 +61,14 @@ struct TCfg {
     static constexpr int RG = kTW * RW;                                        // rows per group, row sweep
 };
 
+constexpr int kMCH = 128;  // columns of Y pieces staged per chunk (matrix-core sweeps, D >= 32)
+
 template <int D>
 size_t tiled_lds_bytes() {
+    if (D >= 32) {  // Y pieces [8 tiles][D/32 chunks][3 pieces][64 lanes] x 16 B, column terms, shifts, wave sums
+        return (size_t)(kMCH / 16) * (D / 32) * 3 * 64 * 16 + 2 * kMCH * sizeof(double) +
+               (size_t)kTW * kMCH * sizeof(double);
+    }
     using Cf = TCfg<D>;
     const size_t cols = (size_t)Cf::CH * (Cf::DD + 1) * sizeof(double);
     const size_t rows = (size_t)kTRB * (Cf::DD + 1) * sizeof(double);
@@ -85,6 +100,8 @@ struct TiledArgs {
     double eps, tol, tol_stop, mu0;
     long long max_iter, m0;
     int method, w_rule, flags;
+    int split;      // matrix-core cross term (D >= 32): 2 or 3 BF16 pieces
+    const bf16x8 *Xpk, *Ypk;  // (D >= 32) X and Y split into BF16 pieces in the operand layout (split_pieces)
     double *cond;   // ACCSK_FLAG_CONDITIONS (Acc): [3][m] grad f, D and v of the last iterate (slice-owned)
     double *cscal;  // [2][G][8] per-block sums of the boundedness monitor, by step parity
 };
@@ -184,6 +201,23 @@ __global__ __launch_bounds__(1024) void tiled_setup(const TiledArgs *__restrict_
     }
 }
 
+// FP64 sum / maximum over the 16 lanes of a DPP row (quad_perm [1,0,3,2], [2,3,0,1],
+// row_half_mirror, row_mirror); every lane of the row gets the result, in the same order.
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_f64<0xB1, 0xf, 0xf>(v, v);
+    v += dpp_f64<0x4E, 0xf, 0xf>(v, v);
+    v += dpp_f64<0x141, 0xf, 0xf>(v, v);
+    v += dpp_f64<0x140, 0xf, 0xf>(v, v);
+    return v;
+}
+__device__ __forceinline__ double row16_max(double v) {
+    v = fmax(v, dpp_f64<0xB1, 0xf, 0xf>(v, v));
+    v = fmax(v, dpp_f64<0x4E, 0xf, 0xf>(v, v));
+    v = fmax(v, dpp_f64<0x141, 0xf, 0xf>(v, v));
+    v = fmax(v, dpp_f64<0x140, 0xf, 0xf>(v, v));
+    return v;
+}
+
 __device__ __forceinline__ double readlane63_f64(double v) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)b, 63);
@@ -223,7 +257,8 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         return;
     }
     const long long n = A.n, m = A.m, d = A.d;
-    const long long rpb = (n + G - 1) / G;
+    // (matrix-core sweeps: whole 16-row tiles per block)
+    const long long rpb = D >= 32 ? ((n + G - 1) / G + 15) / 16 * 16 : (n + G - 1) / G;
     const long long r0 = std::min(n, (long long)bid * rpb), r1 = std::min(n, r0 + rpb);
     const long long nr = r1 - r0;
     const long long spb = (m + G - 1) / G;
@@ -258,54 +293,86 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
     double *xtl = tl;                  // [DD][kTRB] staged xt, column sweep
     double *rhl = tl + (size_t)DD * kTRB;  // [kTRB] staged row term
 
+    constexpr bool MF = D >= 32;  // matrix-core cross term (the sweeps further below)
     auto stage_cols = [&](long long ja, int len) {
-        for (int c = tid; c < len; c += kTT) {
-            const long long j = ja + c;
-            if (D > 0)
+        if constexpr (!MF) {
+            for (int c = tid; c < len; c += kTT) {
+                const long long j = ja + c;
+                if (D > 0)
 #pragma unroll
-                for (int k = 0; k < D; k++) ysl[(size_t)k * CH + c] = k < d ? (double)A.Y[j * d + k] : 0.0;
-            xhl[c] = col_term(j);
+                    for (int k = 0; k < D; k++) ysl[(size_t)k * CH + c] = k < d ? (double)A.Y[j * d + k] : 0.0;
+                xhl[c] = col_term(j);
+            }
         }
     };
 
     // ---- row sweep: u for the block's rows --------------------------------
     auto row_sweep = [&]() {
-        for (long long g0 = 0; g0 < nr; g0 += RG) {
-            double xt[RW][DD];
-            double rc0[RW], shift[RW];
-            bool rv[RW];
-            long long ri[RW];
-            int unknown = 0;
+        if constexpr (!MF) {
+            for (long long g0 = 0; g0 < nr; g0 += RG) {
+                double xt[RW][DD];
+                double rc0[RW], shift[RW];
+                bool rv[RW];
+                long long ri[RW];
+                int unknown = 0;
 #pragma unroll
-            for (int q = 0; q < RW; q++) {
-                const long long lr = g0 + wid * RW + q;
-                rv[q] = lr < nr;
-                ri[q] = r0 + std::min(lr, nr - 1);
+                for (int q = 0; q < RW; q++) {
+                    const long long lr = g0 + wid * RW + q;
+                    rv[q] = lr < nr;
+                    ri[q] = r0 + std::min(lr, nr - 1);
 #pragma unroll
-                for (int k = 0; k < DD; k++)
-                    xt[q][k] = (D > 0 && k < d) ? coef * (double)A.X[ri[q] * d + k] : 0.0;
-                rc0[q] = row_const(ri[q]);
-                shift[q] = A.rowL[ri[q]];
-                unknown |= (rv[q] && !(shift[q] < INFINITY)) ? 1 : 0;
-            }
-            __syncthreads();
-            if (tid == 0) sflag = 0;
-            __syncthreads();
-            if (unknown) atomicOr(&sflag, 1);
-            __syncthreads();
-            bool need_max = sflag != 0;
-            double S[RW];
-            for (int attempt = 0; attempt < 2; attempt++) {
-                if (need_max) {
-                    // exact row maximum of the argument
-                    double mx[RW];
+                    for (int k = 0; k < DD; k++)
+                        xt[q][k] = (D > 0 && k < d) ? coef * (double)A.X[ri[q] * d + k] : 0.0;
+                    rc0[q] = row_const(ri[q]);
+                    shift[q] = A.rowL[ri[q]];
+                    unknown |= (rv[q] && !(shift[q] < INFINITY)) ? 1 : 0;
+                }
+                __syncthreads();
+                if (tid == 0) sflag = 0;
+                __syncthreads();
+                if (unknown) atomicOr(&sflag, 1);
+                __syncthreads();
+                bool need_max = sflag != 0;
+                double S[RW];
+                for (int attempt = 0; attempt < 2; attempt++) {
+                    if (need_max) {
+                        // exact row maximum of the argument
+                        double mx[RW];
 #pragma unroll
-                    for (int q = 0; q < RW; q++) mx[q] = -INFINITY;
+                        for (int q = 0; q < RW; q++) mx[q] = -INFINITY;
+                        for (long long ja = 0; ja < m; ja += CH) {
+                            const int len = (int)std::min<long long>(CH, m - ja);
+                            __syncthreads();
+                            stage_cols(ja, len);
+                            __syncthreads();
+                            for (int c = lane; c < len; c += 64) {
+                                double y[DD];
+#pragma unroll
+                                for (int k = 0; k < DD; k++) y[k] = D > 0 ? ysl[(size_t)k * CH + c] : 0.0;
+                                const double xh = xhl[c];
+#pragma unroll
+                                for (int q = 0; q < RW; q++) {
+                                    double t;
+                                    if (D == 0) t = fma(-(double)A.C[ri[q] * A.ldc + ja + c], kap2, xh);
+                                    else t = arg_pts(xt[q], rc0[q], y, xh);
+                                    mx[q] = fmax(mx[q], t);
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < RW; q++) shift[q] = wave_max(mx[q]);
+                    }
+                    double acc[RW];
+#pragma unroll
+                    for (int q = 0; q < RW; q++) acc[q] = 0.0;
                     for (long long ja = 0; ja < m; ja += CH) {
                         const int len = (int)std::min<long long>(CH, m - ja);
                         __syncthreads();
                         stage_cols(ja, len);
                         __syncthreads();
+                        float sp[RW];
+#pragma unroll
+                        for (int q = 0; q < RW; q++) sp[q] = 0.f;
                         for (int c = lane; c < len; c += 64) {
                             double y[DD];
 #pragma unroll
@@ -314,67 +381,40 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
 #pragma unroll
                             for (int q = 0; q < RW; q++) {
                                 double t;
-                                if (D == 0) t = fma(-(double)A.C[ri[q] * A.ldc + ja + c], kap2, xh);
-                                else t = arg_pts(xt[q], rc0[q], y, xh);
-                                mx[q] = fmax(mx[q], t);
+                                if (D == 0) t = fma(-(double)A.C[ri[q] * A.ldc + ja + c], kap2, xh) - shift[q];
+                                else t = arg_pts(xt[q], rc0[q] - shift[q], y, xh);
+                                sp[q] += __builtin_amdgcn_exp2f((float)t);
                             }
                         }
+#pragma unroll
+                        for (int q = 0; q < RW; q++) acc[q] += (double)sp[q];
                     }
+                    int bad = 0;
 #pragma unroll
-                    for (int q = 0; q < RW; q++) shift[q] = wave_max(mx[q]);
-                }
-                double acc[RW];
-#pragma unroll
-                for (int q = 0; q < RW; q++) acc[q] = 0.0;
-                for (long long ja = 0; ja < m; ja += CH) {
-                    const int len = (int)std::min<long long>(CH, m - ja);
-                    __syncthreads();
-                    stage_cols(ja, len);
-                    __syncthreads();
-                    float sp[RW];
-#pragma unroll
-                    for (int q = 0; q < RW; q++) sp[q] = 0.f;
-                    for (int c = lane; c < len; c += 64) {
-                        double y[DD];
-#pragma unroll
-                        for (int k = 0; k < DD; k++) y[k] = D > 0 ? ysl[(size_t)k * CH + c] : 0.0;
-                        const double xh = xhl[c];
-#pragma unroll
-                        for (int q = 0; q < RW; q++) {
-                            double t;
-                            if (D == 0) t = fma(-(double)A.C[ri[q] * A.ldc + ja + c], kap2, xh) - shift[q];
-                            else t = arg_pts(xt[q], rc0[q] - shift[q], y, xh);
-                            sp[q] += __builtin_amdgcn_exp2f((float)t);
-                        }
+                    for (int q = 0; q < RW; q++) {
+                        S[q] = readlane63_f64(wave_sum_l63(acc[q]));
+                        bad |= (rv[q] && !(S[q] >= 0x1p-40 && S[q] <= 0x1p40)) ? 1 : 0;
                     }
-#pragma unroll
-                    for (int q = 0; q < RW; q++) acc[q] += (double)sp[q];
+                    __syncthreads();
+                    if (tid == 0) sflag = 0;
+                    __syncthreads();
+                    if (bad) atomicOr(&sflag, 1);
+                    __syncthreads();
+                    if (sflag == 0 || need_max) break;
+                    need_max = true;  // redo the group with the exact maximum
                 }
-                int bad = 0;
+                if (lane == 0) {
 #pragma unroll
-                for (int q = 0; q < RW; q++) {
-                    S[q] = readlane63_f64(wave_sum_l63(acc[q]));
-                    bad |= (rv[q] && !(S[q] >= 0x1p-40 && S[q] <= 0x1p40)) ? 1 : 0;
-                }
-                __syncthreads();
-                if (tid == 0) sflag = 0;
-                __syncthreads();
-                if (bad) atomicOr(&sflag, 1);
-                __syncthreads();
-                if (sflag == 0 || need_max) break;
-                need_max = true;  // redo the group with the exact maximum
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int q = 0; q < RW; q++) {
-                    if (!rv[q]) continue;
-                    const double lse = shift[q] + dlog2(S[q]);  // log2-sum-exp of the row (without r_i)
-                    A.rowL[ri[q]] = lse;
-                    A.rowU[ri[q]] = A.la2[ri[q]] - lse;  // u_i = log a_i - LSE_j t_ij, log2 units
+                    for (int q = 0; q < RW; q++) {
+                        if (!rv[q]) continue;
+                        const double lse = shift[q] + dlog2(S[q]);  // log2-sum-exp of the row (without r_i)
+                        A.rowL[ri[q]] = lse;
+                        A.rowU[ri[q]] = A.la2[ri[q]] - lse;  // u_i = log a_i - LSE_j t_ij, log2 units
+                    }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     };
 
     // ---- column sweep: per-block column sums ---------------------------------
@@ -385,74 +425,382 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
     // EXACT = true: per-column maximum m_j of t_ij + u_i over the block's rows,
     // then sum of 2^(t_ij + u_i - m_j) into part / partmax.
     auto col_sweep = [&](bool exact) {
-        for (long long ja = 0; ja < m; ja += CH) {
-            double y[CPL][DD], xh[CPL];
-            long long jc[CPL];
-            bool cv[CPL];
+        if constexpr (!MF) {
+            for (long long ja = 0; ja < m; ja += CH) {
+                double y[CPL][DD], xh[CPL];
+                long long jc[CPL];
+                bool cv[CPL];
 #pragma unroll
-            for (int p = 0; p < CPL; p++) {
-                const long long c = (long long)wid * 64 * CPL + lane + 64 * p;
-                cv[p] = ja + c < m;
-                jc[p] = std::min(ja + c, m - 1);
+                for (int p = 0; p < CPL; p++) {
+                    const long long c = (long long)wid * 64 * CPL + lane + 64 * p;
+                    cv[p] = ja + c < m;
+                    jc[p] = std::min(ja + c, m - 1);
 #pragma unroll
-                for (int k = 0; k < DD; k++) y[p][k] = (D > 0 && k < d) ? (double)A.Y[jc[p] * d + k] : 0.0;
-                xh[p] = col_term(jc[p]);
-            }
-            double cmx[CPL], acc[CPL];
+                    for (int k = 0; k < DD; k++) y[p][k] = (D > 0 && k < d) ? (double)A.Y[jc[p] * d + k] : 0.0;
+                    xh[p] = col_term(jc[p]);
+                }
+                double cmx[CPL], acc[CPL];
 #pragma unroll
-            for (int p = 0; p < CPL; p++) {
-                cmx[p] = exact ? -INFINITY : A.colL[jc[p]];
-                acc[p] = 0.0;
-            }
-            for (int sweep = exact ? 0 : 1; sweep < 2; sweep++) {
-                for (long long rb0 = 0; rb0 < nr; rb0 += kTRB) {
-                    const int rl = (int)std::min<long long>(kTRB, nr - rb0);
-                    __syncthreads();
-                    for (int r = tid; r < rl; r += kTT) {
-                        const long long i = r0 + rb0 + r;
+                for (int p = 0; p < CPL; p++) {
+                    cmx[p] = exact ? -INFINITY : A.colL[jc[p]];
+                    acc[p] = 0.0;
+                }
+                for (int sweep = exact ? 0 : 1; sweep < 2; sweep++) {
+                    for (long long rb0 = 0; rb0 < nr; rb0 += kTRB) {
+                        const int rl = (int)std::min<long long>(kTRB, nr - rb0);
+                        __syncthreads();
+                        for (int r = tid; r < rl; r += kTT) {
+                            const long long i = r0 + rb0 + r;
 #pragma unroll
-                        for (int k = 0; k < DD; k++)
-                            xtl[(size_t)k * kTRB + r] = (D > 0 && k < d) ? coef * (double)A.X[i * d + k] : 0.0;
-                        rhl[r] = row_const(i) + A.rowU[i];
-                    }
-                    __syncthreads();
-                    float sp[CPL];
-#pragma unroll
-                    for (int p = 0; p < CPL; p++) sp[p] = 0.f;
-                    for (int r = 0; r < rl; r++) {
-                        double xt[DD];
-#pragma unroll
-                        for (int k = 0; k < DD; k++) xt[k] = D > 0 ? xtl[(size_t)k * kTRB + r] : 0.0;
-                        const double rh = rhl[r];
-#pragma unroll
-                        for (int p = 0; p < CPL; p++) {
-                            double t;
-                            if (D == 0) t = fma(-(double)A.C[(r0 + rb0 + r) * A.ldc + jc[p]], kap2, xh[p]) + rh;
-                            else t = arg_pts(xt, rh, y[p], xh[p]);
-                            if (sweep == 0) cmx[p] = (t > cmx[p] || t != t) ? t : cmx[p];  // NaN propagates
-                            else sp[p] += __builtin_amdgcn_exp2f((float)(t - cmx[p]));
+                            for (int k = 0; k < DD; k++)
+                                xtl[(size_t)k * kTRB + r] = (D > 0 && k < d) ? coef * (double)A.X[i * d + k] : 0.0;
+                            rhl[r] = row_const(i) + A.rowU[i];
                         }
-                        if ((r & 7) == 7) {
+                        __syncthreads();
+                        float sp[CPL];
+#pragma unroll
+                        for (int p = 0; p < CPL; p++) sp[p] = 0.f;
+                        for (int r = 0; r < rl; r++) {
+                            double xt[DD];
+#pragma unroll
+                            for (int k = 0; k < DD; k++) xt[k] = D > 0 ? xtl[(size_t)k * kTRB + r] : 0.0;
+                            const double rh = rhl[r];
 #pragma unroll
                             for (int p = 0; p < CPL; p++) {
-                                acc[p] += (double)sp[p];
-                                sp[p] = 0.f;
+                                double t;
+                                if (D == 0) t = fma(-(double)A.C[(r0 + rb0 + r) * A.ldc + jc[p]], kap2, xh[p]) + rh;
+                                else t = arg_pts(xt, rh, y[p], xh[p]);
+                                if (sweep == 0) cmx[p] = (t > cmx[p] || t != t) ? t : cmx[p];  // NaN propagates
+                                else sp[p] += __builtin_amdgcn_exp2f((float)(t - cmx[p]));
+                            }
+                            if ((r & 7) == 7) {
+#pragma unroll
+                                for (int p = 0; p < CPL; p++) {
+                                    acc[p] += (double)sp[p];
+                                    sp[p] = 0.f;
+                                }
                             }
                         }
-                    }
 #pragma unroll
-                    for (int p = 0; p < CPL; p++) acc[p] += (double)sp[p];
+                        for (int p = 0; p < CPL; p++) acc[p] += (double)sp[p];
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < CPL; p++) {
+                    if (!cv[p]) continue;
+                    if (exact) {
+                        A.part[(size_t)bid * m + jc[p]] = acc[p];
+                        A.partmax[(size_t)bid * m + jc[p]] = cmx[p];
+                    } else {
+                        xstore(&A.partf[(size_t)bid * m + jc[p]], (float)acc[p]);
+                    }
                 }
             }
+        }
+    };
+
+    // ---- matrix-core sweeps (D >= 32) ------------------------------------------
+    // X and Y arrive split into BF16 pieces in the operand layout (split_pieces):
+    // unit ((T KC + kc) 3 + piece) 64 + lane (16 B) holds features
+    // kc 32 + (lane / 16) 8 + [0, 8) of point 16 T + lane % 16.  The block walks
+    // the columns in chunks of kMCH (8 column tiles): the next chunk's pieces, column
+    // terms and shifts are loaded into registers while the current one is used from
+    // LDS.  Each wave owns one 16-row tile per round (its A operands in registers).
+    constexpr int KC = MF ? D / 32 : 1;                // 32-wide K chunks
+    constexpr int NTC = kMCH / 16;                     // column tiles per chunk
+    constexpr int CU16 = NTC * KC * 3 * 64;            // 16-byte units per chunk
+    constexpr int PF = CU16 / kTT;                     // units per thread
+    static_assert(CU16 % kTT == 0, "chunk units per thread");
+    bf16x8 *ylp = reinterpret_cast<bf16x8 *>(tl);
+    double *mxh = reinterpret_cast<double *>(ylp + CU16);
+    double *mcl = mxh + kMCH;
+    double *mcp = mcl + kMCH;  // [kTW][kMCH]
+    const int split = A.split;
+    const int ntile = (int)((nr + 15) / 16);  // the block's 16-row tiles (r0 is a multiple of 16)
+    const int nround = (ntile + kTW - 1) / kTW;
+    const long long ytiles = (m + 15) / 16;
+
+    // registers of the chunk in flight: raw loads only (the column term is formed at
+    // commit), so the loads stay outstanding while the current chunk is computed.
+    // Indices are clamped into the arrays: units and columns past the end repeat valid
+    // data, and those columns are masked by xh = -inf.
+    bf16x8 pf[PF];
+    double pxg = 0.0, pyn = 0.0, psh = 0.0;
+    bool pvalid = false;
+    auto fetch = [&](long long ja, auto col_shift) {
+        const long long t0 = ja / 16;
+        const long long last = (ytiles - t0) * KC * 3 * 64 - 1;
+        const bf16x8 *src = A.Ypk + t0 * KC * 3 * 64;
 #pragma unroll
-            for (int p = 0; p < CPL; p++) {
-                if (!cv[p]) continue;
-                if (exact) {
-                    A.part[(size_t)bid * m + jc[p]] = acc[p];
-                    A.partmax[(size_t)bid * m + jc[p]] = cmx[p];
-                } else {
-                    xstore(&A.partf[(size_t)bid * m + jc[p]], (float)acc[p]);
+        for (int u = 0; u < PF; u++) pf[u] = src[std::min<long long>(u * kTT + tid, last)];
+        if (tid < kMCH) {
+            const long long jj = std::min(ja + tid, m - 1);
+            pvalid = ja + tid < m;
+            pxg = A.xg[jj];
+            pyn = sq ? A.ynrm[jj] : 0.0;
+            psh = col_shift(jj);
+        }
+    };
+    auto commit = [&]() {
+#pragma unroll
+        for (int u = 0; u < PF; u++) ylp[u * kTT + tid] = pf[u];
+        if (tid < kMCH) {
+            mxh[tid] = pvalid ? (sq ? pxg - ks * pyn : pxg - ks) : -INFINITY;
+            mcl[tid] = pvalid ? psh : 0.0;
+        }
+    };
+    // Chunks of all m columns through LDS, the next one in flight; body(ja) uses the staged one.
+    auto for_chunks = [&](auto col_shift, auto body) {
+        fetch(0, col_shift);
+        for (long long ja = 0; ja < m; ja += kMCH) {
+            __syncthreads();
+            commit();
+            __syncthreads();
+            if (ja + kMCH < m) fetch(ja + kMCH, col_shift);
+            body(ja);
+        }
+    };
+    // the wave's A operands: global row tile r0 / 16 + tile (clamped: an idle wave's
+    // results are not used)
+    const long long xtiles = (n + 15) / 16;
+    auto load_a = [&](int tile, bf16x8 (&ah)[KC], bf16x8 (&am)[KC], bf16x8 (&al)[KC]) {
+        const long long T = std::min<long long>(r0 / 16 + tile, xtiles - 1);
+        const bf16x8 *src = A.Xpk + (T * KC * 3) * 64 + lane;
+#pragma unroll
+        for (int kc = 0; kc < KC; kc++) {
+            ah[kc] = src[(kc * 3) * 64];
+            am[kc] = src[(kc * 3 + 1) * 64];
+            al[kc] = src[(kc * 3 + 2) * 64];
+        }
+    };
+    // x_i . y_j of column tiles t and t + 1 of the staged chunk (two independent chains):
+    // lane l gets rows 4 (l / 16) + q of the wave's tile, column 16 t + l % 16.  Products small
+    // first: mid*mid, hi*lo, lo*hi, then hi*mid, mid*hi, then hi*hi (split 2: the last three).
+    // x_i . y_j of column tile t of the staged chunk: lane l gets rows 4 (l / 16) + q of the
+    // wave's tile, column 16 t + l % 16.  Products small first: mid*mid, hi*lo, lo*hi, then
+    // hi*mid, mid*hi, then hi*hi (split 2: the last three).
+    auto tile_one = [&](int t, const bf16x8 (&ah)[KC], const bf16x8 (&am)[KC], const bf16x8 (&al)[KC]) {
+        floatx4 a0 = {0.f, 0.f, 0.f, 0.f};
+        const bf16x8 *b0 = ylp + (t * KC * 3) * 64 + lane;
+        if (split == 3) {
+#pragma unroll
+            for (int kc = 0; kc < KC; kc++) {
+                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[kc], b0[(kc * 3 + 1) * 64], a0, 0, 0, 0);
+                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kc], b0[(kc * 3 + 2) * 64], a0, 0, 0, 0);
+                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[kc], b0[(kc * 3) * 64], a0, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int kc = 0; kc < KC; kc++) {
+            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kc], b0[(kc * 3 + 1) * 64], a0, 0, 0, 0);
+            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[kc], b0[(kc * 3) * 64], a0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int kc = 0; kc < KC; kc++)
+            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kc], b0[(kc * 3) * 64], a0, 0, 0, 0);
+        return a0;
+    };
+    // tiles t and t + 1 (adjacent calls: two independent product chains the scheduler can interleave)
+    auto tile_pair = [&](int t, const bf16x8 (&ah)[KC], const bf16x8 (&am)[KC], const bf16x8 (&al)[KC],
+                         floatx4 &c0, floatx4 &c1) {
+        c0 = tile_one(t, ah, am, al);
+        c1 = tile_one(t + 1, ah, am, al);
+    };
+    auto zero_shift = [](long long) { return 0.0; };
+
+    // Row sweep: the same rule as row_sweep (previous log-sum-exp as the shift,
+    // exact row maximum when unknown or when the sum leaves [2^-40, 2^40]).
+    auto mrow_sweep = [&]() {
+        if constexpr (MF) {
+            for (int round = 0; round < nround; round++) {
+                const int tile = round * kTW + wid;
+                const bool act = tile < ntile;
+                bf16x8 ah[KC], am[KC], al[KC];
+                load_a(tile, ah, am, al);
+                double rc[4], shift[4];
+                long long ri[4];
+                bool rv[4];
+                int unknown = 0;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const long long lr = (long long)tile * 16 + 4 * (lane >> 4) + q;
+                    rv[q] = act && lr < nr;
+                    ri[q] = r0 + std::max(0LL, std::min(lr, nr - 1));
+                    rc[q] = row_const(ri[q]);
+                    shift[q] = rv[q] ? A.rowL[ri[q]] : 0.0;
+                    unknown |= (rv[q] && !(shift[q] < INFINITY)) ? 1 : 0;
                 }
+                __syncthreads();
+                if (tid == 0) sflag = 0;
+                __syncthreads();
+                if (unknown) atomicOr(&sflag, 1);
+                __syncthreads();
+                bool need_max = sflag != 0;
+                double S[4];
+                for (int attempt = 0; attempt < 2; attempt++) {
+                    if (need_max) {
+                        double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+                        for_chunks(zero_shift, [&](long long) {
+                            if (!act) return;
+                            for (int t = 0; t < NTC; t += 2) {
+                                floatx4 c0, c1;
+                                tile_pair(t, ah, am, al, c0, c1);
+                                const double x0 = mxh[t * 16 + (lane & 15)], x1 = mxh[t * 16 + 16 + (lane & 15)];
+#pragma unroll
+                                for (int q = 0; q < 4; q++) {
+                                    mx[q] = fmax(mx[q], fma(coef, (double)c0[q], rc[q] + x0));
+                                    mx[q] = fmax(mx[q], fma(coef, (double)c1[q], rc[q] + x1));
+                                }
+                            }
+                        });
+#pragma unroll
+                        for (int q = 0; q < 4; q++) shift[q] = row16_max(mx[q]);
+                    }
+                    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                    double base[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) base[q] = rc[q] - shift[q];
+                    for_chunks(zero_shift, [&](long long) {
+                        if (!act) return;
+                        float sp[4] = {0.f, 0.f, 0.f, 0.f};
+                        for (int t = 0; t < NTC; t += 2) {
+                            floatx4 c0, c1;
+                            tile_pair(t, ah, am, al, c0, c1);
+                            const double x0 = mxh[t * 16 + (lane & 15)], x1 = mxh[t * 16 + 16 + (lane & 15)];
+#pragma unroll
+                            for (int q = 0; q < 4; q++) {
+                                sp[q] += __builtin_amdgcn_exp2f((float)fma(coef, (double)c0[q], base[q] + x0));
+                                sp[q] += __builtin_amdgcn_exp2f((float)fma(coef, (double)c1[q], base[q] + x1));
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; q++) acc[q] += (double)sp[q];
+                    });
+                    int bad = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        S[q] = row16_sum(acc[q]);
+                        bad |= (rv[q] && !(S[q] >= 0x1p-40 && S[q] <= 0x1p40)) ? 1 : 0;
+                    }
+                    __syncthreads();
+                    if (tid == 0) sflag = 0;
+                    __syncthreads();
+                    if (bad) atomicOr(&sflag, 1);
+                    __syncthreads();
+                    if (sflag == 0 || need_max) break;
+                    need_max = true;  // redo the round with the exact maximum
+                }
+                if ((lane & 15) == 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        if (!rv[q]) continue;
+                        const double lse = shift[q] + dlog2(S[q]);
+                        A.rowL[ri[q]] = lse;
+                        A.rowU[ri[q]] = A.la2[ri[q]] - lse;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    };
+
+    // Column sweep: per-block column sums as col_sweep (EXACT = false: shift L_j,
+    // the column's log2-sum of the previous step; EXACT = true: the block's column
+    // maximum, then the sums).  A tile's 16 rows are added in FP32 (4 per lane,
+    // then across the lane groups), the waves' tiles and the rounds in FP64 in a
+    // fixed order.  Several rounds accumulate in part (FP64) before partf is written.
+    auto mcol_sweep = [&](bool exact) {
+        if constexpr (MF) {
+            for (int sweep = exact ? 0 : 1; sweep < 2; sweep++) {
+                const bool mxs = sweep == 0;  // maximum pass of the exact sweep
+                auto shift_src = [&](long long j) {
+                    return exact ? (mxs ? 0.0 : A.partmax[(size_t)bid * m + j]) : A.colL[j];
+                };
+                for (int round = 0; round < nround; round++) {
+                    const int tile = round * kTW + wid;
+                    const bool act = tile < ntile;
+                    bf16x8 ah[KC], am[KC], al[KC];
+                    load_a(tile, ah, am, al);
+                    double rh[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const long long lr = (long long)tile * 16 + 4 * (lane >> 4) + q;
+                        const long long i = r0 + std::max(0LL, std::min(lr, nr - 1));
+                        rh[q] = (act && lr < nr) ? row_const(i) + A.rowU[i] : -INFINITY;
+                    }
+                    for_chunks(shift_src, [&](long long ja) {
+                        for (int t = 0; t < NTC; t += 2) {
+                            double v0 = mxs ? -INFINITY : 0.0, v1 = v0;
+                            if (act) {
+                                floatx4 c0, c1;
+                                tile_pair(t, ah, am, al, c0, c1);
+                                const int k0 = t * 16 + (lane & 15), k1 = k0 + 16;
+                                const double x0 = mxh[k0], s0 = mcl[k0], x1 = mxh[k1], s1 = mcl[k1];
+                                if (mxs) {
+#pragma unroll
+                                    for (int q = 0; q < 4; q++) {
+                                        const double t0 = fma(coef, (double)c0[q], rh[q] + x0);
+                                        const double t1 = fma(coef, (double)c1[q], rh[q] + x1);
+                                        v0 = (t0 > v0 || t0 != t0) ? t0 : v0;  // NaN propagates
+                                        v1 = (t1 > v1 || t1 != t1) ? t1 : v1;
+                                    }
+                                } else {
+                                    float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+                                    for (int q = 0; q < 4; q++) {
+                                        p0 += __builtin_amdgcn_exp2f((float)(fma(coef, (double)c0[q], rh[q] + x0) - s0));
+                                        p1 += __builtin_amdgcn_exp2f((float)(fma(coef, (double)c1[q], rh[q] + x1) - s1));
+                                    }
+                                    v0 = (double)p0;
+                                    v1 = (double)p1;
+                                }
+                            }
+                            // the tile's 16 rows: across the four lane groups of the column
+                            if (mxs) {
+                                double u0 = __shfl_xor(v0, 16, 64), u1 = __shfl_xor(v1, 16, 64);
+                                v0 = (u0 > v0 || u0 != u0) ? u0 : v0;
+                                v1 = (u1 > v1 || u1 != u1) ? u1 : v1;
+                                u0 = __shfl_xor(v0, 32, 64);
+                                u1 = __shfl_xor(v1, 32, 64);
+                                v0 = (u0 > v0 || u0 != u0) ? u0 : v0;
+                                v1 = (u1 > v1 || u1 != u1) ? u1 : v1;
+                            } else {
+                                v0 += __shfl_xor(v0, 16, 64);
+                                v1 += __shfl_xor(v1, 16, 64);
+                                v0 += __shfl_xor(v0, 32, 64);
+                                v1 += __shfl_xor(v1, 32, 64);
+                            }
+                            if (lane < 16) {
+                                mcp[wid * kMCH + t * 16 + lane] = v0;
+                                mcp[wid * kMCH + t * 16 + 16 + lane] = v1;
+                            }
+                        }
+                        __syncthreads();
+                        for (int c = tid; c < kMCH; c += kTT) {
+                            const long long j = ja + c;
+                            if (j >= m) continue;
+                            double tv = mxs ? -INFINITY : 0.0;
+                            for (int w = 0; w < kTW; w++) {
+                                const double x = mcp[w * kMCH + c];
+                                if (mxs) tv = (x > tv || x != x) ? x : tv;
+                                else tv += x;
+                            }
+                            const size_t o = (size_t)bid * m + j;
+                            if (mxs) {
+                                A.partmax[o] = round == 0 ? tv : fmax(A.partmax[o], tv);
+                            } else if (exact) {
+                                A.part[o] = round == 0 ? tv : A.part[o] + tv;
+                            } else if (nround == 1) {
+                                xstore(&A.partf[o], (float)tv);
+                            } else {
+                                const double s2 = round == 0 ? tv : A.part[o] + tv;
+                                A.part[o] = s2;
+                                if (round == nround - 1) xstore(&A.partf[o], (float)s2);
+                            }
+                        }
+                    });
+                }
+                __syncthreads();
             }
         }
     };
@@ -486,8 +834,13 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
     for (long long step = 0;; step++) {
         const int par = (int)(step & 1);
         double *bs = A.bscal + (size_t)par * G * kTNS;
-        row_sweep();
-        col_sweep(false);
+        if constexpr (MF) {
+            mrow_sweep();
+            mcol_sweep(false);
+        } else {
+            row_sweep();
+            col_sweep(false);
+        }
         if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
         cond_settle();
 
@@ -495,7 +848,8 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         for (int pass = 0; pass < 2; pass++) {
             if (pass == 1) {
                 if (!exact) break;
-                col_sweep(true);
+                if constexpr (MF) mcol_sweep(true);
+                else col_sweep(true);
                 if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
                 fallbacks++;
             }
@@ -758,6 +1112,34 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Point rows split into BF16 pieces (bf16_split3) in the matrix-core operand
+// layout of the tiled solver: unit ((T KC + kc) 3 + piece) 64 + lane holds
+// features kc 32 + (lane / 16) 8 + [0, 8) of row 16 T + lane % 16, zeros past
+// the rows and features.  One thread per (T, kc, lane).
+__global__ __launch_bounds__(256) void split_pieces(const float *__restrict__ P, long long rows, long long d, int KC,
+                                                    bf16x8 *__restrict__ out) {
+    const long long u = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (u >= (rows + 15) / 16 * KC * 64) return;
+    const int ln = (int)(u % 64);
+    const long long tk = u / 64, T = tk / KC;
+    const int kc = (int)(tk % KC);
+    const long long p = T * 16 + (ln & 15), k0 = (long long)kc * 32 + (ln >> 4) * 8;
+    bf16x8 h, mi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const float v = (p < rows && k0 + e < d) ? P[p * d + k0 + e] : 0.f;
+        __bf16 bh, bm, bl;
+        bf16_split3(v, bh, bm, bl);
+        h[e] = bh;
+        mi[e] = bm;
+        lo[e] = bl;
+    }
+    bf16x8 *dst = out + ((T * KC + kc) * 3) * 64 + ln;
+    dst[0] = h;
+    dst[64] = mi;
+    dst[128] = lo;
+}
+
 // Stream-ordered calls: the result record, written to the caller's device memory.
 __global__ __launch_bounds__(64) void publish_tiled(const TiledArgs *__restrict__ pa, double tick_ms) {
     if (threadIdx.x == 0 && pa->pub) publish_record(pa->pub, *pa->res, tick_ms);
@@ -771,7 +1153,10 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     const size_t lds = tiled_lds_bytes<D>();
     ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tiled_solve<D, TR, CD>, kTT, lds));
     if (occ < 1) return ACCSK_SHAPE;
-    const long long G = (long long)std::min(occ, 2) * cu;
+    long long G = (long long)std::min(occ, 2) * cu;
+    // matrix-core sweeps: 16-row tiles, one per wave and round, so about 128 rows per
+    // block (each staged column chunk then serves 8 tiles)
+    if (D >= 32) G = std::max<long long>(1, std::min<long long>(G, (A.n + 16 * kTW - 1) / (16 * kTW)));
     const size_t n = A.n, m = A.m;
     size_t off = 0;
     const size_t o_args = off; off = align_up(off + sizeof(TiledArgs));
@@ -785,6 +1170,10 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     const size_t o_bs = off; off = align_up(off + (2 * (size_t)G * kTNS + 2 * (size_t)G) * 8);
     const bool cond = (p->flags & ACCSK_FLAG_CONDITIONS) && p->method == ACCSK_ACC;
     const size_t o_cond = off; off = align_up(off + (cond ? (3 * m + 2 * (size_t)G * 8) * 8 : 0));
+    constexpr int KC = D >= 32 ? D / 32 : 1;  // BF16 pieces of X and Y (matrix-core sweeps)
+    const size_t xp_units = D >= 32 ? (n + 15) / 16 * KC * 3 * 64 : 0, yp_units = D >= 32 ? (m + 15) / 16 * KC * 3 * 64 : 0;
+    const size_t o_xp = off; off = align_up(off + xp_units * sizeof(bf16x8));
+    const size_t o_yp = off; off = align_up(off + yp_units * sizeof(bf16x8));
     char *base = nullptr;
     if (hipMallocAsync((void **)&base, off, s) != hipSuccess) return ACCSK_OOM;
     double *pn = (double *)(base + o_n), *pm = (double *)(base + o_m);
@@ -812,6 +1201,8 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     A.res = (DevResult *)(base + o_res);
     A.cond = cond ? (double *)(base + o_cond) : nullptr;
     A.cscal = cond ? A.cond + 3 * m : nullptr;
+    A.Xpk = D >= 32 ? (const bf16x8 *)(base + o_xp) : nullptr;
+    A.Ypk = D >= 32 ? (const bf16x8 *)(base + o_yp) : nullptr;
     A.tol = p->tol;
     A.tol_stop = p->tol * (1.0 - 1.0 / 16.0);
     A.mu0 = p->mu0;
@@ -830,6 +1221,14 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     // (tiled_setup also zeroes the barrier words)
     hipError_t e = async ? upload_args(d_args, &A, sizeof(TiledArgs), s)
                          : hipMemcpyAsync(d_args, &A, sizeof(TiledArgs), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && D >= 32) {
+        const long long ux = (long long)(n + 15) / 16 * KC * 64, uy = (long long)(m + 15) / 16 * KC * 64;
+        hipLaunchKernelGGL(split_pieces, dim3((unsigned)((ux + 255) / 256)), dim3(256), 0, s, A.X, (long long)n, A.d,
+                           KC, (bf16x8 *)A.Xpk);
+        hipLaunchKernelGGL(split_pieces, dim3((unsigned)((uy + 255) / 256)), dim3(256), 0, s, A.Y, (long long)m, A.d,
+                           KC, (bf16x8 *)A.Ypk);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(tiled_setup, dim3(1), dim3(1024), 0, s, (const TiledArgs *)d_args);
         e = hipGetLastError();
@@ -868,7 +1267,8 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
 
 using namespace accsk;
 
-// Tiled solve of one problem (explicit C when X is null, else points with d <= 16).
+// Tiled solve of one problem (explicit C when X is null, else points with d <= 128:
+// FP64 dot products up to d = 16, the matrix-core cross term of p->split pieces above).
 // pub: null (results to *res, the call waits), or the device result record of
 // the stream-ordered form (res unused, nothing waits).
 accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, const float *Y, int64_t d, int kind,
@@ -894,6 +1294,7 @@ accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, cons
     accsk_status st;
     const bool tr = p->err_trace && p->trace_len > 0;
     const bool cd = (p->flags & ACCSK_FLAG_CONDITIONS) && p->method == ACCSK_ACC;
+    A.split = p->split == 2 ? 2 : 3;
     // diagnostic instantiations: the per-step trace; the boundedness monitor (with the trace code)
     auto launch = [&](auto dtag) {
         constexpr int DD = decltype(dtag)::value;
@@ -904,6 +1305,9 @@ accsk_status accsk_tiled_solve(const float *C, int64_t ldc, const float *X, cons
     else if (d <= 3) st = launch(std::integral_constant<int, 3>{});
     else if (d <= 8) st = launch(std::integral_constant<int, 8>{});
     else if (d <= 16) st = launch(std::integral_constant<int, 16>{});
+    else if (d <= 32) st = launch(std::integral_constant<int, 32>{});   // matrix-core cross term
+    else if (d <= 64) st = launch(std::integral_constant<int, 64>{});
+    else if (d <= 128) st = launch(std::integral_constant<int, 128>{});
     else st = ACCSK_SHAPE;
     if (st != ACCSK_OK || pub) return st;
     return (accsk_status)res->status;
@@ -917,5 +1321,6 @@ size_t accsk_tiled_workspace_bound(int64_t n, int64_t m, int cu) {
     return align_up(sizeof(TiledArgs)) + align_up(sizeof(DevResult)) + align_up(64 * 8) + align_up(256) +
            align_up(5 * (size_t)n * 8) + align_up(7 * (size_t)m * 8) + align_up(G * (size_t)m * 4) +
            align_up(2 * G * (size_t)m * 8) + align_up((2 * G * kTNS + 2 * G) * 8) +
-           align_up((3 * (size_t)m + 2 * G * 8) * 8);
+           align_up((3 * (size_t)m + 2 * G * 8) * 8) +
+           align_up(((size_t)n + 15) / 16 * 4 * 3 * 64 * 16) + align_up(((size_t)m + 15) / 16 * 4 * 3 * 64 * 16);
 }
