@@ -1,6 +1,7 @@
 // Tiled solver for large problems: explicit FP32 costs with m > 8192, and
-// costs formed on the fly from point clouds, never materialized: FP64 dot
-// products for d <= 16, the BF16x3 matrix-core cross term for 16 < d <= 128.
+// costs formed on the fly from point clouds, never materialized: the FP64
+// argument on the matrix cores for d <= 3, FP64 dot products for 3 < d <= 16,
+// the BF16x3 matrix-core cross term for 16 < d <= 128.
 //
 // One cooperative (persistent) launch runs the whole solve (paper Sec. 2 row
 // solve eq:u-update, normalized column step eq:normalized-sinkhorn; Sec. 4
@@ -24,13 +25,17 @@
 //    column term xh_j = x_j - kappa_s |y_j|^2 (cosine: x_j - kappa_s) and a row
 //    term r_i = -kappa_s |x_i|^2 (cosine: 0), xt_i = 2 kappa_s x_i (cosine:
 //    kappa_s x_i), kappa_s = log2(e) / (eps s).  C_ij is never stored.
+//  * points with d <= 3 (D = 3): the whole argument, row and column terms
+//    included, from one v_mfma_f64_16x16x4f64 per 16 x 16 tile (K = 4 holds
+//    the three coordinates and the column term), all FP64.
 //  * points with 16 < d <= 128 (D = 32, 64, 128): the sums over k above are
 //    x_i . y_j from v_mfma_f32_16x16x32_bf16 on a 3-piece BF16 split of X and
-//    Y (or 2 pieces, split 2), all products of a 16 x 16 tile accumulated in
-//    one FP32 accumulator, small products first; the rest of the argument is
-//    FP64 as above.  Each wave owns a 16-row tile of the block's rows (its X
-//    pieces stay in registers), the block stages 128 columns of Y pieces in
-//    LDS in the operand layout, and both sweeps walk the same tiles.
+//    Y (split 3: six products, split 2: three), accumulated in FP32 (two
+//    independent chains, small products first); the rest of the argument is
+//    FP64 as above.
+//    In both cases each wave owns a 16-row tile of the block's rows (its
+//    operands stay in registers), the block stages chunks of columns in LDS in
+//    the operand layout (double-buffered), and both sweeps walk the same tiles.
 // If a combined column sum leaves [2^-64, 2^64] (the column mass changed that
 // much in one step), an exact column sweep with a per-column maximum redoes the
 // column side of that step.
@@ -61,14 +66,13 @@ struct TCfg {
     static constexpr int RG = kTW * RW;                                        // rows per group, row sweep
 };
 
-constexpr int kMCH = 128;  // columns of Y pieces staged per chunk (matrix-core sweeps, D >= 32)
-
 template <int D>
 size_t tiled_lds_bytes() {
-    if (D >= 32) {  // Y pieces [8 tiles][D/32 chunks][3 pieces][64 lanes] x 16 B, column terms, shifts, wave sums
-        return (size_t)(kMCH / 16) * (D / 32) * 3 * 64 * 16 + 2 * kMCH * sizeof(double) +
-               (size_t)kTW * kMCH * sizeof(double);
+    if (D >= 32) {  // two buffers of Y pieces [tiles][D/32 chunks][3 pieces][64 lanes] x 16 B, column terms, wave sums
+        const size_t mch = D == 128 ? 64 : 128;
+        return 2 * (mch / 16) * (D / 32) * 3 * 64 * 16 + 2 * mch * sizeof(double) + (size_t)kTW * mch * sizeof(double);
     }
+    if (D == 3) return 2 * (size_t)(512 / 16) * 64 * sizeof(double) + (size_t)kTW * 512 * sizeof(double);
     using Cf = TCfg<D>;
     const size_t cols = (size_t)Cf::CH * (Cf::DD + 1) * sizeof(double);
     const size_t rows = (size_t)kTRB * (Cf::DD + 1) * sizeof(double);
@@ -227,12 +231,16 @@ __device__ __forceinline__ double readlane63_f64(double v) {
 
 // TR: write the per-step error trace (trace / trace_len).  A separate
 // instantiation, so that untraced solves carry no trace code at all.
+// The arguments come by value, in the kernel argument segment: pointers read
+// from there are known to address global memory, so loads and stores through
+// them are global_* instructions.  (Through a pointer to a copy in device memory
+// they would be flat_* instructions, which count on the LDS counter as well: every
+// wait for an LDS read would then also wait for the outstanding global loads.)
 template <int D, bool TR = false, bool CD = false>
-__global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__ pa, double *__restrict__ trace,
+__global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__restrict__ trace,
                                                    long long trace_len) {
     using Cf = TCfg<D>;
     constexpr int RW = Cf::RW, CH = Cf::CH, CPL = Cf::CPL, RG = Cf::RG, DD = Cf::DD;
-    const TiledArgs A = *pa;
     extern __shared__ double tl[];
     __shared__ double tot[kTNS];
     __shared__ double sred[kTW * 64];
@@ -258,7 +266,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
     }
     const long long n = A.n, m = A.m, d = A.d;
     // (matrix-core sweeps: whole 16-row tiles per block)
-    const long long rpb = D >= 32 ? ((n + G - 1) / G + 15) / 16 * 16 : (n + G - 1) / G;
+    const long long rpb = (D == 3 || D >= 32) ? ((n + G - 1) / G + 15) / 16 * 16 : (n + G - 1) / G;
     const long long r0 = std::min(n, (long long)bid * rpb), r1 = std::min(n, r0 + rpb);
     const long long nr = r1 - r0;
     const long long spb = (m + G - 1) / G;
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
     double *xtl = tl;                  // [DD][kTRB] staged xt, column sweep
     double *rhl = tl + (size_t)DD * kTRB;  // [kTRB] staged row term
 
-    constexpr bool MF = D >= 32;  // matrix-core cross term (the sweeps further below)
+    constexpr bool MF = D == 3 || D >= 32;  // matrix-core sweeps (further below)
     auto stage_cols = [&](long long ja, int len) {
         if constexpr (!MF) {
             for (int c = tid; c < len; c += kTT) {
@@ -499,112 +507,195 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
         }
     };
 
-    // ---- matrix-core sweeps (D >= 32) ------------------------------------------
-    // X and Y arrive split into BF16 pieces in the operand layout (split_pieces):
-    // unit ((T KC + kc) 3 + piece) 64 + lane (16 B) holds features
-    // kc 32 + (lane / 16) 8 + [0, 8) of point 16 T + lane % 16.  The block walks
-    // the columns in chunks of kMCH (8 column tiles): the next chunk's pieces, column
-    // terms and shifts are loaded into registers while the current one is used from
-    // LDS.  Each wave owns one 16-row tile per round (its A operands in registers).
-    constexpr int KC = MF ? D / 32 : 1;                // 32-wide K chunks
-    constexpr int NTC = kMCH / 16;                     // column tiles per chunk
-    constexpr int CU16 = NTC * KC * 3 * 64;            // 16-byte units per chunk
-    constexpr int PF = CU16 / kTT;                     // units per thread
-    static_assert(CU16 % kTT == 0, "chunk units per thread");
-    bf16x8 *ylp = reinterpret_cast<bf16x8 *>(tl);
-    double *mxh = reinterpret_cast<double *>(ylp + CU16);
-    double *mcl = mxh + kMCH;
-    double *mcp = mcl + kMCH;  // [kTW][kMCH]
+    // ---- matrix-core sweeps (D = 3 and D >= 32) --------------------------------
+    // Both sweeps walk the columns in chunks of MCH staged in LDS, two buffers: the
+    // next chunk is loaded while the current one is used.  Each wave owns one
+    // 16-row tile per round and computes 16 x 16 tiles of the exponent argument
+    // on the matrix cores:
+    //  * D >= 32 (BF16 engine): x_i . y_j from v_mfma_f32_16x16x32_bf16 on the
+    //    BF16 pieces (split_pieces layout: unit ((T KC + kc) 3 + piece) 64 + lane
+    //    holds features kc 32 + (lane / 16) 8 + [0, 8) of point 16 T + lane % 16),
+    //    then arg = coef (x_i . y_j) + (row term + column term) in FP64.  Lane l
+    //    holds column l % 16 and rows 4 (l / 16) + q.  The pieces of the next chunk
+    //    go straight from global memory into LDS (global_load_lds_dwordx4).
+    //  * D = 3 (FP64 engine): the whole argument from one v_mfma_f64_16x16x4f64,
+    //    A = [xt_i, 1] (k = 0..3), B = [y_j, column term], accumulator input = the
+    //    row term, all FP64.  Lane l holds column l % 16 and rows l / 16 + 4 q.
+    // The column term carries the sweep's column shift: xh_j - s_j, -inf past m.
+    constexpr bool BF = D >= 32;
+    constexpr int KC = BF ? D / 32 : 1;                   // 32-wide K chunks (BF16 engine)
+    constexpr int MCH = BF ? (D == 128 ? 64 : 128) : 512;  // columns per chunk
+    constexpr int NTC = MCH / 16;                         // column tiles per chunk
+    constexpr int BU = BF ? NTC * KC * 3 * 64 : NTC * 64; // B units per buffer (16 B BF16 pieces, 8 B FP64)
+    constexpr int PF = BF ? BU / kTT : 1;                 // direct loads per thread and chunk
+    static_assert(!MF || !BF || BU % kTT == 0, "chunk units per thread");
+    static_assert(!MF || MCH <= kTT, "one column per thread");
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    bf16x8 *ylp = reinterpret_cast<bf16x8 *>(tl);                       // BF16: [2][BU]
+    double *yl64 = tl;                                                  // FP64: [2][NTC][64]
+    double *colt = BF ? reinterpret_cast<double *>(ylp + 2 * BU) : tl + 2 * BU;  // BF16: [2][MCH] column terms
+    double *mcp = BF ? colt + 2 * MCH : tl + 2 * BU;                    // [kTW][MCH] per-wave column values
     const int split = A.split;
     const int ntile = (int)((nr + 15) / 16);  // the block's 16-row tiles (r0 is a multiple of 16)
     const int nround = (ntile + kTW - 1) / kTW;
-    const long long ytiles = (m + 15) / 16;
+    const long long ytiles = (m + 15) / 16, xtiles = (n + 15) / 16;
+    // block-relative row of (lane, q) in the wave's tile
+    auto trow = [&](int q) -> int { return BF ? 4 * (lane >> 4) + q : (lane >> 4) + 4 * q; };
 
-    // registers of the chunk in flight: raw loads only (the column term is formed at
-    // commit), so the loads stay outstanding while the current chunk is computed.
-    // Indices are clamped into the arrays: units and columns past the end repeat valid
-    // data, and those columns are masked by xh = -inf.
-    bf16x8 pf[PF];
+    // Column data of the next chunk, in registers until it is committed to LDS
+    // (one column per thread; index clamped, columns past m get the term -inf).
     double pxg = 0.0, pyn = 0.0, psh = 0.0;
+    float py[3] = {0.f, 0.f, 0.f};
     bool pvalid = false;
-    auto fetch = [&](long long ja, auto col_shift) {
-        const long long t0 = ja / 16;
-        const long long last = (ytiles - t0) * KC * 3 * 64 - 1;
-        const bf16x8 *src = A.Ypk + t0 * KC * 3 * 64;
+    auto fetch = [&](long long ja, int buf, auto col_shift) {
+        if constexpr (BF) {
+            // this thread's share of the chunk's pieces, straight into LDS buffer buf
+            // (wave w's lanes fill units u kTT + 64 w + [0, 64))
+            const long long t0 = ja / 16;
+            const long long last = (ytiles - t0) * KC * 3 * 64 - 1;
+            const bf16x8 *src = A.Ypk + t0 * KC * 3 * 64;
 #pragma unroll
-        for (int u = 0; u < PF; u++) pf[u] = src[std::min<long long>(u * kTT + tid, last)];
-        if (tid < kMCH) {
+            for (int u = 0; u < PF; u++) {
+                const long long unit = std::min<long long>((long long)u * kTT + tid, last);
+                __builtin_amdgcn_global_load_lds(
+                    (__attribute__((address_space(1))) const void *)(src + unit),
+                    (__attribute__((address_space(3))) void *)(ylp + (size_t)buf * BU + u * kTT + wid * 64), 16, 0, 0);
+            }
+        }
+        if (tid < MCH) {
             const long long jj = std::min(ja + tid, m - 1);
             pvalid = ja + tid < m;
             pxg = A.xg[jj];
             pyn = sq ? A.ynrm[jj] : 0.0;
             psh = col_shift(jj);
-        }
-    };
-    auto commit = [&]() {
+            if constexpr (!BF) {
 #pragma unroll
-        for (int u = 0; u < PF; u++) ylp[u * kTT + tid] = pf[u];
-        if (tid < kMCH) {
-            mxh[tid] = pvalid ? (sq ? pxg - ks * pyn : pxg - ks) : -INFINITY;
-            mcl[tid] = pvalid ? psh : 0.0;
+                for (int k = 0; k < 3; k++) py[k] = k < d ? A.Y[jj * d + k] : 0.f;
+            }
         }
     };
-    // Chunks of all m columns through LDS, the next one in flight; body(ja) uses the staged one.
+    auto commit = [&](int buf) {
+        if (tid < MCH) {
+            const double ct = pvalid ? (sq ? pxg - ks * pyn : pxg - ks) - psh : -INFINITY;
+            if constexpr (BF) {
+                colt[buf * MCH + tid] = ct;
+            } else {
+                double *bt = yl64 + (size_t)buf * BU + (tid >> 4) * 64 + (tid & 15);
+#pragma unroll
+                for (int k = 0; k < 3; k++) bt[16 * k] = (double)py[k];
+                bt[48] = ct;
+            }
+        }
+    };
+    // all m columns chunk by chunk; body(ja, buf) uses the chunk staged in LDS buffer buf
     auto for_chunks = [&](auto col_shift, auto body) {
-        fetch(0, col_shift);
-        for (long long ja = 0; ja < m; ja += kMCH) {
+        __syncthreads();  // every wave has left the previous walk's buffers
+        fetch(0, 0, col_shift);
+        int buf = 0;
+        for (long long ja = 0; ja < m; ja += MCH) {
+            // this thread's loads of the chunk (direct-to-LDS pieces and column data) are in
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+            commit(buf);
+            // the chunk is complete in LDS, and every wave has left chunk ja - MCH, whose
+            // buffer the next fetch refills
             __syncthreads();
-            commit();
-            __syncthreads();
-            if (ja + kMCH < m) fetch(ja + kMCH, col_shift);
-            body(ja);
+            if (ja + MCH < m) fetch(ja + MCH, buf ^ 1, col_shift);
+            body(ja, buf);
+            buf ^= 1;
         }
     };
-    // the wave's A operands: global row tile r0 / 16 + tile (clamped: an idle wave's
-    // results are not used)
-    const long long xtiles = (n + 15) / 16;
-    auto load_a = [&](int tile, bf16x8 (&ah)[KC], bf16x8 (&am)[KC], bf16x8 (&al)[KC]) {
-        const long long T = std::min<long long>(r0 / 16 + tile, xtiles - 1);
-        const bf16x8 *src = A.Xpk + (T * KC * 3) * 64 + lane;
-#pragma unroll
-        for (int kc = 0; kc < KC; kc++) {
-            ah[kc] = src[(kc * 3) * 64];
-            am[kc] = src[(kc * 3 + 1) * 64];
-            al[kc] = src[(kc * 3 + 2) * 64];
-        }
+
+    // A operands of the wave's tile: global row tile r0 / 16 + tile (clamped: an idle
+    // wave's results are not used)
+    struct AOps {
+        bf16x8 h[KC], m_[KC], l[KC];
+        double a64;
     };
-    // x_i . y_j of column tiles t and t + 1 of the staged chunk (two independent chains):
-    // lane l gets rows 4 (l / 16) + q of the wave's tile, column 16 t + l % 16.  Products small
-    // first: mid*mid, hi*lo, lo*hi, then hi*mid, mid*hi, then hi*hi (split 2: the last three).
-    // x_i . y_j of column tile t of the staged chunk: lane l gets rows 4 (l / 16) + q of the
-    // wave's tile, column 16 t + l % 16.  Products small first: mid*mid, hi*lo, lo*hi, then
-    // hi*mid, mid*hi, then hi*hi (split 2: the last three).
-    auto tile_one = [&](int t, const bf16x8 (&ah)[KC], const bf16x8 (&am)[KC], const bf16x8 (&al)[KC]) {
-        floatx4 a0 = {0.f, 0.f, 0.f, 0.f};
-        const bf16x8 *b0 = ylp + (t * KC * 3) * 64 + lane;
-        if (split == 3) {
+    auto load_a = [&](int tile, AOps &ao) {
+        if constexpr (BF) {
+            const long long T = std::min<long long>(r0 / 16 + tile, xtiles - 1);
+            const bf16x8 *src = A.Xpk + (T * KC * 3) * 64 + lane;
 #pragma unroll
             for (int kc = 0; kc < KC; kc++) {
-                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[kc], b0[(kc * 3 + 1) * 64], a0, 0, 0, 0);
-                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kc], b0[(kc * 3 + 2) * 64], a0, 0, 0, 0);
-                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[kc], b0[(kc * 3) * 64], a0, 0, 0, 0);
+                ao.h[kc] = src[(kc * 3) * 64];
+                ao.m_[kc] = src[(kc * 3 + 1) * 64];
+                ao.l[kc] = src[(kc * 3 + 2) * 64];
+            }
+        } else {
+            const long long i = r0 + std::min<long long>((long long)tile * 16 + (lane & 15), nr - 1);
+            const int k = lane >> 4;
+            ao.a64 = k == 3 ? 1.0 : (k < d ? coef * (double)A.X[i * d + k] : 0.0);
+        }
+    };
+    // BF16 engine: x_i . y_j of one column tile; the tile's B operands are read first, the
+    // products go into two independent accumulators (small products first in each), summed
+    // at the end.  S3: the six products of split 3, else the three of split 2.
+    auto bf_tile = [&](auto S3, const bf16x8 *bt, const AOps &ao) -> floatx4 {
+        bf16x8 bh[KC], bm[KC], bl[KC];
+#pragma unroll
+        for (int kc = 0; kc < KC; kc++) {
+            bh[kc] = bt[(kc * 3) * 64];
+            bm[kc] = bt[(kc * 3 + 1) * 64];
+            if constexpr (decltype(S3)::value) bl[kc] = bt[(kc * 3 + 2) * 64];
+        }
+        floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (decltype(S3)::value) {
+#pragma unroll
+            for (int kc = 0; kc < KC; kc++) {
+                c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.m_[kc], bm[kc], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bl[kc], c1, 0, 0, 0);
+                c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.l[kc], bh[kc], c0, 0, 0, 0);
             }
         }
 #pragma unroll
         for (int kc = 0; kc < KC; kc++) {
-            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kc], b0[(kc * 3 + 1) * 64], a0, 0, 0, 0);
-            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[kc], b0[(kc * 3) * 64], a0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bm[kc], c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.m_[kc], bh[kc], c0, 0, 0, 0);
         }
 #pragma unroll
-        for (int kc = 0; kc < KC; kc++)
-            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kc], b0[(kc * 3) * 64], a0, 0, 0, 0);
-        return a0;
+        for (int kc = 0; kc < KC; kc++) {
+            if (kc & 1) c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bh[kc], c0, 0, 0, 0);
+            else c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bh[kc], c1, 0, 0, 0);
+        }
+        return c0 + c1;
     };
-    // tiles t and t + 1 (adjacent calls: two independent product chains the scheduler can interleave)
-    auto tile_pair = [&](int t, const bf16x8 (&ah)[KC], const bf16x8 (&am)[KC], const bf16x8 (&al)[KC],
-                         floatx4 &c0, floatx4 &c1) {
-        c0 = tile_one(t, ah, am, al);
-        c1 = tile_one(t + 1, ah, am, al);
+    // For every column tile t of the staged chunk: arg[q] = the exponent argument of
+    // (row trow(q), column 16 t + lane % 16), given the row terms rt[q] (BF16: added in
+    // FP64 after the product; FP64: the accumulator input); then use(t, arg).
+    auto for_tiles = [&](auto S3, int buf, const AOps &ao, const double (&rt)[4], auto use) {
+        if constexpr (BF) {
+            const bf16x8 *b0 = ylp + (size_t)buf * BU + lane;
+            const double *ct = colt + buf * MCH + (lane & 15);
+#pragma unroll
+            for (int t = 0; t < NTC; t++) {
+                const floatx4 c = bf_tile(S3, b0 + t * KC * 3 * 64, ao);
+                const double x0 = ct[t * 16];
+                double arg[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) arg[q] = fma(coef, (double)c[q], rt[q] + x0);
+                use(t, arg);
+            }
+        } else {
+            const f64x4 cin = {rt[0], rt[1], rt[2], rt[3]};
+            const double *b0 = yl64 + (size_t)buf * BU + lane;
+            constexpr int G4 = 4;  // independent products in flight
+#pragma unroll
+            for (int t0 = 0; t0 < NTC; t0 += G4) {
+                f64x4 dv[G4];
+#pragma unroll
+                for (int g = 0; g < G4; g++) dv[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao.a64, b0[(t0 + g) * 64], cin, 0, 0, 0);
+#pragma unroll
+                for (int g = 0; g < G4; g++) {
+                    double arg[4] = {dv[g][0], dv[g][1], dv[g][2], dv[g][3]};
+                    use(t0 + g, arg);
+                }
+            }
+        }
+    };
+    // run f with the split as a compile-time constant (FP64 engine: no split)
+    auto with_split = [&](auto f) {
+        if (BF && split == 2) f(std::integral_constant<bool, false>{});
+        else f(std::integral_constant<bool, true>{});
     };
     auto zero_shift = [](long long) { return 0.0; };
 
@@ -615,15 +706,15 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
             for (int round = 0; round < nround; round++) {
                 const int tile = round * kTW + wid;
                 const bool act = tile < ntile;
-                bf16x8 ah[KC], am[KC], al[KC];
-                load_a(tile, ah, am, al);
+                AOps ao;
+                load_a(tile, ao);
                 double rc[4], shift[4];
                 long long ri[4];
                 bool rv[4];
                 int unknown = 0;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const long long lr = (long long)tile * 16 + 4 * (lane >> 4) + q;
+                    const long long lr = (long long)tile * 16 + trow(q);
                     rv[q] = act && lr < nr;
                     ri[q] = r0 + std::max(0LL, std::min(lr, nr - 1));
                     rc[q] = row_const(ri[q]);
@@ -640,18 +731,14 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                 for (int attempt = 0; attempt < 2; attempt++) {
                     if (need_max) {
                         double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-                        for_chunks(zero_shift, [&](long long) {
-                            if (!act) return;
-                            for (int t = 0; t < NTC; t += 2) {
-                                floatx4 c0, c1;
-                                tile_pair(t, ah, am, al, c0, c1);
-                                const double x0 = mxh[t * 16 + (lane & 15)], x1 = mxh[t * 16 + 16 + (lane & 15)];
+                        with_split([&](auto S3) {
+                            for_chunks(zero_shift, [&](long long, int buf) {
+                                if (!act) return;
+                                for_tiles(S3, buf, ao, rc, [&](int, const double (&arg)[4]) {
 #pragma unroll
-                                for (int q = 0; q < 4; q++) {
-                                    mx[q] = fmax(mx[q], fma(coef, (double)c0[q], rc[q] + x0));
-                                    mx[q] = fmax(mx[q], fma(coef, (double)c1[q], rc[q] + x1));
-                                }
-                            }
+                                    for (int q = 0; q < 4; q++) mx[q] = fmax(mx[q], arg[q]);
+                                });
+                            });
                         });
 #pragma unroll
                         for (int q = 0; q < 4; q++) shift[q] = row16_max(mx[q]);
@@ -660,21 +747,17 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                     double base[4];
 #pragma unroll
                     for (int q = 0; q < 4; q++) base[q] = rc[q] - shift[q];
-                    for_chunks(zero_shift, [&](long long) {
-                        if (!act) return;
-                        float sp[4] = {0.f, 0.f, 0.f, 0.f};
-                        for (int t = 0; t < NTC; t += 2) {
-                            floatx4 c0, c1;
-                            tile_pair(t, ah, am, al, c0, c1);
-                            const double x0 = mxh[t * 16 + (lane & 15)], x1 = mxh[t * 16 + 16 + (lane & 15)];
+                    with_split([&](auto S3) {
+                        for_chunks(zero_shift, [&](long long, int buf) {
+                            if (!act) return;
+                            float sp[4] = {0.f, 0.f, 0.f, 0.f};
+                            for_tiles(S3, buf, ao, base, [&](int, const double (&arg)[4]) {
 #pragma unroll
-                            for (int q = 0; q < 4; q++) {
-                                sp[q] += __builtin_amdgcn_exp2f((float)fma(coef, (double)c0[q], base[q] + x0));
-                                sp[q] += __builtin_amdgcn_exp2f((float)fma(coef, (double)c1[q], base[q] + x1));
-                            }
-                        }
+                                for (int q = 0; q < 4; q++) sp[q] += __builtin_amdgcn_exp2f((float)arg[q]);
+                            });
 #pragma unroll
-                        for (int q = 0; q < 4; q++) acc[q] += (double)sp[q];
+                            for (int q = 0; q < 4; q++) acc[q] += (double)sp[q];
+                        });
                     });
                     int bad = 0;
 #pragma unroll
@@ -719,85 +802,65 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs *__restrict__
                 for (int round = 0; round < nround; round++) {
                     const int tile = round * kTW + wid;
                     const bool act = tile < ntile;
-                    bf16x8 ah[KC], am[KC], al[KC];
-                    load_a(tile, ah, am, al);
+                    AOps ao;
+                    load_a(tile, ao);
                     double rh[4];
 #pragma unroll
                     for (int q = 0; q < 4; q++) {
-                        const long long lr = (long long)tile * 16 + 4 * (lane >> 4) + q;
+                        const long long lr = (long long)tile * 16 + trow(q);
                         const long long i = r0 + std::max(0LL, std::min(lr, nr - 1));
                         rh[q] = (act && lr < nr) ? row_const(i) + A.rowU[i] : -INFINITY;
                     }
-                    for_chunks(shift_src, [&](long long ja) {
-                        for (int t = 0; t < NTC; t += 2) {
-                            double v0 = mxs ? -INFINITY : 0.0, v1 = v0;
+                    with_split([&](auto S3) {
+                        for_chunks(shift_src, [&](long long ja, int buf) {
                             if (act) {
-                                floatx4 c0, c1;
-                                tile_pair(t, ah, am, al, c0, c1);
-                                const int k0 = t * 16 + (lane & 15), k1 = k0 + 16;
-                                const double x0 = mxh[k0], s0 = mcl[k0], x1 = mxh[k1], s1 = mcl[k1];
+                                for_tiles(S3, buf, ao, rh, [&](int t, const double (&arg)[4]) {
+                                    double v;
+                                    if (mxs) {
+                                        v = -INFINITY;
+#pragma unroll
+                                        for (int q = 0; q < 4; q++) v = (arg[q] > v || arg[q] != arg[q]) ? arg[q] : v;  // NaN propagates
+                                        double u = __shfl_xor(v, 16, 64);
+                                        v = (u > v || u != u) ? u : v;
+                                        u = __shfl_xor(v, 32, 64);
+                                        v = (u > v || u != u) ? u : v;
+                                    } else {
+                                        float p = 0.f;
+#pragma unroll
+                                        for (int q = 0; q < 4; q++) p += __builtin_amdgcn_exp2f((float)arg[q]);
+                                        p += __shfl_xor(p, 16, 64);  // the tile's 16 rows: across the lane groups
+                                        p += __shfl_xor(p, 32, 64);
+                                        v = (double)p;
+                                    }
+                                    if (lane < 16) mcp[wid * MCH + t * 16 + lane] = v;
+                                });
+                            } else {
+                                for (int c = lane; c < MCH; c += 64) mcp[wid * MCH + c] = mxs ? -INFINITY : 0.0;
+                            }
+                            __syncthreads();
+                            for (int c = tid; c < MCH; c += kTT) {
+                                const long long j = ja + c;
+                                if (j >= m) continue;
+                                double tv = mxs ? -INFINITY : 0.0;
+                                for (int w = 0; w < kTW; w++) {
+                                    const double x = mcp[w * MCH + c];
+                                    if (mxs) tv = (x > tv || x != x) ? x : tv;
+                                    else tv += x;
+                                }
+                                const size_t o = (size_t)bid * m + j;
                                 if (mxs) {
-#pragma unroll
-                                    for (int q = 0; q < 4; q++) {
-                                        const double t0 = fma(coef, (double)c0[q], rh[q] + x0);
-                                        const double t1 = fma(coef, (double)c1[q], rh[q] + x1);
-                                        v0 = (t0 > v0 || t0 != t0) ? t0 : v0;  // NaN propagates
-                                        v1 = (t1 > v1 || t1 != t1) ? t1 : v1;
-                                    }
+                                    A.partmax[o] = round == 0 ? tv : fmax(A.partmax[o], tv);
+                                } else if (exact) {
+                                    A.part[o] = round == 0 ? tv : A.part[o] + tv;
+                                } else if (nround == 1) {
+                                    xstore(&A.partf[o], (float)tv);
                                 } else {
-                                    float p0 = 0.f, p1 = 0.f;
-#pragma unroll
-                                    for (int q = 0; q < 4; q++) {
-                                        p0 += __builtin_amdgcn_exp2f((float)(fma(coef, (double)c0[q], rh[q] + x0) - s0));
-                                        p1 += __builtin_amdgcn_exp2f((float)(fma(coef, (double)c1[q], rh[q] + x1) - s1));
-                                    }
-                                    v0 = (double)p0;
-                                    v1 = (double)p1;
+                                    const double s2 = round == 0 ? tv : A.part[o] + tv;
+                                    A.part[o] = s2;
+                                    if (round == nround - 1) xstore(&A.partf[o], (float)s2);
                                 }
                             }
-                            // the tile's 16 rows: across the four lane groups of the column
-                            if (mxs) {
-                                double u0 = __shfl_xor(v0, 16, 64), u1 = __shfl_xor(v1, 16, 64);
-                                v0 = (u0 > v0 || u0 != u0) ? u0 : v0;
-                                v1 = (u1 > v1 || u1 != u1) ? u1 : v1;
-                                u0 = __shfl_xor(v0, 32, 64);
-                                u1 = __shfl_xor(v1, 32, 64);
-                                v0 = (u0 > v0 || u0 != u0) ? u0 : v0;
-                                v1 = (u1 > v1 || u1 != u1) ? u1 : v1;
-                            } else {
-                                v0 += __shfl_xor(v0, 16, 64);
-                                v1 += __shfl_xor(v1, 16, 64);
-                                v0 += __shfl_xor(v0, 32, 64);
-                                v1 += __shfl_xor(v1, 32, 64);
-                            }
-                            if (lane < 16) {
-                                mcp[wid * kMCH + t * 16 + lane] = v0;
-                                mcp[wid * kMCH + t * 16 + 16 + lane] = v1;
-                            }
-                        }
-                        __syncthreads();
-                        for (int c = tid; c < kMCH; c += kTT) {
-                            const long long j = ja + c;
-                            if (j >= m) continue;
-                            double tv = mxs ? -INFINITY : 0.0;
-                            for (int w = 0; w < kTW; w++) {
-                                const double x = mcp[w * kMCH + c];
-                                if (mxs) tv = (x > tv || x != x) ? x : tv;
-                                else tv += x;
-                            }
-                            const size_t o = (size_t)bid * m + j;
-                            if (mxs) {
-                                A.partmax[o] = round == 0 ? tv : fmax(A.partmax[o], tv);
-                            } else if (exact) {
-                                A.part[o] = round == 0 ? tv : A.part[o] + tv;
-                            } else if (nround == 1) {
-                                xstore(&A.partf[o], (float)tv);
-                            } else {
-                                const double s2 = round == 0 ? tv : A.part[o] + tv;
-                                A.part[o] = s2;
-                                if (round == nround - 1) xstore(&A.partf[o], (float)s2);
-                            }
-                        }
+                        });
                     });
                 }
                 __syncthreads();
@@ -1156,7 +1219,7 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     long long G = (long long)std::min(occ, 2) * cu;
     // matrix-core sweeps: 16-row tiles, one per wave and round, so about 128 rows per
     // block (each staged column chunk then serves 8 tiles)
-    if (D >= 32) G = std::max<long long>(1, std::min<long long>(G, (A.n + 16 * kTW - 1) / (16 * kTW)));
+    if (D == 3 || D >= 32) G = std::max<long long>(1, std::min<long long>(G, (A.n + 16 * kTW - 1) / (16 * kTW)));
     const size_t n = A.n, m = A.m;
     size_t off = 0;
     const size_t o_args = off; off = align_up(off + sizeof(TiledArgs));
@@ -1237,7 +1300,7 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     if (e == hipSuccess) {
         double *tr = TR ? p->err_trace : nullptr;
         long long tl = TR ? p->trace_len : 0;
-        void *kargs[] = {&d_args, &tr, &tl};
+        void *kargs[] = {&A, &tr, &tl};
         e = hipLaunchCooperativeKernel((const void *)tiled_solve<D, TR, CD>, dim3((unsigned)G), dim3(kTT), kargs, lds, s);
     }
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);

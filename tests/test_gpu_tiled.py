@@ -31,8 +31,11 @@ def _points(seed, n, m, d, kind):
     return rng.uniform(0, 1, (n, d)).astype(np.float32), rng.uniform(0, 1, (m, d)).astype(np.float32)
 
 
+# d <= 3 runs the FP64 matrix-core sweeps: cosine included, and 40000 rows give
+# every wave several 16-row tiles (rounds) on 256 blocks
 CASES = [(0, 500, 700, 3, 1e-2), (1, 300, 200, 8, 3e-3), (0, 64, 1500, 16, 2e-2), (0, 5, 3000, 2, 1e-2),
-         (0, 1, 1, 1, 1e-1), (0, 2000, 64, 3, 1e-3), (1, 77, 9000, 4, 1e-2)]
+         (0, 1, 1, 1, 1e-1), (0, 2000, 64, 3, 1e-3), (1, 77, 9000, 4, 1e-2), (1, 300, 700, 3, 3e-3),
+         (0, 40000, 40, 2, 2e-2)]
 
 
 @pytest.mark.parametrize("method", [0, 1])
