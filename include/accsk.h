@@ -399,6 +399,23 @@ accsk_status accsk_backward_points(const float *X, const float *Y, int64_t batch
                                    float *dX, float *dY, double *da, double *db, void *stream);
 
 /*
+ * Gradients of the EOT value of an explicit-cost problem at the potentials
+ * (f, g) by the envelope theorem (eq:P-from-dual): dC = grad_scale * P with
+ * P_ij = exp((f_i + g_j - C_ij)/eps) (FP64 argument and exponential, written as
+ * FP32, device n x m with leading dimension lddc >= m), and, if not NULL,
+ * da = grad_scale * (f - <f, a/sum a>)/sum a and db likewise (device FP64), the
+ * gradients with respect to un-normalized marginals.  C (leading dimension
+ * ldc >= m) may be NULL when dC is; a, b may be NULL when da, db are.
+ * grad_scale: device FP64[1] upstream gradient, or NULL for 1.  f, g are the
+ * potentials a solve returned (device FP64).  Nothing is allocated; the call
+ * only enqueues work on stream.
+ */
+accsk_status accsk_backward_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,
+                                  const double *a, const double *b, const double *f, const double *g,
+                                  const double *grad_scale, float *dC, int64_t lddc, double *da, double *db,
+                                  void *stream);
+
+/*
  * ---------------------------------------------------------------------------
  * Serving loop (continuous batching of point-cloud requests).
  *

@@ -431,6 +431,9 @@ def _register_points(L):
     L.accsk_backward_points.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.accsk_backward_points.restype = ctypes.c_int
+    L.accsk_backward_dense.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
+                                       _vp]
+    L.accsk_backward_dense.restype = ctypes.c_int
     L.accsk_cost_max_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, ctypes.POINTER(_dbl), _vp]
     L.accsk_cost_max_points.restype = ctypes.c_int
     L.accsk_plan_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, _dbl, _vp, _vp, _i64, _i64, _vp,
@@ -639,6 +642,77 @@ def backward_points(X, Y, a, b, f, g, eps, kind=SQEUCLID, cost_scale=1.0, grad_s
     if single:
         return dX[0], dY[0], (da[0] if marginals else None), (db[0] if marginals else None)
     return dX, dY, da, db
+
+
+def backward_dense(C, a, b, f, g, eps, grad_scale=None, cost=True, marginals=True):
+    """Envelope-theorem gradients of EOT on an explicit cost at potentials (f, g).
+
+    Returns (dC, da, db): dC = grad_scale * P (float32 [n, m], None if cost=False),
+    da, db the gradients with respect to the un-normalized marginals (float64, None
+    if marginals=False).  grad_scale: None or a float64 device scalar tensor.
+    """
+    import torch
+    _check_dev(C, torch.float32, "C", 2)
+    _check_dev(f, torch.float64, "f", 1)
+    _check_dev(g, torch.float64, "g", 1)
+    if C.stride(1) != 1:
+        raise ValueError("C must have unit column stride")
+    n, m = C.shape
+    a = a.contiguous()
+    b = b.contiguous()
+    dC = torch.empty((n, m), dtype=torch.float32, device=C.device) if cost else None
+    da = torch.empty_like(a) if marginals else None
+    db = torch.empty_like(b) if marginals else None
+    gs = None
+    if grad_scale is not None:
+        gs = grad_scale.to(device=C.device, dtype=torch.float64).reshape(1).contiguous()
+    st = _points_lib().accsk_backward_dense(
+        _ptr(C), n, m, C.stride(0), float(eps), _ptr(a), _ptr(b), _ptr(f.contiguous()), _ptr(g.contiguous()),
+        _ptr(gs) if gs is not None else None, _ptr(dC) if dC is not None else None, m,
+        _ptr(da) if da is not None else None, _ptr(db) if db is not None else None, _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_backward_dense")
+    return dC, da, db
+
+
+def _eot_dense_function():
+    import torch
+
+    class EOTDenseLoss(torch.autograd.Function):
+        """EOT value of one explicit-cost problem, differentiable in C, a and b.
+
+        Forward solves with the library and returns the FP64 EOT value; backward
+        gives dEOT/dC = P (eq:P-from-dual) and the marginal gradients, scaled by
+        the incoming gradient, from accsk_backward_dense.
+        """
+
+        @staticmethod
+        def forward(ctx, C, a, b, eps, tol, method):
+            f, g, res = solve_dense(C, a, b, eps, tol=tol, method=method)
+            ctx.save_for_backward(C, a, b, f, g)
+            ctx.eps = eps
+            return torch.tensor(res["eot_value"], dtype=torch.float64, device=C.device)
+
+        @staticmethod
+        def backward(ctx, grad):
+            C, a, b, f, g = ctx.saved_tensors
+            dC, da, db = backward_dense(C, a, b, f, g, ctx.eps, grad_scale=grad.detach(),
+                                        cost=ctx.needs_input_grad[0],
+                                        marginals=ctx.needs_input_grad[1] or ctx.needs_input_grad[2])
+            return dC, da, db, None, None, None
+
+    return EOTDenseLoss
+
+
+_EOT_DENSE = None
+
+
+def eot_loss_dense(C, a, b, eps, tol=1e-6, method=ACC):
+    """Differentiable EOT value (torch.autograd) of an explicit FP32 cost C [n, m]; see EOTDenseLoss."""
+    global _EOT_DENSE
+    if _EOT_DENSE is None:
+        _EOT_DENSE = _eot_dense_function()
+    return _EOT_DENSE.apply(C, a, b, eps, tol, method)
 
 
 def _eot_function():

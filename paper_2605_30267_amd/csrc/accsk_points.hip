@@ -235,6 +235,30 @@ __global__ __launch_bounds__(256) void grad_marginal(const double *__restrict__ 
     for (long long i = threadIdx.x; i < len; i += 256) out[i] = gscale * (pot[i] - mean) / sw_;
 }
 
+// dEOT/dC = gscale P for an explicit cost (envelope theorem, eq:P-from-dual):
+// P_ij = exp((f_i + g_j - C_ij)/eps), FP64 argument and exponential, FP32
+// output.  Block (x, y): columns 1024 x + [0, 1024), rows y, y + gridDim.y, ...;
+// thread t takes columns t, t + 256, t + 512, t + 768 of its block (coalesced).
+__global__ __launch_bounds__(256) void grad_cost_rows(const float *__restrict__ C, long long n, long long m,
+                                                      long long ldc, double inv_eps, const double *__restrict__ f,
+                                                      const double *__restrict__ g,
+                                                      const double *__restrict__ gsc, float *__restrict__ dC,
+                                                      long long ldd) {
+    const double gs = gsc ? gsc[0] : 1.0;
+    const long long j0 = (long long)blockIdx.x * 1024 + threadIdx.x;
+    double gj[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) gj[k] = j0 + 256 * k < m ? g[j0 + 256 * k] : 0.0;
+    for (long long i = blockIdx.y; i < n; i += gridDim.y) {
+        const double fi = f[i];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const long long j = j0 + 256 * k;
+            if (j < m) dC[i * ldd + j] = (float)(gs * exp((fi + gj[k] - (double)C[i * ldc + j]) * inv_eps));
+        }
+    }
+}
+
 // Plan rows from points (eq:P-from-dual): 16 x 16 tiles of
 // P_ij = exp((f_i + g_j - C_ij) / eps), C_ij in FP64 as in cost_fp64, FP64
 // exponential, FP32 output.  Tile row r covers plan row row0 + r.
@@ -698,5 +722,22 @@ extern "C" accsk_status accsk_backward_points(const float *X, const float *Y, in
     }
     if (da && a) hipLaunchKernelGGL(grad_marginal, dim3((unsigned)batch), dim3(256), 0, s, f, a, n, n, n, grad_scale, da);
     if (db && b) hipLaunchKernelGGL(grad_marginal, dim3((unsigned)batch), dim3(256), 0, s, g, b, m, m, m, grad_scale, db);
+    return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+extern "C" accsk_status accsk_backward_dense(const float *C, int64_t n, int64_t m, int64_t ldc, double eps,
+                                             const double *a, const double *b, const double *f, const double *g,
+                                             const double *grad_scale, float *dC, int64_t lddc, double *da,
+                                             double *db, void *stream) {
+    if (!f || !g || (dC && !C) || (da && !a) || (db && !b) || !finite_pos(eps)) return ACCSK_INVALID_ARG;
+    if (n < 1 || m < 1 || (dC && (ldc < m || lddc < m))) return ACCSK_SHAPE;
+    hipStream_t s = (hipStream_t)stream;
+    if (dC) {
+        const dim3 grid((unsigned)((m + 1023) / 1024), (unsigned)std::min<int64_t>(n, 4096));
+        hipLaunchKernelGGL(grad_cost_rows, grid, dim3(256), 0, s, C, (long long)n, (long long)m, (long long)ldc,
+                           1.0 / eps, f, g, grad_scale, dC, (long long)lddc);
+    }
+    if (da) hipLaunchKernelGGL(grad_marginal, dim3(1), dim3(256), 0, s, f, a, n, n, n, grad_scale, da);
+    if (db) hipLaunchKernelGGL(grad_marginal, dim3(1), dim3(256), 0, s, g, b, m, m, m, grad_scale, db);
     return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
 }

@@ -209,3 +209,17 @@ def test_host_validation_async(lib):
     h = accsk._points_lib().accsk_solve_points_batched_async
     assert h(fake, fake, 2, 4, 4, 3, 0, 1.0, fake, fake, ctypes.byref(p), fake, fake, None, None) == accsk.INVALID_ARG
     assert h(fake, fake, 2, 4, 4, 0, 0, 1.0, fake, fake, ctypes.byref(p), fake, fake, fake, None) == accsk.SHAPE
+
+
+def test_host_validation_backward_dense(lib):
+    """accsk_backward_dense: missing arrays, eps and shapes fail before any device work."""
+    fake = ctypes.c_void_p(4096)  # never dereferenced
+    f = accsk._points_lib().accsk_backward_dense
+    # (C, n, m, ldc, eps, a, b, f, g, grad_scale, dC, lddc, da, db, stream)
+    assert f(fake, 4, 5, 5, 0.1, fake, fake, None, fake, None, fake, 5, None, None, None) == accsk.INVALID_ARG
+    assert f(None, 4, 5, 5, 0.1, fake, fake, fake, fake, None, fake, 5, None, None, None) == accsk.INVALID_ARG
+    assert f(fake, 4, 5, 5, 0.1, None, fake, fake, fake, None, None, 5, fake, None, None) == accsk.INVALID_ARG
+    assert f(fake, 4, 5, 5, 0.0, fake, fake, fake, fake, None, fake, 5, None, None, None) == accsk.INVALID_ARG
+    assert f(fake, 4, 5, 4, 0.1, fake, fake, fake, fake, None, fake, 5, None, None, None) == accsk.SHAPE
+    assert f(fake, 4, 5, 5, 0.1, fake, fake, fake, fake, None, fake, 4, None, None, None) == accsk.SHAPE
+    assert f(fake, 0, 5, 5, 0.1, fake, fake, fake, fake, None, fake, 5, None, None, None) == accsk.SHAPE
