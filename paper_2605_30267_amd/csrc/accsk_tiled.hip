@@ -627,35 +627,39 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
             ao.a64 = k == 3 ? 1.0 : (k < d ? coef * (double)A.X[i * d + k] : 0.0);
         }
     };
-    // BF16 engine: x_i . y_j of one column tile; the tile's B operands are read first, the
-    // products go into two independent accumulators (small products first in each), summed
-    // at the end.  S3: the six products of split 3, else the three of split 2.
-    auto bf_tile = [&](auto S3, const bf16x8 *bt, const AOps &ao) -> floatx4 {
-        bf16x8 bh[KC], bm[KC], bl[KC];
+    // BF16 engine: x_i . y_j of one column tile from its B operands (read from LDS by
+    // load_b): the products go into two independent accumulators (small products first in
+    // each), summed at the end.  S3: the six products of split 3, else the three of split 2.
+    struct BOps {
+        bf16x8 h[KC], m_[KC], l[KC];
+    };
+    auto load_b = [&](auto S3, const bf16x8 *bt, BOps &bo) {
 #pragma unroll
         for (int kc = 0; kc < KC; kc++) {
-            bh[kc] = bt[(kc * 3) * 64];
-            bm[kc] = bt[(kc * 3 + 1) * 64];
-            if constexpr (decltype(S3)::value) bl[kc] = bt[(kc * 3 + 2) * 64];
+            bo.h[kc] = bt[(kc * 3) * 64];
+            bo.m_[kc] = bt[(kc * 3 + 1) * 64];
+            if constexpr (decltype(S3)::value) bo.l[kc] = bt[(kc * 3 + 2) * 64];
         }
+    };
+    auto bf_tile = [&](auto S3, const BOps &bo, const AOps &ao) -> floatx4 {
         floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
         if constexpr (decltype(S3)::value) {
 #pragma unroll
             for (int kc = 0; kc < KC; kc++) {
-                c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.m_[kc], bm[kc], c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bl[kc], c1, 0, 0, 0);
-                c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.l[kc], bh[kc], c0, 0, 0, 0);
+                c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.m_[kc], bo.m_[kc], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bo.l[kc], c1, 0, 0, 0);
+                c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.l[kc], bo.h[kc], c0, 0, 0, 0);
             }
         }
 #pragma unroll
         for (int kc = 0; kc < KC; kc++) {
-            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bm[kc], c1, 0, 0, 0);
-            c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.m_[kc], bh[kc], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bo.m_[kc], c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.m_[kc], bo.h[kc], c0, 0, 0, 0);
         }
 #pragma unroll
         for (int kc = 0; kc < KC; kc++) {
-            if (kc & 1) c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bh[kc], c0, 0, 0, 0);
-            else c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bh[kc], c1, 0, 0, 0);
+            if (kc & 1) c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bo.h[kc], c0, 0, 0, 0);
+            else c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao.h[kc], bo.h[kc], c1, 0, 0, 0);
         }
         return c0 + c1;
     };
@@ -666,9 +670,14 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
         if constexpr (BF) {
             const bf16x8 *b0 = ylp + (size_t)buf * BU + lane;
             const double *ct = colt + buf * MCH + (lane & 15);
+            // the next tile's B operands are read before this tile's products, so that
+            // their LDS latency overlaps the matrix-core work
+            BOps bo[2];
+            load_b(S3, b0, bo[0]);
 #pragma unroll
             for (int t = 0; t < NTC; t++) {
-                const floatx4 c = bf_tile(S3, b0 + t * KC * 3 * 64, ao);
+                if (t + 1 < NTC) load_b(S3, b0 + (t + 1) * KC * 3 * 64, bo[(t + 1) & 1]);
+                const floatx4 c = bf_tile(S3, bo[t & 1], ao);
                 const double x0 = ct[t * 16];
                 double arg[4];
 #pragma unroll
