@@ -808,6 +808,14 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                 auto shift_src = [&](long long j) {
                     return exact ? (mxs ? 0.0 : A.partmax[(size_t)bid * m + j]) : A.colL[j];
                 };
+                if (nround == 0) {  // a block without rows: its partials are the identity
+                    for (long long j = tid; j < m; j += kTT) {
+                        const size_t o = (size_t)bid * m + j;
+                        if (mxs) A.partmax[o] = -INFINITY;
+                        else if (exact) A.part[o] = 0.0;
+                        else xstore(&A.partf[o], 0.0f);
+                    }
+                }
                 for (int round = 0; round < nround; round++) {
                     const int tile = round * kTW + wid;
                     const bool act = tile < ntile;
@@ -1125,19 +1133,56 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
         // <C, P> at the returned potentials: C in FP64 (recomputed from the points)
         double cst = 0.0;
         if (!(A.flags & ACCSK_FLAG_NO_COST)) {
-            for (long long i = r0 + wid; i < r1; i += kTW) {
-                const double u2 = A.rowU[i];
-                for (long long j = lane; j < m; j += 64) {
-                    double cij;
-                    if (D == 0) {
-                        cij = (double)A.C[i * A.ldc + j];
-                    } else {
-                        double dot = 0.0;
-                        for (long long k = 0; k < d; k++) dot = fma((double)A.X[i * d + k], (double)A.Y[j * d + k], dot);
-                        cij = (sq ? A.xnrm[i] + A.ynrm[j] - 2.0 * dot : 1.0 - dot) * A.inv_s;
+            if constexpr (D == 0) {
+                for (long long i = r0 + wid; i < r1; i += kTW) {
+                    const double u2 = A.rowU[i];
+                    for (long long j = lane; j < m; j += 64) {
+                        const double cij = (double)A.C[i * A.ldc + j];
+                        const double t = A.xg[j] - kap2 * cij + u2;
+                        cst += cij * (double)__builtin_amdgcn_exp2f((float)t);
                     }
-                    const double t = A.xg[j] - kap2 * cij + u2;
-                    cst += cij * (double)__builtin_amdgcn_exp2f((float)t);
+                }
+            } else {
+                // 64 columns at a time in LDS (FP64, feature-major: lane c reads feature k of
+                // its column at k * 64 + c), one column per lane; each wave takes four rows at
+                // a time, so every LDS read feeds four FP64 FMAs
+                constexpr int EC = 64, ER = 4;
+                double *eyl = tl;              // [d][EC]
+                double *exg = tl + d * EC;     // [EC] x_j
+                double *eyn = exg + EC;        // [EC] |y_j|^2
+                for (long long ja = 0; ja < m; ja += EC) {
+                    __syncthreads();
+                    for (long long q = tid; q < EC * d; q += kTT) {
+                        const long long c = q % EC, k = q / EC, j = std::min(ja + c, m - 1);
+                        eyl[q] = (double)A.Y[j * d + k];
+                    }
+                    if (tid < EC) {
+                        const long long j = std::min(ja + tid, m - 1);
+                        exg[tid] = ja + tid < m ? A.xg[j] : -INFINITY;
+                        eyn[tid] = A.ynrm[j];
+                    }
+                    __syncthreads();
+                    for (long long i0 = r0 + (long long)wid * ER; i0 < r1; i0 += (long long)kTW * ER) {
+                        long long ir[ER];
+                        double dot[ER];
+#pragma unroll
+                        for (int r = 0; r < ER; r++) {
+                            ir[r] = std::min(i0 + r, r1 - 1);
+                            dot[r] = 0.0;
+                        }
+                        for (long long k = 0; k < d; k++) {
+                            const double y = eyl[k * EC + lane];
+#pragma unroll
+                            for (int r = 0; r < ER; r++) dot[r] = fma((double)A.X[ir[r] * d + k], y, dot[r]);
+                        }
+#pragma unroll
+                        for (int r = 0; r < ER; r++) {
+                            if (i0 + r >= r1) continue;
+                            const double cij = (sq ? A.xnrm[ir[r]] + eyn[lane] - 2.0 * dot[r] : 1.0 - dot[r]) * A.inv_s;
+                            const double t = exg[lane] - kap2 * cij + A.rowU[ir[r]];
+                            if (t > -INFINITY) cst += cij * (double)__builtin_amdgcn_exp2f((float)t);
+                        }
+                    }
                 }
             }
             cst = tblock_sum(cst, sred);

@@ -188,3 +188,29 @@ def test_on_the_fly_small_eps_fallback(torch_gpu, method):
     print("eps 1e-4 method", method, "It", r["iters"], "fallback", r["fallback_steps"], "err", ev["err"], flush=True)
     assert r["converged"] == 1 and ev["err"] <= 1e-6 * 1.0001
     assert abs(r["eot_value"] - ev["dual"]) <= 2e-7 * eps + 1e-12 * abs(ev["dual"])
+
+
+@pytest.mark.parametrize("d,split", [(2, 0), (33, 3)])
+def test_blocks_without_rows_on_reused_workspace(torch_gpu, d, split):
+    """40000 rows over 256 blocks of 160 rows leave the last six blocks without rows; their
+    column partials must still be written (as zeros) every step.  The second of two identical
+    solves runs on workspace the first one left dirty: it must converge and equal the first
+    bit for bit (d = 2: FP64 matrix-core sweeps; d = 33: BF16 split-3 sweeps)."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    n, m, eps = 40000, 40, 2e-2
+    X, Y = _points(31 + d, n, m, d, 0)
+    rng = np.random.default_rng(32)
+    a, b = rng.uniform(0.5, 1.5, n), rng.uniform(0.5, 1.5, m)
+    s = float(d)
+    args = [_dev(torch, X, torch.float32), _dev(torch, Y, torch.float32), _dev(torch, a, torch.float64),
+            _dev(torch, b, torch.float64), eps]
+    print("case blocks without rows, d", d, flush=True)
+    outs = []
+    for _ in range(2):
+        f, g, res = accsk.solve_points(*args, cost_scale=s, split=split, on_the_fly=True)
+        torch.cuda.synchronize()
+        outs.append((f, g, res[0]))
+        assert res[0]["converged"] == 1, res[0]
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    assert outs[0][2]["iters"] == outs[1][2]["iters"]
