@@ -52,8 +52,18 @@
 namespace accsk {
 namespace {
 
-constexpr int kTT = 512;          // threads per block
+constexpr int kTT = 512;          // threads per block (explicit costs, FP64 sweeps)
 constexpr int kTW = kTT / 64;     // waves per block
+
+// Block shape of tiled_solve<D>: the BF16 matrix-core sweeps run 256 threads (one
+// wave per SIMD, up to 512 registers each, so that a wave can hold two row tiles);
+// everything else 512.
+template <int D>
+struct TBlk {
+    static constexpr int TT = D >= 32 ? 256 : kTT;
+    static constexpr int TW = TT / 64;
+    static constexpr int ROWS = 16 * TW * (D >= 32 ? 2 : 1);  // rows per block and round (matrix-core sweeps)
+};
 constexpr int kTNS = 8;           // block scalar slots: 0 <u,a>, 1 sum S^, 2 err, 3 mass, 4 <x,b>, 5 fallback
 constexpr int kTRB = 256;         // rows staged per row group of the column sweep
 
@@ -70,7 +80,8 @@ template <int D>
 size_t tiled_lds_bytes() {
     if (D >= 32) {  // two buffers of Y pieces [tiles][D/32 chunks][3 pieces][64 lanes] x 16 B, column terms, wave sums
         const size_t mch = D == 128 ? 64 : 128;
-        return 2 * (mch / 16) * (D / 32) * 3 * 64 * 16 + 2 * mch * sizeof(double) + (size_t)kTW * mch * sizeof(double);
+        return 2 * (mch / 16) * (D / 32) * 3 * 64 * 16 + 2 * mch * sizeof(double) +
+               (size_t)TBlk<D>::TW * mch * sizeof(double);
     }
     if (D == 3) return 2 * (size_t)(512 / 16) * 64 * sizeof(double) + (size_t)kTW * 512 * sizeof(double);
     using Cf = TCfg<D>;
@@ -237,13 +248,14 @@ __device__ __forceinline__ double readlane63_f64(double v) {
 // they would be flat_* instructions, which count on the LDS counter as well: every
 // wait for an LDS read would then also wait for the outstanding global loads.)
 template <int D, bool TR = false, bool CD = false>
-__global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__restrict__ trace,
-                                                   long long trace_len) {
+__global__ __launch_bounds__(TBlk<D>::TT) __attribute__((amdgpu_waves_per_eu(D >= 32 ? 1 : 2)))
+void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_len) {
+    constexpr int TT = TBlk<D>::TT, TW = TBlk<D>::TW;
     using Cf = TCfg<D>;
     constexpr int RW = Cf::RW, CH = Cf::CH, CPL = Cf::CPL, RG = Cf::RG, DD = Cf::DD;
     extern __shared__ double tl[];
     __shared__ double tot[kTNS];
-    __shared__ double sred[kTW * 64];
+    __shared__ double sred[TW * 64];
     __shared__ int bflag, sflag;
     __shared__ CondPending cpend;  // used by block 0 only
 
@@ -277,7 +289,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
     const double coef = sq ? 2.0 * ks : ks;  // cross-term coefficient
     const double La2 = A.gscal[0];
 
-    for (long long i = r0 + tid; i < r1; i += kTT) A.rowL[i] = INFINITY;
+    for (long long i = r0 + tid; i < r1; i += TT) A.rowL[i] = INFINITY;
 
     // ---- helpers -------------------------------------------------------
     // row constant r_i (log2 units) of the folded argument
@@ -304,7 +316,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
     constexpr bool MF = D == 3 || D >= 32;  // matrix-core sweeps (further below)
     auto stage_cols = [&](long long ja, int len) {
         if constexpr (!MF) {
-            for (int c = tid; c < len; c += kTT) {
+            for (int c = tid; c < len; c += TT) {
                 const long long j = ja + c;
                 if (D > 0)
 #pragma unroll
@@ -457,7 +469,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                     for (long long rb0 = 0; rb0 < nr; rb0 += kTRB) {
                         const int rl = (int)std::min<long long>(kTRB, nr - rb0);
                         __syncthreads();
-                        for (int r = tid; r < rl; r += kTT) {
+                        for (int r = tid; r < rl; r += TT) {
                             const long long i = r0 + rb0 + r;
 #pragma unroll
                             for (int k = 0; k < DD; k++)
@@ -509,9 +521,10 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
 
     // ---- matrix-core sweeps (D = 3 and D >= 32) --------------------------------
     // Both sweeps walk the columns in chunks of MCH staged in LDS, two buffers: the
-    // next chunk is loaded while the current one is used.  Each wave owns one
-    // 16-row tile per round and computes 16 x 16 tiles of the exponent argument
-    // on the matrix cores:
+    // next chunk is loaded while the current one is used.  Each wave owns RT
+    // 16-row tiles per round (BF16 engine: two, so that every B operand read from
+    // LDS feeds both) and computes 16 x 16 tiles of the exponent argument on the
+    // matrix cores:
     //  * D >= 32 (BF16 engine): x_i . y_j from v_mfma_f32_16x16x32_bf16 on the
     //    BF16 pieces (split_pieces layout: unit ((T KC + kc) 3 + piece) 64 + lane
     //    holds features kc 32 + (lane / 16) 8 + [0, 8) of point 16 T + lane % 16),
@@ -527,17 +540,20 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
     constexpr int MCH = BF ? (D == 128 ? 64 : 128) : 512;  // columns per chunk
     constexpr int NTC = MCH / 16;                         // column tiles per chunk
     constexpr int BU = BF ? NTC * KC * 3 * 64 : NTC * 64; // B units per buffer (16 B BF16 pieces, 8 B FP64)
-    constexpr int PF = BF ? BU / kTT : 1;                 // direct loads per thread and chunk
-    static_assert(!MF || !BF || BU % kTT == 0, "chunk units per thread");
-    static_assert(!MF || MCH <= kTT, "one column per thread");
+    constexpr int PF = BF ? BU / TT : 1;                  // direct loads per thread and chunk
+    constexpr int RT = BF ? 2 : 1;                        // 16-row tiles per wave and round
+    static_assert(!MF || !BF || BU % TT == 0, "chunk units per thread");
+    static_assert(!MF || MCH <= TT, "one column per thread");
     typedef double f64x4 __attribute__((ext_vector_type(4)));
     bf16x8 *ylp = reinterpret_cast<bf16x8 *>(tl);                       // BF16: [2][BU]
     double *yl64 = tl;                                                  // FP64: [2][NTC][64]
     double *colt = BF ? reinterpret_cast<double *>(ylp + 2 * BU) : tl + 2 * BU;  // BF16: [2][MCH] column terms
-    double *mcp = BF ? colt + 2 * MCH : tl + 2 * BU;                    // [kTW][MCH] per-wave column values
+    double *mcp = BF ? colt + 2 * MCH : tl + 2 * BU;                    // [TW][MCH] per-wave column values
     const int split = A.split;
     const int ntile = (int)((nr + 15) / 16);  // the block's 16-row tiles (r0 is a multiple of 16)
-    const int nround = (ntile + kTW - 1) / kTW;
+    const int nround = (ntile + TW * RT - 1) / (TW * RT);
+    // the block-relative tile of row tile rt of this wave in a round
+    auto wtile = [&](int round, int rt) -> int { return (round * TW + wid) * RT + rt; };
     const long long ytiles = (m + 15) / 16, xtiles = (n + 15) / 16;
     // block-relative row of (lane, q) in the wave's tile
     auto trow = [&](int q) -> int { return BF ? 4 * (lane >> 4) + q : (lane >> 4) + 4 * q; };
@@ -550,16 +566,16 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
     auto fetch = [&](long long ja, int buf, auto col_shift) {
         if constexpr (BF) {
             // this thread's share of the chunk's pieces, straight into LDS buffer buf
-            // (wave w's lanes fill units u kTT + 64 w + [0, 64))
+            // (wave w's lanes fill units u TT + 64 w + [0, 64))
             const long long t0 = ja / 16;
             const long long last = (ytiles - t0) * KC * 3 * 64 - 1;
             const bf16x8 *src = A.Ypk + t0 * KC * 3 * 64;
 #pragma unroll
             for (int u = 0; u < PF; u++) {
-                const long long unit = std::min<long long>((long long)u * kTT + tid, last);
+                const long long unit = std::min<long long>((long long)u * TT + tid, last);
                 __builtin_amdgcn_global_load_lds(
                     (__attribute__((address_space(1))) const void *)(src + unit),
-                    (__attribute__((address_space(3))) void *)(ylp + (size_t)buf * BU + u * kTT + wid * 64), 16, 0, 0);
+                    (__attribute__((address_space(3))) void *)(ylp + (size_t)buf * BU + u * TT + wid * 64), 16, 0, 0);
             }
         }
         if (tid < MCH) {
@@ -663,10 +679,11 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
         }
         return c0 + c1;
     };
-    // For every column tile t of the staged chunk: arg[q] = the exponent argument of
-    // (row trow(q), column 16 t + lane % 16), given the row terms rt[q] (BF16: added in
-    // FP64 after the product; FP64: the accumulator input); then use(t, arg).
-    auto for_tiles = [&](auto S3, int buf, const AOps &ao, const double (&rt)[4], auto use) {
+    // For every column tile t of the staged chunk: arg[rt][q] = the exponent argument of
+    // (row trow(q) of the wave's row tile rt, column 16 t + lane % 16), given the row terms
+    // rt_[rt][q] (BF16: added in FP64 after the product; FP64: the accumulator input); then
+    // use(t, arg).
+    auto for_tiles = [&](auto S3, int buf, const AOps (&ao)[RT], const double (&rt_)[RT][4], auto use) {
         if constexpr (BF) {
             const bf16x8 *b0 = ylp + (size_t)buf * BU + lane;
             const double *ct = colt + buf * MCH + (lane & 15);
@@ -677,25 +694,32 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
 #pragma unroll
             for (int t = 0; t < NTC; t++) {
                 if (t + 1 < NTC) load_b(S3, b0 + (t + 1) * KC * 3 * 64, bo[(t + 1) & 1]);
-                const floatx4 c = bf_tile(S3, bo[t & 1], ao);
-                const double x0 = ct[t * 16];
-                double arg[4];
+                floatx4 c[RT];
 #pragma unroll
-                for (int q = 0; q < 4; q++) arg[q] = fma(coef, (double)c[q], rt[q] + x0);
+                for (int r = 0; r < RT; r++) c[r] = bf_tile(S3, bo[t & 1], ao[r]);
+                const double x0 = ct[t * 16];
+                double arg[RT][4];
+#pragma unroll
+                for (int r = 0; r < RT; r++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) arg[r][q] = fma(coef, (double)c[r][q], rt_[r][q] + x0);
                 use(t, arg);
             }
         } else {
-            const f64x4 cin = {rt[0], rt[1], rt[2], rt[3]};
+            const f64x4 cin = {rt_[0][0], rt_[0][1], rt_[0][2], rt_[0][3]};
             const double *b0 = yl64 + (size_t)buf * BU + lane;
             constexpr int G4 = 4;  // independent products in flight
 #pragma unroll
             for (int t0 = 0; t0 < NTC; t0 += G4) {
                 f64x4 dv[G4];
 #pragma unroll
-                for (int g = 0; g < G4; g++) dv[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao.a64, b0[(t0 + g) * 64], cin, 0, 0, 0);
+                for (int g = 0; g < G4; g++)
+                    dv[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[0].a64, b0[(t0 + g) * 64], cin, 0, 0, 0);
 #pragma unroll
                 for (int g = 0; g < G4; g++) {
-                    double arg[4] = {dv[g][0], dv[g][1], dv[g][2], dv[g][3]};
+                    double arg[RT][4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) arg[0][q] = dv[g][q];
                     use(t0 + g, arg);
                 }
             }
@@ -713,67 +737,94 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
     auto mrow_sweep = [&]() {
         if constexpr (MF) {
             for (int round = 0; round < nround; round++) {
-                const int tile = round * kTW + wid;
-                const bool act = tile < ntile;
-                AOps ao;
-                load_a(tile, ao);
-                double rc[4], shift[4];
-                long long ri[4];
-                bool rv[4];
+                bool act[RT];
+                AOps ao[RT];
+                double rc[RT][4], shift[RT][4];
+                long long ri[RT][4];
+                bool rv[RT][4];
                 int unknown = 0;
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const long long lr = (long long)tile * 16 + trow(q);
-                    rv[q] = act && lr < nr;
-                    ri[q] = r0 + std::max(0LL, std::min(lr, nr - 1));
-                    rc[q] = row_const(ri[q]);
-                    shift[q] = rv[q] ? A.rowL[ri[q]] : 0.0;
-                    unknown |= (rv[q] && !(shift[q] < INFINITY)) ? 1 : 0;
+                for (int r = 0; r < RT; r++) {
+                    const int tile = wtile(round, r);
+                    act[r] = tile < ntile;
+                    load_a(tile, ao[r]);
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const long long lr = (long long)tile * 16 + trow(q);
+                        rv[r][q] = act[r] && lr < nr;
+                        ri[r][q] = r0 + std::max(0LL, std::min(lr, nr - 1));
+                        rc[r][q] = row_const(ri[r][q]);
+                        shift[r][q] = rv[r][q] ? A.rowL[ri[r][q]] : 0.0;
+                        unknown |= (rv[r][q] && !(shift[r][q] < INFINITY)) ? 1 : 0;
+                    }
                 }
+                const bool wact = act[0];  // the wave has work this round (its first tile is in range)
                 __syncthreads();
                 if (tid == 0) sflag = 0;
                 __syncthreads();
                 if (unknown) atomicOr(&sflag, 1);
                 __syncthreads();
                 bool need_max = sflag != 0;
-                double S[4];
+                double S[RT][4];
                 for (int attempt = 0; attempt < 2; attempt++) {
                     if (need_max) {
-                        double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+                        double mx[RT][4];
+#pragma unroll
+                        for (int r = 0; r < RT; r++)
+#pragma unroll
+                            for (int q = 0; q < 4; q++) mx[r][q] = -INFINITY;
                         with_split([&](auto S3) {
                             for_chunks(zero_shift, [&](long long, int buf) {
-                                if (!act) return;
-                                for_tiles(S3, buf, ao, rc, [&](int, const double (&arg)[4]) {
+                                if (!wact) return;
+                                for_tiles(S3, buf, ao, rc, [&](int, const double (&arg)[RT][4]) {
 #pragma unroll
-                                    for (int q = 0; q < 4; q++) mx[q] = fmax(mx[q], arg[q]);
+                                    for (int r = 0; r < RT; r++)
+#pragma unroll
+                                        for (int q = 0; q < 4; q++) mx[r][q] = fmax(mx[r][q], arg[r][q]);
                                 });
                             });
                         });
 #pragma unroll
-                        for (int q = 0; q < 4; q++) shift[q] = row16_max(mx[q]);
-                    }
-                    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-                    double base[4];
+                        for (int r = 0; r < RT; r++)
 #pragma unroll
-                    for (int q = 0; q < 4; q++) base[q] = rc[q] - shift[q];
+                            for (int q = 0; q < 4; q++) shift[r][q] = row16_max(mx[r][q]);
+                    }
+                    double acc[RT][4], base[RT][4];
+#pragma unroll
+                    for (int r = 0; r < RT; r++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            acc[r][q] = 0.0;
+                            base[r][q] = rc[r][q] - shift[r][q];
+                        }
                     with_split([&](auto S3) {
                         for_chunks(zero_shift, [&](long long, int buf) {
-                            if (!act) return;
-                            float sp[4] = {0.f, 0.f, 0.f, 0.f};
-                            for_tiles(S3, buf, ao, base, [&](int, const double (&arg)[4]) {
+                            if (!wact) return;
+                            float sp[RT][4];
 #pragma unroll
-                                for (int q = 0; q < 4; q++) sp[q] += __builtin_amdgcn_exp2f((float)arg[q]);
+                            for (int r = 0; r < RT; r++)
+#pragma unroll
+                                for (int q = 0; q < 4; q++) sp[r][q] = 0.f;
+                            for_tiles(S3, buf, ao, base, [&](int, const double (&arg)[RT][4]) {
+#pragma unroll
+                                for (int r = 0; r < RT; r++)
+#pragma unroll
+                                    for (int q = 0; q < 4; q++) sp[r][q] += __builtin_amdgcn_exp2f((float)arg[r][q]);
                             });
 #pragma unroll
-                            for (int q = 0; q < 4; q++) acc[q] += (double)sp[q];
+                            for (int r = 0; r < RT; r++)
+#pragma unroll
+                                for (int q = 0; q < 4; q++) acc[r][q] += (double)sp[r][q];
                         });
                     });
                     int bad = 0;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        S[q] = row16_sum(acc[q]);
-                        bad |= (rv[q] && !(S[q] >= 0x1p-40 && S[q] <= 0x1p40)) ? 1 : 0;
-                    }
+                    for (int r = 0; r < RT; r++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            S[r][q] = row16_sum(acc[r][q]);
+                            bad |= (rv[r][q] && !(S[r][q] >= 0x1p-40 && S[r][q] <= 0x1p40)) ? 1 : 0;
+                        }
                     __syncthreads();
                     if (tid == 0) sflag = 0;
                     __syncthreads();
@@ -784,12 +835,14 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                 }
                 if ((lane & 15) == 0) {
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        if (!rv[q]) continue;
-                        const double lse = shift[q] + dlog2(S[q]);
-                        A.rowL[ri[q]] = lse;
-                        A.rowU[ri[q]] = A.la2[ri[q]] - lse;
-                    }
+                    for (int r = 0; r < RT; r++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            if (!rv[r][q]) continue;
+                            const double lse = shift[r][q] + dlog2(S[r][q]);
+                            A.rowL[ri[r][q]] = lse;
+                            A.rowU[ri[r][q]] = A.la2[ri[r][q]] - lse;
+                        }
                 }
             }
             __syncthreads();
@@ -809,7 +862,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                     return exact ? (mxs ? 0.0 : A.partmax[(size_t)bid * m + j]) : A.colL[j];
                 };
                 if (nround == 0) {  // a block without rows: its partials are the identity
-                    for (long long j = tid; j < m; j += kTT) {
+                        for (long long j = tid; j < m; j += TT) {
                         const size_t o = (size_t)bid * m + j;
                         if (mxs) A.partmax[o] = -INFINITY;
                         else if (exact) A.part[o] = 0.0;
@@ -817,26 +870,34 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                     }
                 }
                 for (int round = 0; round < nround; round++) {
-                    const int tile = round * kTW + wid;
-                    const bool act = tile < ntile;
-                    AOps ao;
-                    load_a(tile, ao);
-                    double rh[4];
+                    bool act[RT];
+                    AOps ao[RT];
+                    double rh[RT][4];
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const long long lr = (long long)tile * 16 + trow(q);
-                        const long long i = r0 + std::max(0LL, std::min(lr, nr - 1));
-                        rh[q] = (act && lr < nr) ? row_const(i) + A.rowU[i] : -INFINITY;
+                    for (int r = 0; r < RT; r++) {
+                        const int tile = wtile(round, r);
+                        act[r] = tile < ntile;
+                        load_a(tile, ao[r]);
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            const long long lr = (long long)tile * 16 + trow(q);
+                            const long long i = r0 + std::max(0LL, std::min(lr, nr - 1));
+                            rh[r][q] = (act[r] && lr < nr) ? row_const(i) + A.rowU[i] : -INFINITY;
+                        }
                     }
+                    const bool wact = act[0];
                     with_split([&](auto S3) {
                         for_chunks(shift_src, [&](long long ja, int buf) {
-                            if (act) {
-                                for_tiles(S3, buf, ao, rh, [&](int t, const double (&arg)[4]) {
+                            if (wact) {
+                                for_tiles(S3, buf, ao, rh, [&](int t, const double (&arg)[RT][4]) {
                                     double v;
                                     if (mxs) {
                                         v = -INFINITY;
 #pragma unroll
-                                        for (int q = 0; q < 4; q++) v = (arg[q] > v || arg[q] != arg[q]) ? arg[q] : v;  // NaN propagates
+                                        for (int r = 0; r < RT; r++)
+#pragma unroll
+                                            for (int q = 0; q < 4; q++)
+                                                v = (arg[r][q] > v || arg[r][q] != arg[r][q]) ? arg[r][q] : v;  // NaN propagates
                                         double u = __shfl_xor(v, 16, 64);
                                         v = (u > v || u != u) ? u : v;
                                         u = __shfl_xor(v, 32, 64);
@@ -844,8 +905,10 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                                     } else {
                                         float p = 0.f;
 #pragma unroll
-                                        for (int q = 0; q < 4; q++) p += __builtin_amdgcn_exp2f((float)arg[q]);
-                                        p += __shfl_xor(p, 16, 64);  // the tile's 16 rows: across the lane groups
+                                        for (int r = 0; r < RT; r++)
+#pragma unroll
+                                            for (int q = 0; q < 4; q++) p += __builtin_amdgcn_exp2f((float)arg[r][q]);
+                                        p += __shfl_xor(p, 16, 64);  // the tiles' rows: across the lane groups
                                         p += __shfl_xor(p, 32, 64);
                                         v = (double)p;
                                     }
@@ -855,11 +918,11 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                                 for (int c = lane; c < MCH; c += 64) mcp[wid * MCH + c] = mxs ? -INFINITY : 0.0;
                             }
                             __syncthreads();
-                            for (int c = tid; c < MCH; c += kTT) {
+                            for (int c = tid; c < MCH; c += TT) {
                                 const long long j = ja + c;
                                 if (j >= m) continue;
                                 double tv = mxs ? -INFINITY : 0.0;
-                                for (int w = 0; w < kTW; w++) {
+                                for (int w = 0; w < TW; w++) {
                                     const double x = mcp[w * MCH + c];
                                     if (mxs) tv = (x > tv || x != x) ? x : tv;
                                     else tv += x;
@@ -934,7 +997,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                 fallbacks++;
             }
             // combine the column slice [j0, j1): thread t sums blocks grp, grp + NGRP, ... of column cb + t % CW
-            constexpr int CW = 32, NGRP = kTT / CW;
+            constexpr int CW = 32, NGRP = TT / CW;
             const int coff = tid % CW, grp = tid / CW;
             double aS = 0.0, aE = 0.0, aC = 0.0, aXB = 0.0, aFB = 0.0;
             for (long long cb = j0; cb < j1; cb += CW) {
@@ -1021,7 +1084,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                 }
             }
             if (!grid_sync(A.bar, gen, &bflag, (unsigned)G)) { status = ACCSK_HIP_ERROR; break; }
-            for (int sidx = wid; sidx < 6; sidx += kTW) {
+            for (int sidx = wid; sidx < 6; sidx += TW) {
                 double v = 0.0;
                 for (int b = lane; b < G; b += 64) v += bs[(size_t)b * kTNS + sidx];
                 v = wave_sum(v);
@@ -1054,20 +1117,20 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
             if (steps > 1 && fval_rose(fval, fp)) incr++;
             if (err < A.tol_stop || it >= A.max_iter) stop = true;
             else {
-                for (long long j = j0 + tid; j < j1; j += kTT) xstore(&A.xg[j], A.shat[j] - mean);
+                for (long long j = j0 + tid; j < j1; j += TT) xstore(&A.xg[j], A.shat[j] - mean);
                 it++;
             }
         } else {
             if (!first) {
                 const double c2 = alpha * alpha - 2.0, inv = 1.0 / (1.0 + alpha);
-                for (long long j = j0 + tid; j < j1; j += kTT)
+                for (long long j = j0 + tid; j < j1; j += TT)
                     A.wg[j] = (A.wg[j] + c2 * A.xg[j] + 2.0 * (A.shat[j] - mean)) * inv;
                 it++;
                 kin++;
                 if (fval_rose(fval, fp)) {
                     incr++;
                     if (A.flags & ACCSK_FLAG_RESTART) {  // safeguard: reset the extrapolation, w <- alpha x
-                        for (long long j = j0 + tid; j < j1; j += kTT) A.wg[j] = alpha * A.xg[j];
+                        for (long long j = j0 + tid; j < j1; j += TT) A.wg[j] = alpha * A.xg[j];
                         restarts++;
                     }
                 }
@@ -1078,7 +1141,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                 const bool stage = !(err < A.tol_stop || it >= A.max_iter) && !first && kin == mstage;
                 const double a_new = dsqrt(mu), ratio = A.w_rule == ACCSK_W_Y_CONTINUOUS ? a_new / alpha : 1.0;
                 const CondCols cc{A.xg, A.wg, A.shat, A.bn, A.cond, A.cond + m, A.cond + 2 * m};
-                const CondSums cv = cond_cols(cc, j0 + tid, j1, kTT, 0, 0.0, 0.0, 0.0, alpha, first ? 0 : 1,
+                const CondSums cv = cond_cols(cc, j0 + tid, j1, TT, 0, 0.0, 0.0, 0.0, alpha, first ? 0 : 1,
                                               stage ? 1 : 0, ratio, a_new);
                 double s6[6] = {cv.lhs1, cv.lhs2, cv.vd, cv.K, cv.l1, cv.vd2};
                 for (int q = 0; q < 6; q++) s6[q] = tblock_sum(s6[q], sred);
@@ -1104,7 +1167,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                     const double mu_new = mu / 2.0;
                     if (A.w_rule == ACCSK_W_Y_CONTINUOUS) {
                         const double ratio = dsqrt(2.0 * mu_new) / alpha;
-                        for (long long j = j0 + tid; j < j1; j += kTT) A.wg[j] *= ratio;
+                        for (long long j = j0 + tid; j < j1; j += TT) A.wg[j] *= ratio;
                     }
                     mu = mu_new;
                     alpha = dsqrt(2.0 * mu);
@@ -1113,7 +1176,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                 }
                 first = false;
                 const double inv = 1.0 / (1.0 + alpha);
-                for (long long j = j0 + tid; j < j1; j += kTT) xstore(&A.xg[j], (A.wg[j] + (A.shat[j] - mean)) * inv);
+                for (long long j = j0 + tid; j < j1; j += TT) xstore(&A.xg[j], (A.wg[j] + (A.shat[j] - mean)) * inv);
             }
         }
         if (stop) break;
@@ -1123,18 +1186,18 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
     // ---------------- outputs ----------------
     if (status == ACCSK_OK || status == ACCSK_DIVERGED) {
         double ua = 0.0;
-        for (long long i = r0 + tid; i < r1; i += kTT) {
+        for (long long i = r0 + tid; i < r1; i += TT) {
             const double u2 = A.rowU[i];
             ua += A.an[i] * u2;
             A.f_out[i] = A.eps * kLn2 * u2;
         }
         ua = tblock_sum(ua, sred);
-        for (long long j = j0 + tid; j < j1; j += kTT) A.g_out[j] = A.eps * kLn2 * A.xg[j];
+        for (long long j = j0 + tid; j < j1; j += TT) A.g_out[j] = A.eps * kLn2 * A.xg[j];
         // <C, P> at the returned potentials: C in FP64 (recomputed from the points)
         double cst = 0.0;
         if (!(A.flags & ACCSK_FLAG_NO_COST)) {
             if constexpr (D == 0) {
-                for (long long i = r0 + wid; i < r1; i += kTW) {
+                for (long long i = r0 + wid; i < r1; i += TW) {
                     const double u2 = A.rowU[i];
                     for (long long j = lane; j < m; j += 64) {
                         const double cij = (double)A.C[i * A.ldc + j];
@@ -1152,7 +1215,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                 double *eyn = exg + EC;        // [EC] |y_j|^2
                 for (long long ja = 0; ja < m; ja += EC) {
                     __syncthreads();
-                    for (long long q = tid; q < EC * d; q += kTT) {
+                    for (long long q = tid; q < EC * d; q += TT) {
                         const long long c = q % EC, k = q / EC, j = std::min(ja + c, m - 1);
                         eyl[q] = (double)A.Y[j * d + k];
                     }
@@ -1162,7 +1225,7 @@ __global__ __launch_bounds__(kTT) void tiled_solve(const TiledArgs A, double *__
                         eyn[tid] = A.ynrm[j];
                     }
                     __syncthreads();
-                    for (long long i0 = r0 + (long long)wid * ER; i0 < r1; i0 += (long long)kTW * ER) {
+                    for (long long i0 = r0 + (long long)wid * ER; i0 < r1; i0 += (long long)TW * ER) {
                         long long ir[ER];
                         double dot[ER];
 #pragma unroll
@@ -1268,12 +1331,13 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     ACCSK_HIP_TRY(hipGetDevice(&dev));
     ACCSK_HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
     const size_t lds = tiled_lds_bytes<D>();
-    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tiled_solve<D, TR, CD>, kTT, lds));
+    ACCSK_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tiled_solve<D, TR, CD>, TBlk<D>::TT, lds));
     if (occ < 1) return ACCSK_SHAPE;
     long long G = (long long)std::min(occ, 2) * cu;
     // matrix-core sweeps: 16-row tiles, one per wave and round, so about 128 rows per
     // block (each staged column chunk then serves 8 tiles)
-    if (D == 3 || D >= 32) G = std::max<long long>(1, std::min<long long>(G, (A.n + 16 * kTW - 1) / (16 * kTW)));
+    if (D == 3 || D >= 32)
+        G = std::max<long long>(1, std::min<long long>(G, (A.n + TBlk<D>::ROWS - 1) / TBlk<D>::ROWS));
     const size_t n = A.n, m = A.m;
     size_t off = 0;
     const size_t o_args = off; off = align_up(off + sizeof(TiledArgs));
@@ -1355,7 +1419,7 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
         double *tr = TR ? p->err_trace : nullptr;
         long long tl = TR ? p->trace_len : 0;
         void *kargs[] = {&A, &tr, &tl};
-        e = hipLaunchCooperativeKernel((const void *)tiled_solve<D, TR, CD>, dim3((unsigned)G), dim3(kTT), kargs, lds, s);
+        e = hipLaunchCooperativeKernel((const void *)tiled_solve<D, TR, CD>, dim3((unsigned)G), dim3(TBlk<D>::TT), kargs, lds, s);
     }
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     if (async) {
