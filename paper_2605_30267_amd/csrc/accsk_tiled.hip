@@ -687,23 +687,31 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
         if constexpr (BF) {
             const bf16x8 *b0 = ylp + (size_t)buf * BU + lane;
             const double *ct = colt + buf * MCH + (lane & 15);
-            // the next tile's B operands are read before this tile's products, so that
-            // their LDS latency overlaps the matrix-core work
-            BOps bo[2];
+            // Software pipeline over the chunk's column tiles: the B operands are read two
+            // tiles ahead, and tile t + 1's products are issued before tile t's FP64
+            // epilogue, so that one wave keeps the matrix cores and the VALU busy together.
+            BOps bo[3];
+            floatx4 cc[RT], cn[RT];
             load_b(S3, b0, bo[0]);
+            if (NTC > 1) load_b(S3, b0 + KC * 3 * 64, bo[1]);
+#pragma unroll
+            for (int r = 0; r < RT; r++) cc[r] = bf_tile(S3, bo[0], ao[r]);
 #pragma unroll
             for (int t = 0; t < NTC; t++) {
-                if (t + 1 < NTC) load_b(S3, b0 + (t + 1) * KC * 3 * 64, bo[(t + 1) & 1]);
-                floatx4 c[RT];
+                if (t + 2 < NTC) load_b(S3, b0 + (t + 2) * KC * 3 * 64, bo[(t + 2) % 3]);
+                if (t + 1 < NTC) {
 #pragma unroll
-                for (int r = 0; r < RT; r++) c[r] = bf_tile(S3, bo[t & 1], ao[r]);
+                    for (int r = 0; r < RT; r++) cn[r] = bf_tile(S3, bo[(t + 1) % 3], ao[r]);
+                }
                 const double x0 = ct[t * 16];
                 double arg[RT][4];
 #pragma unroll
                 for (int r = 0; r < RT; r++)
 #pragma unroll
-                    for (int q = 0; q < 4; q++) arg[r][q] = fma(coef, (double)c[r][q], rt_[r][q] + x0);
+                    for (int q = 0; q < 4; q++) arg[r][q] = fma(coef, (double)cc[r][q], rt_[r][q] + x0);
                 use(t, arg);
+#pragma unroll
+                for (int r = 0; r < RT; r++) cc[r] = cn[r];
             }
         } else {
             const f64x4 cin = {rt_[0][0], rt_[0][1], rt_[0][2], rt_[0][3]};
