@@ -194,8 +194,9 @@ def diff_bench(args, dev):
     t_all, (vals, gx) = timed(fwd_bwd, 2)
     t_fwd, (f, g, res) = timed(lambda: accsk.solve_points(X, Y, a, b, p["eps"], cost_scale=s, split=3), 2)
     t_bwd, _ = timed(lambda: accsk.backward_points(X, Y, a, b, f, g, p["eps"], cost_scale=s), 3)
-    C = torch.empty((n, m), dtype=torch.float32, device=dev)
-    t_cost, _ = timed(lambda: [accsk.cost_points(X[k], Y[k], cost_scale=s, split=3, out=C) for k in range(B)], 3)
+    Cb = torch.empty((B, n, m), dtype=torch.float32, device=dev)  # the forward's 1 GiB of costs, one launch
+    t_cost, _ = timed(lambda: accsk.cost_points(X, Y, cost_scale=s, split=3, out=Cb), 3)
+    del Cb
     its = [r["iters"] for r in res]
     cost_flops = B * n * m * d * 2.0 * 6  # six BF16 products per split-3 cross term
     # backward, per side and entry: d FMA (cost) and d FMA (P times points), 2 flop each

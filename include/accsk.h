@@ -306,6 +306,16 @@ accsk_status accsk_cost_points(const float *X, const float *Y, int64_t n, int64_
                                double cost_scale, int split, float *C, int64_t ldc, void *stream);
 
 /*
+ * accsk_cost_points for a batch of equal-shape problems in one launch: X is
+ * batch x n x d, Y batch x m x d (problems consecutive), and problem k's cost
+ * goes to C + k n ldc (leading dimension ldc >= m).  Same arguments, costs and
+ * limits otherwise; batch >= 1.
+ */
+accsk_status accsk_cost_points_batched(const float *X, const float *Y, int64_t batch, int64_t n, int64_t m,
+                                       int64_t d, int kind, double cost_scale, int split, float *C, int64_t ldc,
+                                       void *stream);
+
+/*
  * Point-cloud solve: builds the cost as accsk_cost_points does (with
  * p->split) into library scratch memory and solves EOT on it.  a, b, f_out,
  * g_out as for accsk_solve_dense.  With ACCSK_FLAG_ON_THE_FLY, or when

@@ -419,6 +419,9 @@ def _register_points(L):
         return
     L.accsk_cost_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, ctypes.c_int, _vp, _i64, _vp]
     L.accsk_cost_points.restype = ctypes.c_int
+    L.accsk_cost_points_batched.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.c_int, _dbl, ctypes.c_int, _vp,
+                                            _i64, _vp]
+    L.accsk_cost_points_batched.restype = ctypes.c_int
     L.accsk_solve_points.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int, _dbl, _vp, _vp,
                                      ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(Result), _vp]
     L.accsk_solve_points.restype = ctypes.c_int
@@ -454,8 +457,27 @@ def _points_lib():
 
 
 def cost_points(X, Y, kind=SQEUCLID, cost_scale=1.0, split=0, out=None):
-    """Cost matrix from point clouds X [n, d], Y [m, d] (float32, device)."""
+    """Cost matrix from point clouds X [n, d], Y [m, d] (float32, device); a batch
+    X [B, n, d], Y [B, m, d] gives [B, n, m] in one call."""
     import torch
+    if X.dim() == 3:
+        _check_dev(X, torch.float32, "X", 3)
+        _check_dev(Y, torch.float32, "Y", 3)
+        X = X.contiguous()
+        Y = Y.contiguous()
+        B, n, d = X.shape
+        m = Y.shape[1]
+        if Y.shape[0] != B or Y.shape[2] != d:
+            raise ValueError("X and Y must have the same batch and feature dimensions")
+        if out is None:
+            out = torch.empty((B, n, m), dtype=torch.float32, device=X.device)
+        if out.shape != (B, n, m) or out.stride(2) != 1 or out.stride(0) != n * out.stride(1):
+            raise ValueError("out must be a contiguous-row [B, n, m] tensor")
+        st = _points_lib().accsk_cost_points_batched(_ptr(X), _ptr(Y), B, n, m, d, int(kind), float(cost_scale),
+                                                     int(split), _ptr(out), out.stride(1), _stream_ptr())
+        if st != OK:
+            raise AccskError(st, "accsk_cost_points_batched")
+        return out
     _check_dev(X, torch.float32, "X", 2)
     _check_dev(Y, torch.float32, "Y", 2)
     X = X.contiguous()

@@ -83,26 +83,72 @@ __global__ __launch_bounds__(256) void cost_fp64(const float *__restrict__ X, co
 }
 
 // ---------------------------------------------------------------------------
-// BF16-split matrix-core cost: block tile 32 x 32, one 16 x 16 tile per wave.
+// BF16-split matrix-core cost from pieces (split_pieces layout), for a batch of
+// equal-shape problems (blockIdx.z).  Block tile 64 x 64: wave w owns the 16-row
+// tile 4 blockIdx.y + w and the block's four 16-column tiles; for each 32-wide K
+// chunk it loads its three A pieces once and applies them to the four column
+// tiles.  The products and their FP64 sums are those of mfma_cross_tile (same
+// pieces, same order), so the costs are the same as that per-lane form gives.
 // ---------------------------------------------------------------------------
 template <int SPLIT, int KIND>
-__global__ __launch_bounds__(256) void cost_mfma(const float *__restrict__ X, const float *__restrict__ Y,
+__global__ __launch_bounds__(256) void cost_mfma(const bf16x8 *__restrict__ Xp, const bf16x8 *__restrict__ Yp,
                                                  const double *__restrict__ nx, const double *__restrict__ ny,
-                                                 long long n, long long m, long long d, double inv_s,
-                                                 float *__restrict__ C, long long ldc) {
+                                                 long long n, long long m, int KC, double inv_s,
+                                                 float *__restrict__ C, long long ldc, long long xu, long long yu,
+                                                 long long cstride) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    // block tile 32 x 32: wave (wid>>1, wid&1) owns the 16x16 sub-tile
-    const long long i0 = (long long)blockIdx.y * 32 + (wid >> 1) * 16;
-    const long long j0 = (long long)blockIdx.x * 32 + (wid & 1) * 16;
-    const int rr = lane & 15;
-    const long long ia = std::min(i0 + rr, n - 1), jb = std::min(j0 + rr, m - 1);
-    double g[4];
-    mfma_cross_tile<SPLIT>(X + ia * d, Y + jb * d, d, lane, g);
+    const long long b = blockIdx.z;
+    Xp += b * xu;
+    Yp += b * yu;
+    nx += b * n;
+    ny += b * m;
+    C += b * cstride;
+    const long long T = (long long)blockIdx.y * 4 + wid;  // row tile (pieces exist for every tile < ceil(n/16))
+    const long long xt = (n + 15) / 16, yt = (m + 15) / 16;
+    if (T >= xt) return;
+    const long long U0 = (long long)blockIdx.x * 4;
+    double g[4][4];
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const long long i = i0 + (lane >> 4) * 4 + q, j = j0 + (lane & 15);
-        if (i < n && j < m) C[i * ldc + j] = finish_mfma<KIND>(g[q], KIND == ACCSK_SQEUCLID ? nx[i] : 0.0,
-                                                                KIND == ACCSK_SQEUCLID ? ny[j] : 0.0, inv_s);
+    for (int c = 0; c < 4; c++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) g[c][q] = 0.0;
+    const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < KC; kc++) {
+        const bf16x8 *ap = Xp + ((T * KC + kc) * 3) * 64 + lane;
+        const bf16x8 ah = ap[0], am = ap[64], al = ap[128];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const long long U = std::min(U0 + c, yt - 1);
+            const bf16x8 *bp = Yp + ((U * KC + kc) * 3) * 64 + lane;
+            const bf16x8 bh = bp[0], bm = bp[64], bl = bp[128];
+            const floatx4 p_hl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, SPLIT == 2 ? bm : bl, z, 0, 0, 0);
+            const floatx4 p_lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(SPLIT == 2 ? am : al, bh, z, 0, 0, 0);
+            floatx4 p_mm = z, p_hm = z, p_mh = z;
+            if (SPLIT == 3) {
+                p_mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, z, 0, 0, 0);
+                p_hm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, z, 0, 0, 0);
+                p_mh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, z, 0, 0, 0);
+            }
+            const floatx4 p_hh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, z, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                double small = (double)p_hl[q] + (double)p_lh[q];
+                if (SPLIT == 3) small += (double)p_mm[q] + ((double)p_hm[q] + (double)p_mh[q]);
+                g[c][q] += small + (double)p_hh[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const long long j = (U0 + c) * 16 + (lane & 15);
+        if (j >= m) continue;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const long long i = T * 16 + (lane >> 4) * 4 + q;
+            if (i < n)
+                C[i * ldc + j] = finish_mfma<KIND>(g[c][q], KIND == ACCSK_SQEUCLID ? nx[i] : 0.0,
+                                                   KIND == ACCSK_SQEUCLID ? ny[j] : 0.0, inv_s);
+        }
     }
 }
 
@@ -405,36 +451,68 @@ __global__ __launch_bounds__(256) void topk_rows(const float *__restrict__ X, co
     }
 }
 
-accsk_status build_cost(const float *X, const float *Y, long long n, long long m, long long d, int kind,
-                        double scale, int split, float *C, long long ldc, double *norms_ws, hipStream_t s) {
+// Costs of `batch` equal-shape problems (X: batch x n x d, Y: batch x m x d, C:
+// problem k at C + k cstride, leading dimension ldc).  split 0: FP64 dot
+// products; split 2/3: BF16 pieces, one launch for the whole batch (pieces and
+// norms in stream-ordered workspace).
+accsk_status build_cost_batch(const float *X, const float *Y, long long batch, long long n, long long m,
+                              long long d, int kind, double scale, int split, float *C, long long ldc,
+                              long long cstride, hipStream_t s) {
     const double inv_s = 1.0 / scale;
     if (split == 0) {
         const size_t lds = 2 * 16 * (size_t)(d + 1) * sizeof(float);
         dim3 grid((unsigned)((m + 15) / 16), (unsigned)((n + 15) / 16));
-        if (kind == ACCSK_SQEUCLID)
-            hipLaunchKernelGGL(cost_fp64<ACCSK_SQEUCLID>, grid, dim3(256), lds, s, X, Y, n, m, d, inv_s, C, ldc);
-        else
-            hipLaunchKernelGGL(cost_fp64<ACCSK_COSINE>, grid, dim3(256), lds, s, X, Y, n, m, d, inv_s, C, ldc);
-    } else {
-        double *nx = norms_ws, *ny = norms_ws + n;
-        if (kind == ACCSK_SQEUCLID) {
-            hipLaunchKernelGGL(row_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d, nx);
-            hipLaunchKernelGGL(row_norms, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, Y, m, d, ny);
-        }
-        dim3 grid((unsigned)((m + 31) / 32), (unsigned)((n + 31) / 32));
-        if (kind == ACCSK_SQEUCLID) {
-            if (split == 2)
-                hipLaunchKernelGGL((cost_mfma<2, ACCSK_SQEUCLID>), grid, dim3(256), 0, s, X, Y, nx, ny, n, m, d, inv_s, C, ldc);
+        for (long long k = 0; k < batch; k++) {
+            const float *Xk = X + k * n * d, *Yk = Y + k * m * d;
+            float *Ck = C + k * cstride;
+            if (kind == ACCSK_SQEUCLID)
+                hipLaunchKernelGGL(cost_fp64<ACCSK_SQEUCLID>, grid, dim3(256), lds, s, Xk, Yk, n, m, d, inv_s, Ck, ldc);
             else
-                hipLaunchKernelGGL((cost_mfma<3, ACCSK_SQEUCLID>), grid, dim3(256), 0, s, X, Y, nx, ny, n, m, d, inv_s, C, ldc);
-        } else {
-            if (split == 2)
-                hipLaunchKernelGGL((cost_mfma<2, ACCSK_COSINE>), grid, dim3(256), 0, s, X, Y, nx, ny, n, m, d, inv_s, C, ldc);
-            else
-                hipLaunchKernelGGL((cost_mfma<3, ACCSK_COSINE>), grid, dim3(256), 0, s, X, Y, nx, ny, n, m, d, inv_s, C, ldc);
+                hipLaunchKernelGGL(cost_fp64<ACCSK_COSINE>, grid, dim3(256), lds, s, Xk, Yk, n, m, d, inv_s, Ck, ldc);
         }
+        return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
     }
-    return hipGetLastError() == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+    const int KC = (int)((d + 31) / 32);
+    const long long xu = (n + 15) / 16 * KC * 3 * 64, yu = (m + 15) / 16 * KC * 3 * 64;  // piece units per problem
+    const size_t pbytes = (size_t)batch * (xu + yu) * sizeof(bf16x8);
+    const size_t nbytes = (size_t)batch * (n + m) * sizeof(double);
+    char *ws = nullptr;
+    if (hipMallocAsync((void **)&ws, pbytes + nbytes, s) != hipSuccess) return ACCSK_OOM;
+    bf16x8 *Xp = (bf16x8 *)ws, *Yp = Xp + batch * xu;
+    double *nx = (double *)(ws + pbytes), *ny = nx + batch * n;
+    const long long ux = (n + 15) / 16 * KC * 64, uy = (m + 15) / 16 * KC * 64;
+    hipLaunchKernelGGL(split_pieces, dim3((unsigned)((ux + 255) / 256), (unsigned)batch), dim3(256), 0, s, X, n, d, KC,
+                       Xp, xu);
+    hipLaunchKernelGGL(split_pieces, dim3((unsigned)((uy + 255) / 256), (unsigned)batch), dim3(256), 0, s, Y, m, d, KC,
+                       Yp, yu);
+    if (kind == ACCSK_SQEUCLID) {  // rows of consecutive problems are consecutive rows
+        hipLaunchKernelGGL(row_norms, dim3((unsigned)((batch * n + 3) / 4)), dim3(256), 0, s, X, batch * n, d, nx);
+        hipLaunchKernelGGL(row_norms, dim3((unsigned)((batch * m + 3) / 4)), dim3(256), 0, s, Y, batch * m, d, ny);
+    }
+    dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64), (unsigned)batch);
+    if (kind == ACCSK_SQEUCLID) {
+        if (split == 2)
+            hipLaunchKernelGGL((cost_mfma<2, ACCSK_SQEUCLID>), grid, dim3(256), 0, s, Xp, Yp, nx, ny, n, m, KC, inv_s, C,
+                               ldc, xu, yu, cstride);
+        else
+            hipLaunchKernelGGL((cost_mfma<3, ACCSK_SQEUCLID>), grid, dim3(256), 0, s, Xp, Yp, nx, ny, n, m, KC, inv_s, C,
+                               ldc, xu, yu, cstride);
+    } else {
+        if (split == 2)
+            hipLaunchKernelGGL((cost_mfma<2, ACCSK_COSINE>), grid, dim3(256), 0, s, Xp, Yp, nx, ny, n, m, KC, inv_s, C,
+                               ldc, xu, yu, cstride);
+        else
+            hipLaunchKernelGGL((cost_mfma<3, ACCSK_COSINE>), grid, dim3(256), 0, s, Xp, Yp, nx, ny, n, m, KC, inv_s, C,
+                               ldc, xu, yu, cstride);
+    }
+    const hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(ws, s);
+    return e == hipSuccess ? ACCSK_OK : ACCSK_HIP_ERROR;
+}
+
+accsk_status build_cost(const float *X, const float *Y, long long n, long long m, long long d, int kind,
+                        double scale, int split, float *C, long long ldc, hipStream_t s) {
+    return build_cost_batch(X, Y, 1, n, m, d, kind, scale, split, C, ldc, 0, s);
 }
 
 accsk_status check_points(const float *X, const float *Y, long long n, long long m, long long d, int kind,
@@ -457,12 +535,17 @@ extern "C" accsk_status accsk_cost_points(const float *X, const float *Y, int64_
     accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, split);
     if (st != ACCSK_OK) return st;
     if (!C || ldc < m) return C ? ACCSK_SHAPE : ACCSK_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    double *ws = nullptr;
-    if (split != 0 && hipMallocAsync((void **)&ws, (size_t)(n + m) * 8, s) != hipSuccess) return ACCSK_OOM;
-    st = build_cost(X, Y, n, m, d, kind, cost_scale, split, C, ldc, ws, s);
-    if (ws) (void)hipFreeAsync(ws, s);
-    return st;
+    return build_cost(X, Y, n, m, d, kind, cost_scale, split, C, ldc, (hipStream_t)stream);
+}
+
+extern "C" accsk_status accsk_cost_points_batched(const float *X, const float *Y, int64_t batch, int64_t n,
+                                                  int64_t m, int64_t d, int kind, double cost_scale, int split,
+                                                  float *C, int64_t ldc, void *stream) {
+    accsk_status st = check_points(X, Y, n, m, d, kind, cost_scale, split);
+    if (st != ACCSK_OK) return st;
+    if (!C || batch < 1) return ACCSK_INVALID_ARG;
+    if (ldc < m || batch > 65535) return ACCSK_SHAPE;
+    return build_cost_batch(X, Y, batch, n, m, d, kind, cost_scale, split, C, ldc, n * ldc, (hipStream_t)stream);
 }
 
 extern "C" accsk_status accsk_plan_points(const float *X, const float *Y, int64_t n, int64_t m, int64_t d, int kind,
@@ -574,15 +657,10 @@ static accsk_status solve_points_tiled(const float *X, const float *Y, int64_t b
                                        const accsk_params *p, double *f_out, double *g_out, accsk_result *res,
                                        accsk_result *dres, hipStream_t s) {
     float *C = nullptr;
-    double *nws = nullptr;
     const long long ldc = (m + 3) / 4 * 4;
     const bool fly = d <= 16 || (d <= 128 && p->split != 0);
     if (!fly) {
-        const size_t cbytes = ((size_t)n * ldc * sizeof(float) + 255) & ~size_t(255);
-        char *ws = nullptr;
-        if (hipMallocAsync((void **)&ws, cbytes + (size_t)(n + m) * 8, s) != hipSuccess) return ACCSK_OOM;
-        C = (float *)ws;
-        nws = (double *)(ws + cbytes);
+        if (hipMallocAsync((void **)&C, (size_t)n * ldc * sizeof(float), s) != hipSuccess) return ACCSK_OOM;
     }
     accsk_status worst = ACCSK_OK;
     for (int64_t k = 0; k < batch; k++) {
@@ -593,7 +671,7 @@ static accsk_status solve_points_tiled(const float *X, const float *Y, int64_t b
             st = accsk_tiled_solve(nullptr, 0, Xk, Yk, d, kind, cost_scale, n, m, a + k * n, b + k * m, p, p->eps,
                                    f_out + k * n, g_out + k * m, rk, s, pk);
         } else {
-            st = build_cost(Xk, Yk, n, m, d, kind, cost_scale, p->split, C, ldc, nws, s);
+            st = build_cost(Xk, Yk, n, m, d, kind, cost_scale, p->split, C, ldc, s);
             if (st == ACCSK_OK)
                 st = accsk_tiled_solve(C, ldc, nullptr, nullptr, 0, kind, 1.0, n, m, a + k * n, b + k * m, p, p->eps,
                                        f_out + k * n, g_out + k * m, rk, s, pk);
@@ -635,12 +713,9 @@ static accsk_status solve_points_batched(const float *X, const float *Y, int64_t
     const long long ldc = (m + 3) / 4 * 4;
     const size_t cbytes = (size_t)batch * n * ldc * sizeof(float);
     char *ws = nullptr;
-    if (hipMallocAsync((void **)&ws, cbytes + (size_t)(n + m) * 8 + 256, s) != hipSuccess) return ACCSK_OOM;
+    if (hipMallocAsync((void **)&ws, cbytes, s) != hipSuccess) return ACCSK_OOM;
     float *C = (float *)ws;
-    double *nws = (double *)(ws + ((cbytes + 255) & ~size_t(255)));
-    for (int64_t k = 0; k < batch && st == ACCSK_OK; k++)
-        st = build_cost(X + k * n * d, Y + k * m * d, n, m, d, kind, cost_scale, p->split, C + k * n * ldc, ldc,
-                        nws, s);
+    st = build_cost_batch(X, Y, batch, n, m, d, kind, cost_scale, p->split, C, ldc, n * ldc, s);
     if (st == ACCSK_OK) {
         std::vector<accsk_problem> probs((size_t)batch);
         for (int64_t k = 0; k < batch; k++)

@@ -1300,35 +1300,6 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Point rows split into BF16 pieces (bf16_split3) in the matrix-core operand
-// layout of the tiled solver: unit ((T KC + kc) 3 + piece) 64 + lane holds
-// features kc 32 + (lane / 16) 8 + [0, 8) of row 16 T + lane % 16, zeros past
-// the rows and features.  One thread per (T, kc, lane).
-__global__ __launch_bounds__(256) void split_pieces(const float *__restrict__ P, long long rows, long long d, int KC,
-                                                    bf16x8 *__restrict__ out) {
-    const long long u = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (u >= (rows + 15) / 16 * KC * 64) return;
-    const int ln = (int)(u % 64);
-    const long long tk = u / 64, T = tk / KC;
-    const int kc = (int)(tk % KC);
-    const long long p = T * 16 + (ln & 15), k0 = (long long)kc * 32 + (ln >> 4) * 8;
-    bf16x8 h, mi, lo;
-#pragma unroll
-    for (int e = 0; e < 8; e++) {
-        const float v = (p < rows && k0 + e < d) ? P[p * d + k0 + e] : 0.f;
-        __bf16 bh, bm, bl;
-        bf16_split3(v, bh, bm, bl);
-        h[e] = bh;
-        mi[e] = bm;
-        lo[e] = bl;
-    }
-    bf16x8 *dst = out + ((T * KC + kc) * 3) * 64 + ln;
-    dst[0] = h;
-    dst[64] = mi;
-    dst[128] = lo;
-}
-
-// Stream-ordered calls: the result record, written to the caller's device memory.
 __global__ __launch_bounds__(64) void publish_tiled(const TiledArgs *__restrict__ pa, double tick_ms) {
     if (threadIdx.x == 0 && pa->pub) publish_record(pa->pub, *pa->res, tick_ms);
 }
@@ -1413,9 +1384,9 @@ accsk_status tiled_launch(TiledArgs &A, const accsk_params *p, accsk_result *res
     if (e == hipSuccess && D >= 32) {
         const long long ux = (long long)(n + 15) / 16 * KC * 64, uy = (long long)(m + 15) / 16 * KC * 64;
         hipLaunchKernelGGL(split_pieces, dim3((unsigned)((ux + 255) / 256)), dim3(256), 0, s, A.X, (long long)n, A.d,
-                           KC, (bf16x8 *)A.Xpk);
+                           KC, (bf16x8 *)A.Xpk, 0ll);
         hipLaunchKernelGGL(split_pieces, dim3((unsigned)((uy + 255) / 256)), dim3(256), 0, s, A.Y, (long long)m, A.d,
-                           KC, (bf16x8 *)A.Ypk);
+                           KC, (bf16x8 *)A.Ypk, 0ll);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {

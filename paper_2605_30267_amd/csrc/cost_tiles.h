@@ -111,6 +111,37 @@ __device__ __forceinline__ void mfma_cross_tile(const float *xrow, const float *
     }
 }
 
+// Point rows split into BF16 pieces (bf16_split3) in the matrix-core operand
+// layout: unit ((T KC + kc) 3 + piece) 64 + lane (16 B) holds features
+// kc 32 + (lane / 16) 8 + [0, 8) of row 16 T + lane % 16, zeros past the rows and
+// features.  One thread per (T, kc, lane); blockIdx.y = problem of a batch
+// (rows x d points each, consecutive; out_stride units between problems).
+__global__ __launch_bounds__(256) void split_pieces(const float *__restrict__ P, long long rows, long long d, int KC,
+                                                    bf16x8 *__restrict__ out, long long out_stride = 0) {
+    const long long u = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (u >= (rows + 15) / 16 * KC * 64) return;
+    P += (long long)blockIdx.y * rows * d;
+    out += (long long)blockIdx.y * out_stride;
+    const int ln = (int)(u % 64);
+    const long long tk = u / 64, T = tk / KC;
+    const int kc = (int)(tk % KC);
+    const long long p = T * 16 + (ln & 15), k0 = (long long)kc * 32 + (ln >> 4) * 8;
+    bf16x8 h, mi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const float v = (p < rows && k0 + e < d) ? P[p * d + k0 + e] : 0.f;
+        __bf16 bh, bm, bl;
+        bf16_split3(v, bh, bm, bl);
+        h[e] = bh;
+        mi[e] = bm;
+        lo[e] = bl;
+    }
+    bf16x8 *dst = out + ((T * KC + kc) * 3) * 64 + ln;
+    dst[0] = h;
+    dst[64] = mi;
+    dst[128] = lo;
+}
+
 template <int KIND>
 __device__ __forceinline__ float finish_mfma(double g, double nx, double ny, double inv_s) {
     const double v = KIND == ACCSK_SQEUCLID ? fmax(nx + ny - 2.0 * g, 0.0) : 1.0 - g;

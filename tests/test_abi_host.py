@@ -223,3 +223,14 @@ def test_host_validation_backward_dense(lib):
     assert f(fake, 4, 5, 4, 0.1, fake, fake, fake, fake, None, fake, 5, None, None, None) == accsk.SHAPE
     assert f(fake, 4, 5, 5, 0.1, fake, fake, fake, fake, None, fake, 4, None, None, None) == accsk.SHAPE
     assert f(fake, 0, 5, 5, 0.1, fake, fake, fake, fake, None, fake, 5, None, None, None) == accsk.SHAPE
+
+
+def test_host_validation_cost_points_batched(lib):
+    fake = ctypes.c_void_p(4096)  # never dereferenced
+    f = accsk._points_lib().accsk_cost_points_batched
+    # (X, Y, batch, n, m, d, kind, cost_scale, split, C, ldc, stream)
+    assert f(fake, fake, 0, 4, 5, 3, 0, 1.0, 3, fake, 5, None) == accsk.INVALID_ARG
+    assert f(fake, fake, 2, 4, 5, 3, 0, 1.0, 3, None, 5, None) == accsk.INVALID_ARG
+    assert f(fake, fake, 2, 4, 5, 3, 0, 1.0, 3, fake, 4, None) == accsk.SHAPE
+    assert f(fake, fake, 2, 4, 5, 513, 0, 1.0, 3, fake, 5, None) == accsk.SHAPE
+    assert f(fake, fake, 2, 4, 5, 3, 0, 1.0, 1, fake, 5, None) == accsk.INVALID_ARG

@@ -330,3 +330,32 @@ def test_topk_points(torch_gpu, k, kind, n, m, d):
         np.testing.assert_allclose(val[i, :kk], np.exp((o["f"][i] + score[i, got]) / eps), rtol=1e-12)
         if kk < k:
             assert np.all(idx[i, kk:] == -1)
+
+
+@pytest.mark.parametrize("kind,split,B,n,m,d", [(0, 3, 5, 37, 70, 45), (1, 2, 3, 130, 17, 300), (0, 2, 2, 64, 64, 64),
+                                                (1, 3, 4, 1, 5, 1)])
+def test_cost_points_batched_equals_single(torch_gpu, kind, split, B, n, m, d):
+    """One launch for a batch of problems gives each problem's cost bit for bit as its own call
+    (same pieces, products and sums); ragged n, m (not multiples of 16 or 64) and d (not of 32)."""
+    torch = torch_gpu
+    from paper_2605_30267_amd import accsk
+    rng = np.random.default_rng(B * 100 + n)
+    X = rng.standard_normal((B, n, d)).astype(np.float32)
+    Y = rng.standard_normal((B, m, d)).astype(np.float32)
+    if kind == 1:
+        X /= np.linalg.norm(X, axis=2, keepdims=True)
+        Y /= np.linalg.norm(Y, axis=2, keepdims=True)
+    s = 2.0 * d if kind == 0 else 1.0
+    print("case batched cost", kind, split, B, n, m, d, flush=True)
+    Cb = accsk.cost_points(_dev(torch, X, torch.float32), _dev(torch, Y, torch.float32), kind=kind, cost_scale=s,
+                           split=split)
+    for k in range(B):
+        Ck = accsk.cost_points(_dev(torch, X[k], torch.float32), _dev(torch, Y[k], torch.float32), kind=kind,
+                               cost_scale=s, split=split)
+        assert torch.equal(Cb[k], Ck), k
+    # and the split bound against the exact FP64 cost (as for single problems)
+    Cx = O.cost_points(kind, X[0], Y[0], s)
+    B0 = (np.sum(X[0].astype(np.float64) ** 2, 1)[:, None] + np.sum(Y[0].astype(np.float64) ** 2, 1)[None, :]) / s \
+        if kind == 0 else np.outer(np.linalg.norm(X[0], axis=1), np.linalg.norm(Y[0], axis=1)) / s
+    rel = 2.0 ** -20 if split == 3 else 2.0 ** -14
+    assert np.all(np.abs(Cb[0].cpu().numpy().astype(np.float64) - Cx) <= rel * B0 + 2.0 ** -24 * np.abs(Cx) + 1e-30)
