@@ -254,6 +254,122 @@ __global__ __launch_bounds__(256) void grad_side(const float *__restrict__ X, co
     }
 }
 
+// Backward of one side on the FP64 matrix cores (d <= 4 KK), gradient of the EOT
+// value only.  A block owns 16 rows of X of one problem (blockIdx.y); its four
+// waves take the 16-column tiles of Y in turn.  Per tile, v_mfma_f64_16x16x4f64
+// forms C^T = Y X^T (A: Y rows, B: the block's X rows held in registers; lane
+// group g supplies features g KK + kk at step kk), so that lane l holds
+// P_ij for i = l % 16 and j = l / 16 + 4 q: exactly the A operand of the next
+// product P Y at K step q (j = 4 q + l / 16).  P Y accumulates in FP64 registers
+// per 16-feature tile; the waves' sums and row sums r_i are added in wave order
+// through LDS.  Same quantities as grad_side (FP64 cost, FP32 exponential of the
+// FP64 argument, FP64 sums), in a different order of FP64 additions.
+template <int KIND, int KK>
+__global__ __launch_bounds__(256) void grad_mfma(const float *__restrict__ X, const float *__restrict__ Y,
+                                                 long long n, long long m, long long d, double inv_s,
+                                                 double inv_eps, const double *__restrict__ f,
+                                                 const double *__restrict__ g, const double *__restrict__ gsc,
+                                                 float *__restrict__ dX, long long sX, long long sY,
+                                                 long long sf, long long sg) {
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    constexpr int NFT = KK / 4;  // 16-feature tiles of the output (4 KK features)
+    extern __shared__ double gm_red[];  // [4 waves][NFT][4][64] partial P Y, then [4][16] row sums
+    const long long bidx = blockIdx.y;
+    const double gscale = gsc ? gsc[bidx] : 1.0;
+    X += bidx * sX;
+    Y += bidx * sY;
+    f += bidx * sf;
+    g += bidx * sg;
+    dX += bidx * sX;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int g4 = lane >> 4, r16 = lane & 15;
+    const long long i0 = (long long)blockIdx.x * 16;
+    const long long ib = i0 + r16;  // this lane's X row as a B operand and its P row
+    const double k2 = inv_eps * kLog2e;
+    double xb[KK];
+    double xn = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KK; kk++) {
+        const long long k = (long long)g4 * KK + kk;
+        xb[kk] = (ib < n && k < d) ? (double)X[ib * d + k] : 0.0;
+        xn = fma(xb[kk], xb[kk], xn);
+    }
+    xn += __shfl_xor(xn, 16, 64);
+    xn += __shfl_xor(xn, 32, 64);  // |x_ib|^2
+    const double fi2 = ib < n ? f[ib] * k2 : 0.0;
+    f64x4 acc[NFT];
+#pragma unroll
+    for (int t = 0; t < NFT; t++) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    double rsum = 0.0;
+    const long long ytiles = (m + 15) / 16;
+    for (long long U = wid; U < ytiles; U += 4) {
+        const long long j0 = U * 16;
+        const long long ja = j0 + r16;  // this lane's Y row as an A operand
+        double ya[KK];
+        double yn = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < KK; kk++) {
+            const long long k = (long long)g4 * KK + kk;
+            ya[kk] = (ja < m && k < d) ? (double)Y[ja * d + k] : 0.0;
+            yn = fma(ya[kk], ya[kk], yn);
+        }
+        yn += __shfl_xor(yn, 16, 64);
+        yn += __shfl_xor(yn, 32, 64);  // |y_ja|^2 in every lane of row ja
+        f64x4 cd = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KK; kk++) cd = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[kk], xb[kk], cd, 0, 0, 0);
+        double pv[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int jr = g4 + 4 * q;  // row of the tile this value belongs to
+            const long long j = j0 + jr;
+            const double ynj = __shfl(yn, jr, 64);
+            double cij = KIND == ACCSK_SQEUCLID ? xn + ynj - 2.0 * cd[q] : 1.0 - cd[q];
+            cij *= inv_s;
+            const double gj2 = g[std::min(j, m - 1)] * k2;
+            pv[q] = (ib < n && j < m) ? (double)exp2_split(fma(-cij, k2, fi2 + gj2)) : 0.0;
+            rsum += pv[q];
+        }
+#pragma unroll
+        for (int t = 0; t < NFT; t++) {
+            const long long ft = (long long)t * 16 + r16;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const long long j = j0 + 4 * q + g4;
+                const double yv = (j < m && ft < d) ? (double)Y[j * d + ft] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[q], yv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // the waves' partial sums, added in wave order
+    rsum += __shfl_xor(rsum, 16, 64);
+    rsum += __shfl_xor(rsum, 32, 64);  // row ib over this wave's columns
+    double *rr = gm_red + 4 * NFT * 4 * 64;  // [4][16]
+#pragma unroll
+    for (int t = 0; t < NFT; t++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) gm_red[((wid * NFT + t) * 4 + q) * 64 + lane] = acc[t][q];
+    if (lane < 16) rr[wid * 16 + lane] = rsum;
+    __syncthreads();
+    for (int t = wid; t < NFT; t += 4) {
+        const long long ft = (long long)t * 16 + r16;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int ir = g4 + 4 * q;  // row of the output tile in this lane and register
+            const long long i = i0 + ir;
+            double v = 0.0, ri = 0.0;
+            for (int w = 0; w < 4; w++) {
+                v += gm_red[((w * NFT + t) * 4 + q) * 64 + lane];
+                ri += rr[w * 16 + ir];
+            }
+            if (i < n && ft < d) {
+                const double o = KIND == ACCSK_SQEUCLID ? 2.0 * inv_s * (ri * (double)X[i * d + ft] - v) : -inv_s * v;
+                dX[i * d + ft] = (float)(gscale * o);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void grad_marginal(const double *__restrict__ pot, const double *__restrict__ w,
                                                      long long len, long long sp, long long sw,
                                                      const double *__restrict__ gsc, double *__restrict__ out) {
@@ -783,8 +899,23 @@ extern "C" accsk_status accsk_backward_points(const float *X, const float *Y, in
         hipLaunchKernelGGL(kern, gy, dim3(256), lds, s, Y, X, m, n, d, inv_s, inv_eps, g, f, grad_scale, dY, m * d,
                            n * d, m, n);
     };
-    // features per thread: d <= 16 NQ
-    if (kind == ACCSK_SQEUCLID) {
+    // d <= 128: the FP64 matrix-core form (one block per 16 rows of a problem)
+    if (d <= 128) {
+        auto msides = [&](auto kern, size_t glds) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)((n + 15) / 16), (unsigned)batch), dim3(256), glds, s, X, Y, n, m,
+                               d, inv_s, inv_eps, f, g, grad_scale, dX, n * d, m * d, n, m);
+            hipLaunchKernelGGL(kern, dim3((unsigned)((m + 15) / 16), (unsigned)batch), dim3(256), glds, s, Y, X, m, n,
+                               d, inv_s, inv_eps, g, f, grad_scale, dY, m * d, n * d, m, n);
+        };
+        const size_t l16 = (4 * 4 * 4 * 64 + 64) * sizeof(double), l32 = (4 * 8 * 4 * 64 + 64) * sizeof(double);
+        if (kind == ACCSK_SQEUCLID) {
+            if (d <= 64) msides(grad_mfma<ACCSK_SQEUCLID, 16>, l16);
+            else msides(grad_mfma<ACCSK_SQEUCLID, 32>, l32);
+        } else {
+            if (d <= 64) msides(grad_mfma<ACCSK_COSINE, 16>, l16);
+            else msides(grad_mfma<ACCSK_COSINE, 32>, l32);
+        }
+    } else if (kind == ACCSK_SQEUCLID) {
         if (d <= 64) sides(grad_side<ACCSK_SQEUCLID, 4>);
         else if (d <= 128) sides(grad_side<ACCSK_SQEUCLID, 8>);
         else if (d <= 256) sides(grad_side<ACCSK_SQEUCLID, 16>);
