@@ -302,22 +302,37 @@ __global__ __launch_bounds__(256) void grad_mfma(const float *__restrict__ X, co
     for (int t = 0; t < NFT; t++) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
     double rsum = 0.0;
     const long long ytiles = (m + 15) / 16;
-    for (long long U = wid; U < ytiles; U += 4) {
-        const long long j0 = U * 16;
-        const long long ja = j0 + r16;  // this lane's Y row as an A operand
-        double ya[KK];
-        double yn = 0.0;
+    // this lane's Y values of a tile (FP32 as stored): its A-operand row and its P Y operands;
+    // the next tile's are loaded while the current one is computed
+    float yaf[KK], yvf[NFT][4];
+    auto load_tile = [&](long long U, float (&ya_)[KK], float (&yv_)[NFT][4]) {
+        const long long j0 = U * 16, ja = j0 + r16;
 #pragma unroll
         for (int kk = 0; kk < KK; kk++) {
             const long long k = (long long)g4 * KK + kk;
-            ya[kk] = (ja < m && k < d) ? (double)Y[ja * d + k] : 0.0;
-            yn = fma(ya[kk], ya[kk], yn);
+            ya_[kk] = (ja < m && k < d) ? Y[ja * d + k] : 0.f;
         }
+#pragma unroll
+        for (int t = 0; t < NFT; t++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const long long j = j0 + 4 * q + g4, ft = (long long)t * 16 + r16;
+                yv_[t][q] = (j < m && ft < d) ? Y[j * d + ft] : 0.f;
+            }
+    };
+    if (wid < ytiles) load_tile(wid, yaf, yvf);
+    for (long long U = wid; U < ytiles; U += 4) {
+        const long long j0 = U * 16;
+        float nyaf[KK], nyvf[NFT][4];
+        if (U + 4 < ytiles) load_tile(U + 4, nyaf, nyvf);
+        double yn = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < KK; kk++) yn = fma((double)yaf[kk], (double)yaf[kk], yn);
         yn += __shfl_xor(yn, 16, 64);
         yn += __shfl_xor(yn, 32, 64);  // |y_ja|^2 in every lane of row ja
         f64x4 cd = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kk = 0; kk < KK; kk++) cd = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[kk], xb[kk], cd, 0, 0, 0);
+        for (int kk = 0; kk < KK; kk++) cd = __builtin_amdgcn_mfma_f64_16x16x4f64((double)yaf[kk], xb[kk], cd, 0, 0, 0);
         double pv[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
@@ -331,14 +346,17 @@ __global__ __launch_bounds__(256) void grad_mfma(const float *__restrict__ X, co
             rsum += pv[q];
         }
 #pragma unroll
-        for (int t = 0; t < NFT; t++) {
-            const long long ft = (long long)t * 16 + r16;
+        for (int t = 0; t < NFT; t++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const long long j = j0 + 4 * q + g4;
-                const double yv = (j < m && ft < d) ? (double)Y[j * d + ft] : 0.0;
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[q], yv, acc[t], 0, 0, 0);
-            }
+            for (int q = 0; q < 4; q++)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[q], (double)yvf[t][q], acc[t], 0, 0, 0);
+        if (U + 4 < ytiles) {
+#pragma unroll
+            for (int kk = 0; kk < KK; kk++) yaf[kk] = nyaf[kk];
+#pragma unroll
+            for (int t = 0; t < NFT; t++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) yvf[t][q] = nyvf[t][q];
         }
     }
     // the waves' partial sums, added in wave order
