@@ -101,7 +101,10 @@ def traffic_from_profile():
 # FP32 exponentials the on-the-fly (tiled) solver evaluates per cost entry and
 # Sinkhorn step: one in the row sweep, one in the column sweep.
 TILED_EXPS_PER_ENTRY = 2
-EXP_PEAK = 256 * 64 / 4 * 2.4e9  # v_exp_f32 at quarter rate: 9.8e12 exponentials/s
+# v_exp_f32 ceiling from the unit counts and the clock: 256 CUs x 4 SIMDs x 64 lanes,
+# one exponential instruction per 8 cycles per wave (CDNA4 doubled the transcendental
+# rate of CDNA3's 16), 2.4 GHz: 1.97e13 exponentials/s
+EXP_PEAK = 256 * 4 * 64 / 8 * 2.4e9
 
 
 def color_bench(args, dev):
@@ -144,9 +147,15 @@ def color_bench(args, dev):
                roofline={"bound": "alu", "achieved": achieved, "peak": EXP_PEAK, "unit": "entries/s",
                          "frac": achieved / EXP_PEAK,
                          "note": "one FP32 exponential per cost entry and Sinkhorn step (the minimum), against "
-                                 "the v_exp_f32 ceiling 256 CU x 64 lanes / 4 x 2.4 GHz",
+                                 "the v_exp_f32 ceiling 256 CU x 4 SIMD x 64 lanes / 8 cycles x 2.4 GHz",
                          "exp_rate": achieved * TILED_EXPS_PER_ENTRY,
                          "exp_frac": achieved * TILED_EXPS_PER_ENTRY / EXP_PEAK})
+    # The same ceiling measured on this device (independent exponential chains
+    # with nothing else in the loop), the exponential counterpart of the
+    # measured read stream.
+    exp_meas = accsk.exp_rate(reps=5)
+    out["roofline"]["measured_exp_rate"] = exp_meas
+    out["roofline"]["frac_of_measured"] = achieved / exp_meas
     log("colour transfer: It %d, %.1f ms/solve, %.1f us/step, frac of the exp ceiling %.3f"
         % (r["iters"], 1e3 * dt, out["us_per_step"], out["roofline"]["frac"]))
     return out, dict(X=X, Y=Y, a=a, b=b, scale=s, eps=p["eps"], res=r, f=rs_f[0], g=rs_f[1])

@@ -169,6 +169,15 @@ accsk_status accsk_workspace_bytes(int64_t n, int64_t m, int64_t count, size_t *
  */
 accsk_status accsk_read_bandwidth(const void *buf, int64_t bytes, int32_t reps, double *gbps, void *stream);
 
+/*
+ * Measured ceiling of the FP32 exponential (v_exp_f32), the reference for the
+ * exponential-bound solvers: 8 independent chains a <- 2^(-a) per thread, 8
+ * waves per SIMD on every CU, timed with HIP events over `reps` launches after
+ * one warm-up; *per_s receives the best rate in exponentials per second.  Not
+ * part of the solve.  Errors: INVALID_ARG, OOM, HIP_ERROR.
+ */
+accsk_status accsk_exp_rate(int32_t reps, double *per_s, void *stream);
+
 /* Library version string (static storage). */
 const char *accsk_version(void);
 

@@ -109,6 +109,8 @@ def lib():
         L.accsk_workspace_bytes.restype = ctypes.c_int
         L.accsk_read_bandwidth.argtypes = [_vp, _i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _vp]
         L.accsk_read_bandwidth.restype = ctypes.c_int
+        L.accsk_exp_rate.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _vp]
+        L.accsk_exp_rate.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -264,6 +266,15 @@ def read_bandwidth(buf, reps=10):
                                     _stream_ptr())
     if st != OK:
         raise AccskError(st, "accsk_read_bandwidth")
+    return out.value
+
+
+def exp_rate(reps=5):
+    """Measured FP32 exponential (v_exp_f32) throughput of the device, in exponentials per second."""
+    out = ctypes.c_double(0.0)
+    st = lib().accsk_exp_rate(int(reps), ctypes.byref(out), _stream_ptr())
+    if st != OK:
+        raise AccskError(st, "accsk_exp_rate")
     return out.value
 
 

@@ -81,6 +81,23 @@ double time_read_stream(const float4 *p, long long n4, float *out, unsigned grid
         return 0.0;
     return (double)(n4 * 16) * reps / (ms * 1e-3) / 1e9;
 }
+// Exponential throughput reference: NC independent chains a <- 2^(-a) per thread
+// (one v_exp_f32 per step, the negation an input modifier); the chains stay in
+// (0, 1] and one value per block is written so that none is dropped.
+template <int NC>
+__global__ __launch_bounds__(256) void exp_chain(int iters, float *out) {
+    float a[NC];
+#pragma unroll
+    for (int k = 0; k < NC; k++) a[k] = 0.25f + 0.01f * (float)((threadIdx.x + k) % 7);
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int k = 0; k < NC; k++) a[k] = __builtin_amdgcn_exp2f(-a[k]);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < NC; k++) s += a[k];
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
 }  // namespace
 
 extern "C" accsk_status accsk_read_bandwidth(const void *buf, int64_t bytes, int32_t reps, double *gbps,
@@ -111,5 +128,38 @@ extern "C" accsk_status accsk_read_bandwidth(const void *buf, int64_t bytes, int
     (void)hipFreeAsync(out, s);
     if (!ok) return ACCSK_HIP_ERROR;
     *gbps = best;
+    return ACCSK_OK;
+}
+
+extern "C" accsk_status accsk_exp_rate(int32_t reps, double *per_s, void *stream) {
+    if (!per_s || reps < 1) return ACCSK_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cu = 0;
+    ACCSK_HIP_TRY(hipGetDevice(&dev));
+    ACCSK_HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+    constexpr int NC = 8, ITERS = 4096;
+    const unsigned grid = (unsigned)(8 * cu);  // 8 blocks of 4 waves per CU: 8 waves per SIMD
+    float *out = nullptr;
+    if (hipMallocAsync((void **)&out, (size_t)grid * sizeof(float), s) != hipSuccess) return ACCSK_OOM;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    double best = 0.0;
+    hipLaunchKernelGGL(exp_chain<NC>, dim3(grid), dim3(256), 0, s, ITERS, out);  // warm-up
+    for (int r = 0; ok && r < reps; r++) {
+        float ms = 0.f;
+        ok = hipEventRecord(e0, s) == hipSuccess;
+        hipLaunchKernelGGL(exp_chain<NC>, dim3(grid), dim3(256), 0, s, ITERS, out);
+        ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.f;
+        if (ok) {
+            const double rate = (double)grid * 256.0 * ITERS * NC / (ms * 1e-3);
+            if (rate > best) best = rate;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFreeAsync(out, s);
+    if (!ok) return ACCSK_HIP_ERROR;
+    *per_s = best;
     return ACCSK_OK;
 }

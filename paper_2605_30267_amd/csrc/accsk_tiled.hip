@@ -233,6 +233,30 @@ __device__ __forceinline__ double row16_max(double v) {
     return v;
 }
 
+// gfx950 cross-lane exchanges (a row is 16 lanes): v_permlane32_swap_b32 swaps the
+// upper 32 lanes of a with the lower 32 lanes of b, v_permlane16_swap_b32 the odd rows
+// of a with the even rows of b.  Written as instructions (the compiler's builtins
+// return the first register only); a VALU result needs two wait states before either
+// reads it.
+__device__ __forceinline__ void swap_lanes32(float &a, float &b) {
+    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void swap_rows16(float &a, float &b) {
+    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+// Column sums of four 16 x 16 tiles with no LDS traffic: in lane l, p<g> is tile g's
+// partial sum of column l % 16 over the rows that lane group l / 16 holds.  Returns, in
+// lane l, the whole column l % 16 of tile {0, 2, 1, 3}[l / 16], added as
+// (groups 0 + 2) + (groups 1 + 3).
+__device__ __forceinline__ float col_sums4(float p0, float p1, float p2, float p3) {
+    swap_lanes32(p0, p1);  // p0 = [p0 lanes 0-31, p1 lanes 0-31], p1 = [p0 lanes 32-63, p1 lanes 32-63]
+    swap_lanes32(p2, p3);
+    float x = p0 + p1, y = p2 + p3;  // rows: tile 0 (groups 0+2, 1+3), tile 1 (0+2, 1+3); y: tiles 2, 3
+    swap_rows16(x, y);               // x = rows 0 of x, y, rows 2 of x, y; y = the rows 1 and 3
+    return x + y;
+}
+__device__ __forceinline__ int col_sums4_tile(int lane) { return ((lane >> 4) & 1) * 2 + (lane >> 5); }
+
 __device__ __forceinline__ double readlane63_f64(double v) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)b, 63);
@@ -539,6 +563,7 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
     constexpr int KC = BF ? D / 32 : 1;                   // 32-wide K chunks (BF16 engine)
     constexpr int MCH = BF ? (D == 128 ? 64 : 128) : 512;  // columns per chunk
     constexpr int NTC = MCH / 16;                         // column tiles per chunk
+    static_assert(NTC % 4 == 0, "the column sums reduce four tiles at a time");
     constexpr int BU = BF ? NTC * KC * 3 * 64 : NTC * 64; // B units per buffer (16 B BF16 pieces, 8 B FP64)
     constexpr int PF = BF ? BU / TT : 1;                  // direct loads per thread and chunk
     constexpr int RT = BF ? 2 : 1;                        // 16-row tiles per wave and round
@@ -864,13 +889,15 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
     // fixed order.  Several rounds accumulate in part (FP64) before partf is written.
     auto mcol_sweep = [&](bool exact) {
         if constexpr (MF) {
-            for (int sweep = exact ? 0 : 1; sweep < 2; sweep++) {
-                const bool mxs = sweep == 0;  // maximum pass of the exact sweep
+            // one pass over the block's rows; MXS (compile time): the maximum pass of the
+            // exact sweep, else a sum pass
+            auto col_pass = [&](auto MXS) {
+                constexpr bool mxs = decltype(MXS)::value;
                 auto shift_src = [&](long long j) {
                     return exact ? (mxs ? 0.0 : A.partmax[(size_t)bid * m + j]) : A.colL[j];
                 };
                 if (nround == 0) {  // a block without rows: its partials are the identity
-                        for (long long j = tid; j < m; j += TT) {
+                    for (long long j = tid; j < m; j += TT) {
                         const size_t o = (size_t)bid * m + j;
                         if (mxs) A.partmax[o] = -INFINITY;
                         else if (exact) A.part[o] = 0.0;
@@ -897,10 +924,11 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
                     with_split([&](auto S3) {
                         for_chunks(shift_src, [&](long long ja, int buf) {
                             if (wact) {
+                                float p4[4];          // the current group of four tiles' partial sums
+                                float cs[NTC / 4];    // the chunk's column sums, stored after its last tile
                                 for_tiles(S3, buf, ao, rh, [&](int t, const double (&arg)[RT][4]) {
-                                    double v;
-                                    if (mxs) {
-                                        v = -INFINITY;
+                                    if constexpr (mxs) {
+                                        double v = -INFINITY;
 #pragma unroll
                                         for (int r = 0; r < RT; r++)
 #pragma unroll
@@ -910,18 +938,24 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
                                         v = (u > v || u != u) ? u : v;
                                         u = __shfl_xor(v, 32, 64);
                                         v = (u > v || u != u) ? u : v;
+                                        if (lane < 16) mcp[wid * MCH + t * 16 + lane] = v;
                                     } else {
-                                        float p = 0.f;
+                                        float p = __builtin_amdgcn_exp2f((float)arg[0][0]);
 #pragma unroll
                                         for (int r = 0; r < RT; r++)
 #pragma unroll
-                                            for (int q = 0; q < 4; q++) p += __builtin_amdgcn_exp2f((float)arg[r][q]);
-                                        p += __shfl_xor(p, 16, 64);  // the tiles' rows: across the lane groups
-                                        p += __shfl_xor(p, 32, 64);
-                                        v = (double)p;
+                                            for (int q = 0; q < 4; q++)
+                                                if (r + q > 0) p += __builtin_amdgcn_exp2f((float)arg[r][q]);
+                                        p4[t & 3] = p;
+                                        // tiles t - 3 .. t: across the lane groups at once
+                                        if ((t & 3) == 3) cs[t >> 2] = col_sums4(p4[0], p4[1], p4[2], p4[3]);
                                     }
-                                    if (lane < 16) mcp[wid * MCH + t * 16 + lane] = v;
                                 });
+                                if constexpr (!mxs) {
+#pragma unroll
+                                    for (int k = 0; k < NTC / 4; k++)
+                                        mcp[wid * MCH + (4 * k + col_sums4_tile(lane)) * 16 + (lane & 15)] = (double)cs[k];
+                                }
                             } else {
                                 for (int c = lane; c < MCH; c += 64) mcp[wid * MCH + c] = mxs ? -INFINITY : 0.0;
                             }
@@ -952,7 +986,9 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
                     });
                 }
                 __syncthreads();
-            }
+            };
+            if (exact) col_pass(std::integral_constant<bool, true>{});
+            col_pass(std::integral_constant<bool, false>{});
         }
     };
 

@@ -174,6 +174,12 @@ def test_host_validation_read_bandwidth(lib):
     assert f(4096, 1 << 20, 1, None, None) == accsk.INVALID_ARG
 
 
+def test_host_validation_exp_rate(lib):
+    out = ctypes.c_double(0.0)
+    assert lib.accsk_exp_rate(0, ctypes.byref(out), None) == accsk.INVALID_ARG
+    assert lib.accsk_exp_rate(1, None, None) == accsk.INVALID_ARG
+
+
 def test_host_validation_noalloc(lib):
     """The allocation-free dense solve validates on the host before touching the device."""
     f = lib.accsk_solve_dense_noalloc
