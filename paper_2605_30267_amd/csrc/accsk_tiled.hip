@@ -64,6 +64,7 @@ struct TBlk {
     static constexpr int TW = TT / 64;
     static constexpr int ROWS = 16 * TW * (D >= 32 ? 2 : 1);  // rows per block and round (matrix-core sweeps)
 };
+constexpr int kF64CH = 1024;      // columns per staged chunk, FP64 matrix-core sweeps (d <= 3)
 constexpr int kTNS = 8;           // block scalar slots: 0 <u,a>, 1 sum S^, 2 err, 3 mass, 4 <x,b>, 5 fallback
 constexpr int kTRB = 256;         // rows staged per row group of the column sweep
 
@@ -81,9 +82,10 @@ size_t tiled_lds_bytes() {
     if (D >= 32) {  // two buffers of Y pieces [tiles][D/32 chunks][3 pieces][64 lanes] x 16 B, column terms, wave sums
         const size_t mch = D == 128 ? 64 : 128;
         return 2 * (mch / 16) * (D / 32) * 3 * 64 * 16 + 2 * mch * sizeof(double) +
-               (size_t)TBlk<D>::TW * mch * sizeof(double);
+               2 * (size_t)TBlk<D>::TW * mch * sizeof(float);
     }
-    if (D == 3) return 2 * (size_t)(512 / 16) * 64 * sizeof(double) + (size_t)kTW * 512 * sizeof(double);
+    if (D == 3)  // two buffers of [tiles][64] FP64 B operands, two of the waves' column values
+        return 2 * (size_t)(kF64CH / 16) * 64 * sizeof(double) + 2 * (size_t)TBlk<D>::TW * kF64CH * sizeof(float);
     using Cf = TCfg<D>;
     const size_t cols = (size_t)Cf::CH * (Cf::DD + 1) * sizeof(double);
     const size_t rows = (size_t)kTRB * (Cf::DD + 1) * sizeof(double);
@@ -561,19 +563,21 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
     // The column term carries the sweep's column shift: xh_j - s_j, -inf past m.
     constexpr bool BF = D >= 32;
     constexpr int KC = BF ? D / 32 : 1;                   // 32-wide K chunks (BF16 engine)
-    constexpr int MCH = BF ? (D == 128 ? 64 : 128) : 512;  // columns per chunk
+    constexpr int MCH = BF ? (D == 128 ? 64 : 128) : kF64CH;  // columns per chunk
     constexpr int NTC = MCH / 16;                         // column tiles per chunk
     static_assert(NTC % 4 == 0, "the column sums reduce four tiles at a time");
     constexpr int BU = BF ? NTC * KC * 3 * 64 : NTC * 64; // B units per buffer (16 B BF16 pieces, 8 B FP64)
     constexpr int PF = BF ? BU / TT : 1;                  // direct loads per thread and chunk
     constexpr int RT = BF ? 2 : 1;                        // 16-row tiles per wave and round
     static_assert(!MF || !BF || BU % TT == 0, "chunk units per thread");
-    static_assert(!MF || MCH <= TT, "one column per thread");
+    constexpr int CPT = (MCH + TT - 1) / TT;              // staged columns per thread
     typedef double f64x4 __attribute__((ext_vector_type(4)));
     bf16x8 *ylp = reinterpret_cast<bf16x8 *>(tl);                       // BF16: [2][BU]
     double *yl64 = tl;                                                  // FP64: [2][NTC][64]
     double *colt = BF ? reinterpret_cast<double *>(ylp + 2 * BU) : tl + 2 * BU;  // BF16: [2][MCH] column terms
-    double *mcp = BF ? colt + 2 * MCH : tl + 2 * BU;                    // [TW][MCH] per-wave column values
+    // [2][TW][MCH] per-wave column values (sums are FP32 already), two buffers so that a
+    // chunk's cross-wave combine can wait until the next chunk's barrier
+    float *mcp = reinterpret_cast<float *>(BF ? colt + 2 * MCH : tl + 2 * BU);
     const int split = A.split;
     const int ntile = (int)((nr + 15) / 16);  // the block's 16-row tiles (r0 is a multiple of 16)
     const int nround = (ntile + TW * RT - 1) / (TW * RT);
@@ -584,10 +588,10 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
     auto trow = [&](int q) -> int { return BF ? 4 * (lane >> 4) + q : (lane >> 4) + 4 * q; };
 
     // Column data of the next chunk, in registers until it is committed to LDS
-    // (one column per thread; index clamped, columns past m get the term -inf).
-    double pxg = 0.0, pyn = 0.0, psh = 0.0;
-    float py[3] = {0.f, 0.f, 0.f};
-    bool pvalid = false;
+    // (columns tid + c TT; index clamped, columns past m get the term -inf).
+    double pxg[CPT], pyn[CPT], psh[CPT];
+    float py[CPT][3];
+    bool pvalid[CPT];
     auto fetch = [&](long long ja, int buf, auto col_shift) {
         if constexpr (BF) {
             // this thread's share of the chunk's pieces, straight into LDS buffer buf
@@ -603,27 +607,33 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
                     (__attribute__((address_space(3))) void *)(ylp + (size_t)buf * BU + u * TT + wid * 64), 16, 0, 0);
             }
         }
-        if (tid < MCH) {
-            const long long jj = std::min(ja + tid, m - 1);
-            pvalid = ja + tid < m;
-            pxg = A.xg[jj];
-            pyn = sq ? A.ynrm[jj] : 0.0;
-            psh = col_shift(jj);
+#pragma unroll
+        for (int c = 0; c < CPT; c++) {
+            const int col = tid + c * TT;
+            if (col >= MCH) continue;
+            const long long jj = std::min(ja + col, m - 1);
+            pvalid[c] = ja + col < m;
+            pxg[c] = A.xg[jj];
+            pyn[c] = sq ? A.ynrm[jj] : 0.0;
+            psh[c] = col_shift(jj);
             if constexpr (!BF) {
 #pragma unroll
-                for (int k = 0; k < 3; k++) py[k] = k < d ? A.Y[jj * d + k] : 0.f;
+                for (int k = 0; k < 3; k++) py[c][k] = k < d ? A.Y[jj * d + k] : 0.f;
             }
         }
     };
     auto commit = [&](int buf) {
-        if (tid < MCH) {
-            const double ct = pvalid ? (sq ? pxg - ks * pyn : pxg - ks) - psh : -INFINITY;
-            if constexpr (BF) {
-                colt[buf * MCH + tid] = ct;
-            } else {
-                double *bt = yl64 + (size_t)buf * BU + (tid >> 4) * 64 + (tid & 15);
 #pragma unroll
-                for (int k = 0; k < 3; k++) bt[16 * k] = (double)py[k];
+        for (int c = 0; c < CPT; c++) {
+            const int col = tid + c * TT;
+            if (col >= MCH) continue;
+            const double ct = pvalid[c] ? (sq ? pxg[c] - ks * pyn[c] : pxg[c] - ks) - psh[c] : -INFINITY;
+            if constexpr (BF) {
+                colt[buf * MCH + col] = ct;
+            } else {
+                double *bt = yl64 + (size_t)buf * BU + (col >> 4) * 64 + (col & 15);
+#pragma unroll
+                for (int k = 0; k < 3; k++) bt[16 * k] = (double)py[c][k];
                 bt[48] = ct;
             }
         }
@@ -739,20 +749,28 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
                 for (int r = 0; r < RT; r++) cc[r] = cn[r];
             }
         } else {
-            const f64x4 cin = {rt_[0][0], rt_[0][1], rt_[0][2], rt_[0][3]};
+            f64x4 cin[RT];
+#pragma unroll
+            for (int r = 0; r < RT; r++) cin[r] = f64x4{rt_[r][0], rt_[r][1], rt_[r][2], rt_[r][3]};
             const double *b0 = yl64 + (size_t)buf * BU + lane;
-            constexpr int G4 = 4;  // independent products in flight
+            constexpr int G4 = 4;  // column tiles per group: RT x G4 independent products in flight
 #pragma unroll
             for (int t0 = 0; t0 < NTC; t0 += G4) {
-                f64x4 dv[G4];
+                f64x4 dv[G4][RT];
 #pragma unroll
-                for (int g = 0; g < G4; g++)
-                    dv[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[0].a64, b0[(t0 + g) * 64], cin, 0, 0, 0);
+                for (int g = 0; g < G4; g++) {
+                    const double bv = b0[(t0 + g) * 64];
+#pragma unroll
+                    for (int r = 0; r < RT; r++)
+                        dv[g][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[r].a64, bv, cin[r], 0, 0, 0);
+                }
 #pragma unroll
                 for (int g = 0; g < G4; g++) {
                     double arg[RT][4];
 #pragma unroll
-                    for (int q = 0; q < 4; q++) arg[0][q] = dv[g][q];
+                    for (int r = 0; r < RT; r++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++) arg[r][q] = dv[g][r][q];
                     use(t0 + g, arg);
                 }
             }
@@ -921,8 +939,41 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
                         }
                     }
                     const bool wact = act[0];
+                    // a chunk's column values (mcp buffer pb) added over the waves in a fixed
+                    // order, into the block's partials
+                    auto combine = [&](long long ja, int pb) {
+                        const float *mc = mcp + pb * TW * MCH;
+                        for (int c = tid; c < MCH; c += TT) {
+                            const long long j = ja + c;
+                            if (j >= m) continue;
+                            double tv = mxs ? -INFINITY : 0.0;
+                            for (int w = 0; w < TW; w++) {
+                                const double x = mc[w * MCH + c];
+                                if (mxs) tv = (x > tv || x != x) ? x : tv;
+                                else tv += x;
+                            }
+                            const size_t o = (size_t)bid * m + j;
+                            if (mxs) {
+                                A.partmax[o] = round == 0 ? tv : fmax(A.partmax[o], tv);
+                            } else if (exact) {
+                                A.part[o] = round == 0 ? tv : A.part[o] + tv;
+                            } else if (nround == 1) {
+                                xstore(&A.partf[o], (float)tv);
+                            } else {
+                                const double s2 = round == 0 ? tv : A.part[o] + tv;
+                                A.part[o] = s2;
+                                if (round == nround - 1) xstore(&A.partf[o], (float)s2);
+                            }
+                        }
+                    };
                     with_split([&](auto S3) {
+                        long long jlast = 0;
+                        int blast = 0;
                         for_chunks(shift_src, [&](long long ja, int buf) {
+                            // every wave has passed this chunk's barrier, so the previous
+                            // chunk's values are complete
+                            if (ja > 0) combine(ja - MCH, buf ^ 1);
+                            float *mw = mcp + (buf * TW + wid) * MCH;
                             if (wact) {
                                 float p4[4];          // the current group of four tiles' partial sums
                                 float cs[NTC / 4];    // the chunk's column sums, stored after its last tile
@@ -938,7 +989,9 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
                                         v = (u > v || u != u) ? u : v;
                                         u = __shfl_xor(v, 32, 64);
                                         v = (u > v || u != u) ? u : v;
-                                        if (lane < 16) mcp[wid * MCH + t * 16 + lane] = v;
+                                        // a shift: any value near the maximum serves, as the same
+                                        // one is used for the sums and the combine
+                                        if (lane < 16) mw[t * 16 + lane] = (float)v;
                                     } else {
                                         float p = __builtin_amdgcn_exp2f((float)arg[0][0]);
 #pragma unroll
@@ -954,35 +1007,16 @@ void tiled_solve(const TiledArgs A, double *__restrict__ trace, long long trace_
                                 if constexpr (!mxs) {
 #pragma unroll
                                     for (int k = 0; k < NTC / 4; k++)
-                                        mcp[wid * MCH + (4 * k + col_sums4_tile(lane)) * 16 + (lane & 15)] = (double)cs[k];
+                                        mw[(4 * k + col_sums4_tile(lane)) * 16 + (lane & 15)] = cs[k];
                                 }
                             } else {
-                                for (int c = lane; c < MCH; c += 64) mcp[wid * MCH + c] = mxs ? -INFINITY : 0.0;
+                                for (int c = lane; c < MCH; c += 64) mw[c] = mxs ? -INFINITY : 0.f;
                             }
-                            __syncthreads();
-                            for (int c = tid; c < MCH; c += TT) {
-                                const long long j = ja + c;
-                                if (j >= m) continue;
-                                double tv = mxs ? -INFINITY : 0.0;
-                                for (int w = 0; w < TW; w++) {
-                                    const double x = mcp[w * MCH + c];
-                                    if (mxs) tv = (x > tv || x != x) ? x : tv;
-                                    else tv += x;
-                                }
-                                const size_t o = (size_t)bid * m + j;
-                                if (mxs) {
-                                    A.partmax[o] = round == 0 ? tv : fmax(A.partmax[o], tv);
-                                } else if (exact) {
-                                    A.part[o] = round == 0 ? tv : A.part[o] + tv;
-                                } else if (nround == 1) {
-                                    xstore(&A.partf[o], (float)tv);
-                                } else {
-                                    const double s2 = round == 0 ? tv : A.part[o] + tv;
-                                    A.part[o] = s2;
-                                    if (round == nround - 1) xstore(&A.partf[o], (float)s2);
-                                }
-                            }
+                            jlast = ja;
+                            blast = buf;
                         });
+                        __syncthreads();
+                        combine(jlast, blast);
                     });
                 }
                 __syncthreads();
